@@ -1,0 +1,153 @@
+"""FP64 CPU oracle for the stochastic Barnes-Hut estimator.
+
+TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the benchmark's
+CPU-baseline leg.  The product path (the HIP library and its binding) never
+imports this package, and this package imports nothing from the product.
+
+Thin ctypes wrapper over sbh_oracle.c; see that file for the passages of the
+paper each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+POTENTIAL, WINDING, SMOOTHDIST, LINEAR = 0, 1, 2, 99
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.c_void_p
+        i64, i32, u32, u64, f64 = C.c_int64, C.c_int, C.c_uint32, C.c_uint64, C.c_double
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_brute.argtypes = [P, P, P, i64, P, i64, i32, f64, f64, P, i32]
+        L.orc_tree_build.argtypes = [P, P, P, i64, i32, i32, i32]
+        L.orc_tree_build.restype = P
+        L.orc_tree_free.argtypes = [P]
+        L.orc_tree_num_nodes.argtypes = [P]
+        L.orc_tree_num_nodes.restype = i64
+        L.orc_tree_meta.argtypes = [P, P]
+        L.orc_tree_export.argtypes = [P] + [P] * 10
+        L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
+        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, i32]
+        L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32]
+        L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: ctr 4 x uint32, key 2 x uint32 -> 4 x uint32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def brute(sources, weights, normals, queries, kernel, eps=1e-3, alpha=100.0, threads=0):
+    """Eq. (1) in FP64 with compensated summation. Returns the raw sum F."""
+    s = _f32(sources, (-1, 3)); w = _f32(weights).ravel(); q = _f32(queries, (-1, 3))
+    nrm = None if normals is None else _f32(normals, (-1, 3))
+    out = np.zeros(q.shape[0], dtype=np.float64)
+    lib().orc_brute(_p(s), _p(w), _p(nrm), s.shape[0], _p(q), q.shape[0], kernel, eps, alpha, _p(out), threads)
+    return out
+
+
+def smooth_distance(F, alpha=100.0):
+    """Smooth-distance post-transform -log(F)/alpha (results section)."""
+    F = np.asarray(F, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return -np.log(F) / alpha
+
+
+class Tree:
+    """Oracle tree: d in {2,4,8}, leaf_size, max_level (0 = deepest allowed)."""
+
+    def __init__(self, sources, weights, normals=None, d=2, leaf_size=8, max_level=0):
+        self._s = _f32(sources, (-1, 3)); self._w = _f32(weights).ravel()
+        self._n = None if normals is None else _f32(normals, (-1, 3))
+        h = lib().orc_tree_build(_p(self._s), _p(self._w), _p(self._n), self._s.shape[0], d, leaf_size, max_level)
+        if not h:
+            raise ValueError("oracle tree build rejected its arguments")
+        self._h = C.c_void_p(h)
+        meta = np.zeros(10)
+        lib().orc_tree_meta(self._h, _p(meta))
+        self.lo = meta[0:3].astype(np.float32)
+        self.side = np.float32(meta[3]); self.inv_side = np.float32(meta[4])
+        self.d = int(meta[5]); self.leaf_size = int(meta[6]); self.max_level = int(meta[7])
+        self.depth = int(meta[8]); self.m = int(meta[9])
+        self.n_nodes = int(lib().orc_tree_num_nodes(self._h))
+        n = self.n_nodes
+        self.begin = np.zeros(n, np.int64); self.count = np.zeros(n, np.int64)
+        self.level = np.zeros(n, np.int32); self.first_child = np.zeros(n, np.int64)
+        self.nchild = np.zeros(n, np.int32); self.digit = np.zeros(n, np.int32)
+        self.parent = np.zeros(n, np.int64); self.agg = np.zeros((n, 8))
+        self.perm = np.zeros(self.m, np.int64); self.codes = np.zeros(self.m, np.uint64)
+        lib().orc_tree_export(self._h, _p(self.begin), _p(self.count), _p(self.level), _p(self.first_child),
+                              _p(self.nchild), _p(self.digit), _p(self.parent), _p(self.agg), _p(self.perm),
+                              _p(self.codes))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_tree_free(h)
+            self._h = None
+
+    @property
+    def internal(self):
+        return (self.count > self.leaf_size) & (self.level < self.max_level)
+
+    def bh(self, queries, kernel, beta, group=1, eps=1e-3, alpha=100.0, threads=0):
+        """Algorithm 1; returns (F, min relative margin |b-beta|/beta, nodes visited per group)."""
+        q = _f32(queries, (-1, 3)); n = q.shape[0]
+        out = np.zeros(n); mg = np.zeros(n); vis = np.zeros(n, np.int64)
+        lib().orc_bh(self._h, _p(q), n, kernel, eps, alpha, float(beta), group, _p(out), _p(mg), _p(vis), threads)
+        return out, mg, vis
+
+    def sbh(self, queries, kernel, samples=1, seed=0, group=1, batch=0, rr_mode=0, eps=1e-3, alpha=100.0,
+            paths=False, threads=0):
+        """Algorithm 2 driven by Philox; returns dict(F, margin, absum[, paths])."""
+        q = _f32(queries, (-1, 3)); n = q.shape[0]
+        out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n)
+        d3 = self.d ** 3
+        pth = np.zeros((n, d3, samples, 4), np.int32) if paths else None
+        lib().orc_sbh(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, rr_mode,
+                      _p(out), _p(mg), _p(ab), _p(pth), threads)
+        r = dict(F=out, margin=mg, absum=ab)
+        if paths:
+            r["paths"] = pth
+        return r
+
+    def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, threads=0):
+        """Exact expectation of the one-sample estimator (Theorem 1)."""
+        q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
+        lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(out), threads)
+        return out
+
+    def refine_all(self, queries, kernel, eps=1e-3, alpha=100.0):
+        """Telescoping sum with every node refined (Eqs. (3)-(4))."""
+        q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
+        lib().orc_refine_all(self._h, _p(q), q.shape[0], kernel, eps, alpha, _p(out))
+        return out

@@ -1,0 +1,722 @@
+/*
+ * FP64 CPU oracle for the stochastic Barnes-Hut estimator
+ * (Madan, Sharp, Williams, Museth, Levin: "Stochastic Barnes-Hut
+ * Approximation for Fast Summation on the GPU", SIGGRAPH 2025).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * HIP path is checked against.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load it; the product path never does.  It
+ * shares no code, header, table or helper with the HIP library.
+ *
+ * What each part follows:
+ *   kernel sum ............ Section 3, Eq. (1)   (the index under the sum is i)
+ *   tree and aggregates ... Section 3.1 (octree-like tree, per-node box,
+ *                           aggregate mass, centre of mass)
+ *   Barnes-Hut ............ Section 3.1, Eq. (2), Algorithm 1
+ *   path estimator ........ Section 3.3, Eqs. (5)-(7), Section 3.3.1
+ *                           (domain stratification), Algorithm 2
+ *   unbiasedness .......... Theorem 1 and its proof (Appendix A), via the
+ *                           exact-expectation enumerator below
+ *   Philox4x32-10 ......... Salmon, Moraes, Dror, Shaw, "Parallel random
+ *                           numbers: as easy as 1, 2, 3", SC'11
+ *
+ * Readings where the paper is silent (kept identical on the HIP side):
+ *   - |B| is the octree CELL diagonal sqrt(3)*side/d^level, so a child's box
+ *     is exactly 1/d of its parent's (Section 3.3, far-field ratio argument).
+ *   - The tree is built from a 60-bit Morton code of fp32-quantised
+ *     coordinates; a node is split iff count > leaf_size and level < max.
+ *   - A leaf holding several points treats them as virtual children with box
+ *     diameter |B_leaf|/d (the paper assumes one point per leaf).
+ *   - The path index is drawn one level at a time: child c of T with
+ *     probability n_c/n_T, which composes to the uniform path index.
+ *   - Random numbers: Philox4x32-10, key = seed, counter = (stream, a*S+s,
+ *     step/2, batch); words (0,1) drive step 2k, words (2,3) step 2k+1; the
+ *     first word of a pair selects, the second (top 24 bits) drives the
+ *     Russian roulette test "stop iff u >= p".
+ *   - Barnes-Hut opens a leaf that is not far by summing its points exactly.
+ *
+ * Build: gcc -O2 -std=c99 -fopenmp -ffp-contract=off -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_POTENTIAL 0
+#define ORC_WINDING 1
+#define ORC_SMOOTHDIST 2
+#define ORC_LINEAR 99 /* test kernel: first-order LOD is exact for it */
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box with    */
+/* multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments               */
+/* 0x9E3779B9 / 0xBB67AE85.                                                   */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t n0 = hi_b ^ c1 ^ k0;
+        uint32_t n1 = lo_b;
+        uint32_t n2 = hi_a ^ c3 ^ k1;
+        uint32_t n3 = lo_a;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernels f: the term of one source (or one node aggregate) at query q.     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kernel;
+    double eps;   /* potential softening */
+    double alpha; /* smooth-distance sharpness */
+} kparams;
+
+/* m: mass (weight) of the source/aggregate, p: position (or centre of mass),
+ * dip: summed w*n (winding only). */
+static double term(const kparams* kp, const double p[3], double m, const double dip[3], const double q[3])
+{
+    double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    switch (kp->kernel) {
+    case ORC_POTENTIAL:
+        return m / sqrt(r2 + kp->eps * kp->eps);
+    case ORC_WINDING: {
+        if (r2 == 0.0) return 0.0;
+        double r = sqrt(r2);
+        return (dip[0] * dx + dip[1] * dy + dip[2] * dz) / (4.0 * ORC_PI * r2 * r);
+    }
+    case ORC_SMOOTHDIST:
+        return m * exp(-kp->alpha * sqrt(r2));
+    case ORC_LINEAR:
+        /* m * (1 + g.(p - q)) with g = (0.3, -0.2, 0.1) */
+        return m * (1.0 + 0.3 * dx - 0.2 * dy + 0.1 * dz);
+    default:
+        return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brute force, Eq. (1): F(q) = sum_i m_i f(p_i, q), index order, Neumaier   */
+/* compensated summation.                                                     */
+/* ------------------------------------------------------------------------ */
+void orc_brute(const float* src, const float* w, const float* nrm, int64_t m,
+               const float* qry, int64_t n, int kernel, double eps, double alpha,
+               double* out, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t j = 0; j < n; ++j) {
+        double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
+        double s = 0.0, c = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double p[3] = {src[3 * i], src[3 * i + 1], src[3 * i + 2]};
+            double wi = w[i];
+            double d[3] = {0, 0, 0};
+            if (nrm) {
+                d[0] = wi * (double)nrm[3 * i];
+                d[1] = wi * (double)nrm[3 * i + 1];
+                d[2] = wi * (double)nrm[3 * i + 2];
+            }
+            double t = term(&kp, p, wi, d, q);
+            double y = s + t;
+            if (fabs(s) >= fabs(t)) c += (s - y) + t;
+            else c += (t - y) + s;
+            s = y;
+        }
+        out[j] = s + c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree (Section 3.1): octree-like, per-dimension branching d, built from    */
+/* Morton codes of fp32-quantised coordinates.                                */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_tree {
+    int64_t m;
+    int d, bits, leaf_size, max_level, depth;
+    float lo[3], side, inv_side;
+    /* points in sorted (Morton) order, in double */
+    double* pxyz;  /* [m][3] */
+    double* pw;    /* [m] */
+    double* pdip;  /* [m][3]  w*n, zeros without normals */
+    int has_normals;
+    int64_t* perm;   /* sorted position -> input index */
+    uint64_t* codes; /* sorted codes */
+    /* nodes in BFS order; within a level, Morton order */
+    int64_t n_nodes, cap;
+    int64_t *begin, *count, *first_child, *parent;
+    int32_t *level, *nchild, *digit;
+    double *mass, *com, *dip; /* com, dip: [n][3] */
+    double diam[64];          /* |B| per level */
+} orc_tree;
+
+static uint64_t spread3(uint32_t v)
+{
+    /* bit k of v -> bit 3k of the result (k < 20) */
+    uint64_t r = 0;
+    for (int k = 0; k < 20; ++k)
+        if (v & (1u << k)) r |= (uint64_t)1 << (3 * k);
+    return r;
+}
+
+static const uint64_t* g_sort_codes;
+static int cmp_code_index(const void* a, const void* b)
+{
+    int64_t ia = *(const int64_t*)a, ib = *(const int64_t*)b;
+    uint64_t ca = g_sort_codes[ia], cb = g_sort_codes[ib];
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    return (ia < ib) ? -1 : (ia > ib);
+}
+
+static void push_node(orc_tree* t, int64_t b, int64_t c, int32_t lev, int64_t par, int32_t dig)
+{
+    if (t->n_nodes == t->cap) {
+        t->cap = t->cap ? 2 * t->cap : 1024;
+        t->begin = realloc(t->begin, t->cap * sizeof(int64_t));
+        t->count = realloc(t->count, t->cap * sizeof(int64_t));
+        t->first_child = realloc(t->first_child, t->cap * sizeof(int64_t));
+        t->parent = realloc(t->parent, t->cap * sizeof(int64_t));
+        t->level = realloc(t->level, t->cap * sizeof(int32_t));
+        t->nchild = realloc(t->nchild, t->cap * sizeof(int32_t));
+        t->digit = realloc(t->digit, t->cap * sizeof(int32_t));
+    }
+    int64_t i = t->n_nodes++;
+    t->begin[i] = b;
+    t->count[i] = c;
+    t->first_child[i] = -1;
+    t->parent[i] = par;
+    t->level[i] = lev;
+    t->nchild[i] = 0;
+    t->digit[i] = dig;
+}
+
+static int is_internal(const orc_tree* t, int64_t i)
+{
+    return t->count[i] > t->leaf_size && t->level[i] < t->max_level;
+}
+
+void orc_tree_free(orc_tree* t)
+{
+    if (!t) return;
+    free(t->pxyz); free(t->pw); free(t->pdip); free(t->perm); free(t->codes);
+    free(t->begin); free(t->count); free(t->first_child); free(t->parent);
+    free(t->level); free(t->nchild); free(t->digit);
+    free(t->mass); free(t->com); free(t->dip);
+    free(t);
+}
+
+/* d in {2,4,8}; max_level <= 60 / (3 log2 d); leaf_size >= 1. */
+orc_tree* orc_tree_build(const float* src, const float* w, const float* nrm, int64_t m,
+                         int d, int leaf_size, int max_level)
+{
+    if (m <= 0 || leaf_size < 1) return NULL;
+    int lg = (d == 2) ? 1 : (d == 4) ? 2 : (d == 8) ? 3 : 0;
+    if (!lg) return NULL;
+    int bits = 3 * lg;
+    if (max_level <= 0 || max_level > 60 / bits) max_level = 60 / bits;
+    orc_tree* t = calloc(1, sizeof(orc_tree));
+    t->m = m; t->d = d; t->bits = bits; t->leaf_size = leaf_size; t->max_level = max_level;
+
+    /* root cube, in fp32 exactly as specified */
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = src[a]; hi[a] = src[a]; }
+    for (int64_t i = 1; i < m; ++i)
+        for (int a = 0; a < 3; ++a) {
+            float x = src[3 * i + a];
+            if (x < lo[a]) lo[a] = x;
+            if (x > hi[a]) hi[a] = x;
+        }
+    float side = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        float e = hi[a] - lo[a];
+        if (e > side) side = e;
+    }
+    if (side == 0.0f) side = 1.0f;
+    float inv_side = 1.0f / side;
+    for (int a = 0; a < 3; ++a) t->lo[a] = lo[a];
+    t->side = side; t->inv_side = inv_side;
+
+    /* quantise (fp32, no contraction) and Morton-encode: bit 3k+a = bit k of axis a */
+    uint64_t* code = malloc(m * sizeof(uint64_t));
+    for (int64_t i = 0; i < m; ++i) {
+        uint32_t cell[3];
+        for (int a = 0; a < 3; ++a) {
+            float u = src[3 * i + a] - lo[a];
+            u = u * inv_side;
+            u = u * 1048576.0f;
+            uint32_t c = (uint32_t)u;
+            if (c > 1048575u) c = 1048575u;
+            cell[a] = c;
+        }
+        code[i] = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
+    }
+    /* stable sort by code (ties by input index) */
+    int64_t* perm = malloc(m * sizeof(int64_t));
+    for (int64_t i = 0; i < m; ++i) perm[i] = i;
+    g_sort_codes = code;
+    qsort(perm, (size_t)m, sizeof(int64_t), cmp_code_index);
+    t->perm = perm;
+    t->codes = malloc(m * sizeof(uint64_t));
+    t->pxyz = malloc(3 * m * sizeof(double));
+    t->pw = malloc(m * sizeof(double));
+    t->pdip = calloc(3 * m, sizeof(double));
+    t->has_normals = nrm != NULL;
+    for (int64_t s = 0; s < m; ++s) {
+        int64_t i = perm[s];
+        t->codes[s] = code[i];
+        for (int a = 0; a < 3; ++a) t->pxyz[3 * s + a] = src[3 * i + a];
+        t->pw[s] = w[i];
+        if (nrm)
+            for (int a = 0; a < 3; ++a) t->pdip[3 * s + a] = (double)w[i] * (double)nrm[3 * i + a];
+    }
+    free(code);
+
+    /* breadth-first construction: a node is its maximal run of equal prefix;
+     * its children are the non-empty runs of the next digit, in digit order */
+    push_node(t, 0, m, 0, -1, 0);
+    uint64_t dmask = ((uint64_t)1 << bits) - 1;
+    for (int64_t i = 0; i < t->n_nodes; ++i) {
+        if (!is_internal(t, i)) continue;
+        int shift = 60 - bits * (t->level[i] + 1);
+        int64_t b = t->begin[i], e = t->begin[i] + t->count[i];
+        t->first_child[i] = t->n_nodes;
+        int64_t j = b;
+        while (j < e) {
+            uint64_t dig = (t->codes[j] >> shift) & dmask;
+            int64_t k = j;
+            while (k < e && ((t->codes[k] >> shift) & dmask) == dig) ++k;
+            push_node(t, j, k - j, t->level[i] + 1, i, (int32_t)dig);
+            t->nchild[i] += 1;
+            j = k;
+        }
+    }
+    int depth = 0;
+    for (int64_t i = 0; i < t->n_nodes; ++i)
+        if (t->level[i] > depth) depth = t->level[i];
+    t->depth = depth;
+
+    /* aggregates straight from their definition: mass = sum w, centre of
+     * mass = sum w p / mass, dipole = sum w n */
+    int64_t nn = t->n_nodes;
+    t->mass = malloc(nn * sizeof(double));
+    t->com = malloc(3 * nn * sizeof(double));
+    t->dip = malloc(3 * nn * sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < nn; ++i) {
+        double ms = 0, cx = 0, cy = 0, cz = 0, dx = 0, dy = 0, dz = 0;
+        for (int64_t s = t->begin[i]; s < t->begin[i] + t->count[i]; ++s) {
+            double wi = t->pw[s];
+            ms += wi;
+            cx += wi * t->pxyz[3 * s];
+            cy += wi * t->pxyz[3 * s + 1];
+            cz += wi * t->pxyz[3 * s + 2];
+            dx += t->pdip[3 * s];
+            dy += t->pdip[3 * s + 1];
+            dz += t->pdip[3 * s + 2];
+        }
+        t->mass[i] = ms;
+        t->com[3 * i] = cx / ms;
+        t->com[3 * i + 1] = cy / ms;
+        t->com[3 * i + 2] = cz / ms;
+        t->dip[3 * i] = dx;
+        t->dip[3 * i + 1] = dy;
+        t->dip[3 * i + 2] = dz;
+    }
+    /* cell diagonal per level */
+    double dl = 1.0;
+    for (int l = 0; l < 64; ++l) {
+        t->diam[l] = sqrt(3.0) * (double)side / dl;
+        dl *= (double)d;
+    }
+    return t;
+}
+
+int64_t orc_tree_num_nodes(const orc_tree* t) { return t->n_nodes; }
+
+/* meta: lo[3], side, inv_side, d, leaf_size, max_level, depth, m */
+void orc_tree_meta(const orc_tree* t, double* meta)
+{
+    meta[0] = t->lo[0]; meta[1] = t->lo[1]; meta[2] = t->lo[2];
+    meta[3] = t->side; meta[4] = t->inv_side;
+    meta[5] = t->d; meta[6] = t->leaf_size; meta[7] = t->max_level; meta[8] = t->depth;
+    meta[9] = (double)t->m;
+}
+
+/* agg: [n][8] = com xyz, mass, dip xyz, |B| */
+void orc_tree_export(const orc_tree* t, int64_t* begin, int64_t* count, int32_t* level,
+                     int64_t* first_child, int32_t* nchild, int32_t* digit, int64_t* parent,
+                     double* agg, int64_t* perm, uint64_t* codes)
+{
+    for (int64_t i = 0; i < t->n_nodes; ++i) {
+        if (begin) begin[i] = t->begin[i];
+        if (count) count[i] = t->count[i];
+        if (level) level[i] = t->level[i];
+        if (first_child) first_child[i] = t->first_child[i];
+        if (nchild) nchild[i] = t->nchild[i];
+        if (digit) digit[i] = t->digit[i];
+        if (parent) parent[i] = t->parent[i];
+        if (agg) {
+            agg[8 * i + 0] = t->com[3 * i];
+            agg[8 * i + 1] = t->com[3 * i + 1];
+            agg[8 * i + 2] = t->com[3 * i + 2];
+            agg[8 * i + 3] = t->mass[i];
+            agg[8 * i + 4] = t->dip[3 * i];
+            agg[8 * i + 5] = t->dip[3 * i + 1];
+            agg[8 * i + 6] = t->dip[3 * i + 2];
+            agg[8 * i + 7] = t->diam[t->level[i]];
+        }
+    }
+    for (int64_t s = 0; s < t->m; ++s) {
+        if (perm) perm[s] = t->perm[s];
+        if (codes) codes[s] = t->codes[s];
+    }
+}
+
+static double node_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+{
+    return term(kp, &t->com[3 * i], t->mass[i], &t->dip[3 * i], q);
+}
+
+static double point_term(const orc_tree* t, const kparams* kp, int64_t s, const double q[3])
+{
+    return term(kp, &t->pxyz[3 * s], t->pw[s], &t->pdip[3 * s], q);
+}
+
+static double dist3(const double a[3], const double q[3])
+{
+    double dx = a[0] - q[0], dy = a[1] - q[1], dz = a[2] - q[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+static double leaf_exact(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+{
+    double s = 0.0;
+    for (int64_t k = t->begin[i]; k < t->begin[i] + t->count[i]; ++k) s += point_term(t, kp, k, q);
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Barnes-Hut, Algorithm 1 / Eq. (2).  The far-field test is                  */
+/* ||q - com|| / |B| >= beta.  A leaf that is not far is summed exactly.      */
+/* Vote mode (group > 1): for each group of `group` consecutive queries a     */
+/* node is opened iff some query of the group fails the far-field test; all   */
+/* queries of the group then share the same cut.  group = 1 is per query.    */
+/* ------------------------------------------------------------------------ */
+static void bh_group(const orc_tree* t, const kparams* kp, int64_t node, const double* qs, int gn,
+                     double beta, double* acc, double* margin, int64_t* visited)
+{
+    int open = 0;
+    *visited += 1;
+    for (int g = 0; g < gn; ++g) {
+        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / t->diam[t->level[node]];
+        double mg = fabs(bt - beta) / beta;
+        if (mg < margin[g]) margin[g] = mg;
+        if (!(bt >= beta)) open = 1;
+    }
+    if (!open) {
+        for (int g = 0; g < gn; ++g) acc[g] += node_term(t, kp, node, &qs[3 * g]);
+        return;
+    }
+    if (!is_internal(t, node)) {
+        for (int g = 0; g < gn; ++g) acc[g] += leaf_exact(t, kp, node, &qs[3 * g]);
+        return;
+    }
+    for (int c = 0; c < t->nchild[node]; ++c)
+        bh_group(t, kp, t->first_child[node] + c, qs, gn, beta, acc, margin, visited);
+}
+
+void orc_bh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
+            double beta, int group, double* out, double* min_margin, int64_t* visited, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+    if (group < 1) group = 1;
+    int64_t ng = (n + group - 1) / group;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t gi = 0; gi < ng; ++gi) {
+        int64_t j0 = gi * group;
+        int gn = (int)((n - j0 < group) ? (n - j0) : group);
+        double* qs = malloc(3 * gn * sizeof(double));
+        double* acc = calloc(gn, sizeof(double));
+        double* mg = malloc(gn * sizeof(double));
+        for (int g = 0; g < gn; ++g) {
+            for (int a = 0; a < 3; ++a) qs[3 * g + a] = qry[3 * (j0 + g) + a];
+            mg[g] = INFINITY;
+        }
+        int64_t vis = 0;
+        bh_group(t, &kp, 0, qs, gn, beta, acc, mg, &vis);
+        for (int g = 0; g < gn; ++g) {
+            out[j0 + g] = acc[g];
+            if (min_margin) min_margin[j0 + g] = mg[g];
+            if (visited) visited[j0 + g] = vis;
+        }
+        free(qs); free(acc); free(mg);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stochastic path estimator: Eqs. (5)-(7), Section 3.3.1, Algorithm 2.       */
+/* ------------------------------------------------------------------------ */
+
+/* Russian-roulette probability of moving from a node (far-field ratio bT) to
+ * its chosen child (far-field ratio bc): Eq. (5), or the ablations
+ * rr_mode 1 (p = 1, no roulette) and 2 (p = 1/2). */
+static double rr_prob(int rr_mode, double bT, double bc)
+{
+    if (rr_mode == 1) return 1.0;
+    if (rr_mode == 2) return 0.5;
+    if (bc == 0.0) return 1.0;
+    double r = (bT > 1.0 ? bT : 1.0) / bc;
+    return r < 1.0 ? r : 1.0;
+}
+
+typedef struct {
+    double value;    /* estimate of this path's residual sum */
+    double absum;    /* sum of |terms| that entered it, weighted like the value */
+    double margin;   /* min |u - p| over its roulette decisions */
+    int32_t end_begin, end_level, steps, flags;
+} path_out;
+
+/* One path sample rooted at subdomain node `a` (Algorithm 2, inner loop).
+ * counter = (sigma, a_slot*S + s, step/2, batch), key = (seed lo, seed hi). */
+static path_out sample_path(const orc_tree* t, const kparams* kp, const double q[3], int64_t a,
+                            uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode)
+{
+    path_out po = {0.0, 0.0, INFINITY, 0, 0, 0, 0};
+    int64_t T = a;                  /* current node (a real node) */
+    double tT = node_term(t, kp, a, q);
+    double n_a = (double)t->count[a];
+    double p_sel = 1.0;             /* probability that the path index lies in T */
+    double p_rr = 1.0;              /* running product of roulette probabilities */
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int k = 0;; ++k) {
+        int64_t nT = t->count[T];
+        po.end_begin = (int32_t)t->begin[T];
+        po.end_level = t->level[T];
+        if (nT == 1) { po.flags = 1; break; }   /* a one-point leaf: nothing left to refine */
+        uint32_t ctr[4] = {sigma, stream2, (uint32_t)(k >> 1), batch}, rnd[4];
+        orc_philox4x32_10(ctr, key, rnd);
+        uint32_t x_sel = rnd[2 * (k & 1)], x_rr = rnd[2 * (k & 1) + 1];
+        double u_rr = (double)(x_rr >> 8) * (1.0 / 16777216.0);
+        /* uniform path index inside T: offset r in [0, nT) */
+        int64_t r = (int64_t)(((uint64_t)x_sel * (uint64_t)nT) >> 32);
+        int64_t target = t->begin[T] + r;
+        double diam_c = t->diam[t->level[T] + 1];
+        double bT = dist3(&t->com[3 * T], q) / t->diam[t->level[T]];
+        double sum_children = 0.0, abs_children = 0.0;
+        double bc, tc, q_c;
+        int64_t c_node = -1;
+        if (is_internal(t, T)) {
+            int64_t c = -1;
+            for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+                double v = node_term(t, kp, ch, q);
+                sum_children += v;
+                abs_children += fabs(v);
+                if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
+            }
+            c_node = c;
+            bc = dist3(&t->com[3 * c], q) / diam_c;
+            tc = node_term(t, kp, c, q);
+            q_c = (double)t->count[c] / (double)nT;
+        } else {
+            /* leaf with several points: the points are virtual children */
+            for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) {
+                double v = point_term(t, kp, s, q);
+                sum_children += v;
+                abs_children += fabs(v);
+            }
+            bc = dist3(&t->pxyz[3 * target], q) / diam_c;
+            tc = point_term(t, kp, target, q);
+            q_c = 1.0 / (double)nT;
+        }
+        double p = rr_prob(rr_mode, bT, bc);
+        double mg = fabs(u_rr - p);
+        if (rr_mode == 0 && mg < po.margin) po.margin = mg;
+        if (u_rr >= p) { po.flags = 0; break; }
+        p_rr *= p;
+        double delta = sum_children - tT;          /* contribution swap, Eq. (6) */
+        double wgt = 1.0 / (p_sel * p_rr);          /* 1 / (p(I in T) p(K >= k+1)), Eq. (7) */
+        po.value += delta * wgt;
+        po.absum += (abs_children + fabs(tT)) * wgt;
+        po.steps += 1;
+        p_sel *= q_c;
+        (void)n_a;
+        if (c_node < 0) {                           /* moved onto a virtual point */
+            po.end_begin = (int32_t)target;
+            po.end_level = t->level[T] + 1;
+            po.flags = 2;
+            break;
+        }
+        T = c_node;
+        tT = tc;
+    }
+    return po;
+}
+
+/* Subdomains are the root's children (slot = digit); a root that is a leaf
+ * is summed exactly.  Output per query: F estimate; optional: minimal
+ * roulette margin, conditioning sum, and per-path records laid out
+ * [n][d^3][S] x int32{begin, level, steps, flags} (absent slots: begin -1). */
+void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
+             int S, uint64_t seed, int G, uint32_t batch, int rr_mode,
+             double* out, double* min_margin, double* absum, int32_t* paths, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+    int d3 = t->d * t->d * t->d;
+    if (G < 1) G = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t j = 0; j < n; ++j) {
+        double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
+        uint32_t sigma = (uint32_t)(G == 1 ? j : j / G);
+        double F = 0.0, A = 0.0, mg = INFINITY;
+        if (paths)
+            for (int k = 0; k < d3 * S; ++k) {
+                int32_t* rec = &paths[((int64_t)j * d3 * S + k) * 4];
+                rec[0] = -1; rec[1] = 0; rec[2] = 0; rec[3] = 0;
+            }
+        if (!is_internal(t, 0)) {
+            F = leaf_exact(t, &kp, 0, q);
+            A = fabs(F);
+        } else {
+            for (int ci = 0; ci < t->nchild[0]; ++ci) {
+                int64_t a = t->first_child[0] + ci;
+                int slot = t->digit[a];
+                double cv = node_term(t, &kp, a, q);     /* control variate CV_a */
+                double Fa = 0.0, Aa = 0.0;
+                for (int s = 0; s < S; ++s) {
+                    path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode);
+                    Fa += po.value;
+                    Aa += po.absum;
+                    if (po.margin < mg) mg = po.margin;
+                    if (paths) {
+                        int32_t* rec = &paths[((int64_t)j * d3 * S + (int64_t)slot * S + s) * 4];
+                        rec[0] = po.end_begin; rec[1] = po.end_level; rec[2] = po.steps; rec[3] = po.flags;
+                    }
+                }
+                F += cv + Fa / S;
+                A += fabs(cv) + Aa / S;
+            }
+        }
+        out[j] = F;
+        if (min_margin) min_margin[j] = mg;
+        if (absum) absum[j] = A;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact expectation of the estimator (Theorem 1, Appendix A).  For a path   */
+/* at node T, reached with selection probability ps and roulette product pr, */
+/* the expected remaining contribution is                                    */
+/*   V(T) = sum_c q_c p_c [ Delta_T / (ps pr p_c) + V(c) ],                  */
+/* with V = 0 at one-point leaves and virtual points; E[F_1] = sum_a CV_a +  */
+/* V(a).  Exponential in nothing: one visit per node per query.             */
+/* ------------------------------------------------------------------------ */
+static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3], int64_t T, double tT,
+                         double ps, double pr, int rr_mode)
+{
+    int64_t nT = t->count[T];
+    if (nT == 1) return 0.0;
+    double bT = dist3(&t->com[3 * T], q) / t->diam[t->level[T]];
+    double diam_c = t->diam[t->level[T] + 1];
+    double total = 0.0;
+    if (is_internal(t, T)) {
+        double sum = 0.0;
+        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
+            sum += node_term(t, kp, ch, q);
+        double delta = sum - tT;
+        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+            double qc = (double)t->count[ch] / (double)nT;
+            double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / diam_c);
+            double tc = node_term(t, kp, ch, q);
+            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode));
+        }
+    } else {
+        double sum = 0.0;
+        for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) sum += point_term(t, kp, s, q);
+        double delta = sum - tT;
+        for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) {
+            double qc = 1.0 / (double)nT;
+            double pc = rr_prob(rr_mode, bT, dist3(&t->pxyz[3 * s], q) / diam_c);
+            total += qc * pc * (delta / (ps * pr * pc));
+        }
+    }
+    return total;
+}
+
+void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
+                    int rr_mode, double* out, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t j = 0; j < n; ++j) {
+        double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
+        if (!is_internal(t, 0)) { out[j] = leaf_exact(t, &kp, 0, q); continue; }
+        double F = 0.0;
+        for (int ci = 0; ci < t->nchild[0]; ++ci) {
+            int64_t a = t->first_child[0] + ci;
+            double cv = node_term(t, &kp, a, q);
+            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode);
+        }
+        out[j] = F;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Refine-every-node telescoping sum (Section 3.2, Eqs. (3)-(4)):            */
+/*   sum_a CV_a + sum over every node T below the subdomains of Delta_T,     */
+/* with leaves refined into their points.  Equals Eq. (1).                   */
+/* ------------------------------------------------------------------------ */
+void orc_refine_all(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
+                    double* out)
+{
+    kparams kp = {kernel, eps, alpha};
+    for (int64_t j = 0; j < n; ++j) {
+        double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
+        if (!is_internal(t, 0)) { out[j] = leaf_exact(t, &kp, 0, q); continue; }
+        double F = 0.0;
+        for (int ci = 0; ci < t->nchild[0]; ++ci) F += node_term(t, &kp, t->first_child[0] + ci, q);
+        for (int64_t T = 1; T < t->n_nodes; ++T) {
+            if (t->count[T] == 1) continue;
+            double sum = 0.0;
+            if (is_internal(t, T)) {
+                for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
+                    sum += node_term(t, &kp, ch, q);
+            } else {
+                sum = leaf_exact(t, &kp, T, q);
+            }
+            F += sum - node_term(t, &kp, T, q);
+        }
+        out[j] = F;
+    }
+}
