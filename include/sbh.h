@@ -1,0 +1,178 @@
+/*
+ * sbh.h - C ABI of the stochastic Barnes-Hut library for AMD Instinct MI355X
+ * (gfx950).  Madan, Sharp, Williams, Museth, Levin, "Stochastic Barnes-Hut
+ * Approximation for Fast Summation on the GPU" (SIGGRAPH 2025).
+ *
+ * Problem (Section 3, Eq. (1)): given sources p_i with weights m_i and query
+ * points q_j, evaluate F(q_j) = sum_i m_i f(p_i, q_j) for every query.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked (host).  Arrays are dense,
+ *     row-major, float32 unless stated: points are [n][3] (x, y, z).
+ *   - Every call enqueues its work on `stream` (0 = the null stream) and
+ *     returns without waiting for it, except where a call says it
+ *     synchronises.  Build and export synchronise `stream`.
+ *   - Arguments are checked on the host before anything is enqueued; on an
+ *     error nothing is written to any output and a negative status is
+ *     returned.  sbh_last_error() then holds a message for this thread.
+ *   - The library never frees memory it did not allocate.  Output buffers
+ *     are owned by the caller and overwritten.
+ *   - Results are a deterministic function of the inputs and the documented
+ *     arguments only (never of launch geometry).
+ */
+#ifndef SBH_H
+#define SBH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sbh_status {
+    SBH_OK = 0,
+    SBH_EINVAL = -1,        /* invalid argument (null pointer, bad size, NaN input, bad enum) */
+    SBH_ENOMEM = -2,        /* device allocation failed */
+    SBH_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    SBH_EUNSUPPORTED = -4,  /* valid request that this build does not implement */
+    SBH_ESTATE = -5         /* object in an unusable state */
+} sbh_status;
+
+/* Kernels f(p, q) (results section: potential, winding numbers, smooth
+ * distances).  For one source p with weight w (and unit normal n):
+ *   SBH_POTENTIAL   w / sqrt(|p-q|^2 + eps^2)                 (softened 1/r)
+ *   SBH_WINDING     w n.(p-q) / (4 pi |p-q|^3), 0 at p = q     (dipole)
+ *   SBH_SMOOTHDIST  w exp(-alpha |p-q|); the reported value is the smooth
+ *                   distance -log(F)/alpha of the (estimated) sum F.
+ * A tree node uses its aggregate in place of one source: total weight and
+ * weighted centre of mass; the winding kernel uses the summed w n. */
+typedef enum sbh_kernel {
+    SBH_POTENTIAL = 0,
+    SBH_WINDING = 1,
+    SBH_SMOOTHDIST = 2
+} sbh_kernel;
+
+typedef struct sbh_build_opts {
+    int32_t branching;   /* per-dimension branching d: 2 (octree) or 4 (64-way); default 2 */
+    int32_t leaf_size;   /* a node is split iff it holds more points than this; 1..64, default 8 */
+    int32_t max_level;   /* deepest level; 0 = 60/(3 log2 d), i.e. 20 for d=2, 10 for d=4 */
+} sbh_build_opts;
+
+typedef struct sbh_eval_opts {
+    float eps;           /* potential softening, >= 0; default 1e-3 */
+    float alpha;         /* smooth-distance sharpness, > 0; default 100 */
+    int32_t group;       /* G >= 1: queries j with equal floor(j/G) share one random
+                            stream (G = 1: every query has its own); default 1 */
+    int32_t rr_mode;     /* Russian roulette: 0 = Eq. (5) (default), 1 = p = 1 (none),
+                            2 = p = 1/2 (the two comparisons of the supplement) */
+    int32_t proposal;    /* child-selection distribution: 0 = uniform path index
+                            (the paper's); other values return SBH_EUNSUPPORTED */
+    uint32_t batch;      /* fourth Philox counter word, for independent batches; default 0 */
+    int32_t* paths;      /* optional DEVICE [nq][d^3][samples][4] int32 records of every
+                            sampled path: {end begin, end level, accepted steps, stop
+                            reason (0 roulette, 1 one-point node, 2 virtual point)};
+                            subdomain slots that are empty hold begin = -1.  NULL = off. */
+} sbh_eval_opts;
+
+typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */
+
+typedef struct sbh_tree_desc {      /* host copy of a tree's sizes */
+    int64_t n_points, n_nodes, n_blocks;
+    int32_t depth, branching, leaf_size, max_level, has_normals;
+    float lo[3], side, inv_side;    /* root cube [lo, lo + side]^3 and fl32(1/side) */
+} sbh_tree_desc;
+
+/* Fill option structs with the defaults documented above. */
+void sbh_build_opts_default(sbh_build_opts* opts /*host*/);
+void sbh_eval_opts_default(sbh_eval_opts* opts /*host*/);
+
+/*
+ * sbh_build - the spatial tree of Section 3.1 (octree-like, per-dimension
+ * branching d) with per-node aggregate weight, centre of mass and summed
+ * dipole, built on the GPU.
+ *   sources  [n][3]   source positions p_i (finite)
+ *   weights  [n]      source weights m_i (finite, > 0)
+ *   normals  [n][3]   unit normals (needed for SBH_WINDING) or NULL
+ *   n        1 <= n <= 2^30
+ *   opts     (host) or NULL for defaults
+ *   out_tree (host) receives the tree; the caller releases it with sbh_free.
+ * The tree copies what it needs; the inputs may be freed when the call
+ * returns.  Synchronises `stream`.  Errors: SBH_EINVAL (null pointer, n out
+ * of range, bad option, non-finite coordinate or normal, weight <= 0),
+ * SBH_ENOMEM, SBH_EHIP.
+ */
+sbh_status sbh_build(const float* sources, const float* weights, const float* normals, int64_t n,
+                     const sbh_build_opts* opts, hipStream_t stream, sbh_tree** out_tree);
+
+/*
+ * sbh_eval - evaluate every query on a tree.
+ *   samples >= 1: the stratified path-sample estimator (Section 3.3, Eqs.
+ *     (5)-(7), Algorithm 2) with S = samples paths per subdomain; the
+ *     subdomains are the root's children (Section 3.3.1).  Random numbers:
+ *     Philox4x32-10 with key = seed and counter = (stream id, slot*S + s,
+ *     step/2, opts->batch), stream id = j (G = 1) or floor(j/G).  beta is
+ *     ignored.  Unbiased for F (Theorem 1) for the potential and winding
+ *     kernels.
+ *   samples == 0: Barnes-Hut (Eq. (2), Algorithm 1) with opening parameter
+ *     beta > 0 (INFINITY = exact): a node is accepted iff |q - com| / |B| >=
+ *     beta, where |B| is the diagonal of the node's cell; a leaf that is not
+ *     accepted is summed exactly.  Queries are voted on in groups of 64
+ *     consecutive indices: a node is opened for the whole group if any of
+ *     its queries needs it.
+ *   queries [nq][3]; out [nq] float32 (smooth distance for SBH_SMOOTHDIST).
+ *   nq = 0 is a no-op.  Errors: SBH_EINVAL (null pointers, nq < 0, bad
+ *   kernel, samples < 0, beta <= 0 or NaN with samples == 0, group < 1,
+ *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals),
+ *   SBH_EUNSUPPORTED (proposal != 0), SBH_EHIP.
+ */
+sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel,
+                    float beta, int32_t samples, uint64_t seed, const sbh_eval_opts* opts,
+                    hipStream_t stream, float* out);
+
+/*
+ * sbh_brute - Eq. (1) evaluated exactly by tiling the sources through LDS.
+ *   fp64 = 0: float32 arithmetic, out is float[nq];
+ *   fp64 = 1: float64 arithmetic, out is double[nq] (the reference values).
+ * Kernels, eps and alpha as for sbh_eval (opts may be NULL).  Sources are in
+ * the caller's order; no tree is needed.  Errors: SBH_EINVAL, SBH_EHIP.
+ */
+sbh_status sbh_brute(const float* sources, const float* weights, const float* normals, int64_t n,
+                     const float* queries, int64_t nq, sbh_kernel kernel, const sbh_eval_opts* opts,
+                     int32_t fp64, hipStream_t stream, void* out);
+
+/* sbh_tree_info - sizes and root cube of a tree into *info (host). */
+sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info);
+
+/*
+ * sbh_tree_export - copy the tree to host arrays (for verification).  Every
+ * pointer is (host) and may be NULL to skip that array.  Node arrays have
+ * n_nodes entries in breadth-first order (Morton order within a level):
+ *   begin, count      range of the node in sorted point order
+ *   level, digit      depth (root 0) and child digit within the parent
+ *   parent            parent node id (-1 for the root)
+ *   first_child, nchild  children are ids first_child .. first_child+nchild-1
+ *                     (first_child = -1 for a leaf)
+ *   agg  [n_nodes][4] centre of mass (x, y, z) and total weight
+ *   dip  [n_nodes][4] summed w n (x, y, z), 0
+ * Point arrays have n_points entries: perm (sorted position -> input index)
+ * and codes (the 60-bit Morton codes, sorted).  Synchronises the null stream.
+ */
+sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count, int32_t* level,
+                           int32_t* digit, int32_t* parent, int32_t* first_child, int32_t* nchild,
+                           float* agg, float* dip, uint32_t* perm, uint64_t* codes);
+
+/* sbh_free - release a tree (waits for the device to finish using it). NULL is a no-op. */
+sbh_status sbh_free(sbh_tree* tree);
+
+/* Static text for a status code. */
+const char* sbh_status_string(sbh_status status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* sbh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBH_H */

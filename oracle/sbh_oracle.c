@@ -579,11 +579,13 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
 }
 
 /* Subdomains are the root's children (slot = digit); a root that is a leaf
- * is summed exactly.  Output per query: F estimate; optional: minimal
+ * is summed exactly.  The random stream of query j is its index (qindex[j]
+ * when given, so that a subset can be evaluated as part of a larger set).
+ * Output per query: F estimate; optional: minimal
  * roulette margin, conditioning sum, and per-path records laid out
  * [n][d^3][S] x int32{begin, level, steps, flags} (absent slots: begin -1). */
 void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
-             int S, uint64_t seed, int G, uint32_t batch, int rr_mode,
+             int S, uint64_t seed, int G, uint32_t batch, int rr_mode, const int64_t* qindex,
              double* out, double* min_margin, double* absum, int32_t* paths, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
@@ -595,7 +597,8 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
 #endif
     for (int64_t j = 0; j < n; ++j) {
         double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
-        uint32_t sigma = (uint32_t)(G == 1 ? j : j / G);
+        int64_t jj = qindex ? qindex[j] : j;   /* the query's index in the full query set */
+        uint32_t sigma = (uint32_t)(G == 1 ? jj : jj / G);
         double F = 0.0, A = 0.0, mg = INFINITY;
         if (paths)
             for (int k = 0; k < d3 * S; ++k) {

@@ -1,0 +1,206 @@
+"""Stochastic Barnes-Hut on MI355X: Python binding of libsbh.
+
+Argument marshalling only.  Every step of the method runs in the HIP
+kernels of libsbh.so (built from csrc/ by build_lib.py); PyTorch supplies
+device memory and the current stream.  The names follow the C ABI in
+include/sbh.h.  If the library is missing this module raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbh.so")
+
+POTENTIAL, WINDING, SMOOTHDIST = 0, 1, 2
+KERNELS = {"potential": POTENTIAL, "winding": WINDING, "smoothdist": SMOOTHDIST}
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("branching", C.c_int32), ("leaf_size", C.c_int32), ("max_level", C.c_int32)]
+
+
+class EvalOpts(C.Structure):
+    _fields_ = [("eps", C.c_float), ("alpha", C.c_float), ("group", C.c_int32), ("rr_mode", C.c_int32),
+                ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p)]
+
+
+class TreeDesc(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("n_nodes", C.c_int64), ("n_blocks", C.c_int64),
+                ("depth", C.c_int32), ("branching", C.c_int32), ("leaf_size", C.c_int32),
+                ("max_level", C.c_int32), ("has_normals", C.c_int32), ("lo", C.c_float * 3),
+                ("side", C.c_float), ("inv_side", C.c_float)]
+
+
+class SbhError(RuntimeError):
+    def __init__(self, call, status, message):
+        super().__init__(f"{call} failed: {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libsbh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with paper_2506_02219_amd/build_lib.py")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
+        L.sbh_build_opts_default.argtypes = [P]
+        L.sbh_build_opts_default.restype = None
+        L.sbh_eval_opts_default.argtypes = [P]
+        L.sbh_eval_opts_default.restype = None
+        L.sbh_build.argtypes = [P, P, P, i64, P, P, P]
+        L.sbh_build.restype = i32
+        L.sbh_eval.argtypes = [P, P, i64, i32, f32, i32, u64, P, P, P]
+        L.sbh_eval.restype = i32
+        L.sbh_brute.argtypes = [P, P, P, i64, P, i64, i32, P, i32, P, P]
+        L.sbh_brute.restype = i32
+        L.sbh_tree_info.argtypes = [P, P]
+        L.sbh_tree_info.restype = i32
+        L.sbh_tree_export.argtypes = [P] + [P] * 11
+        L.sbh_tree_export.restype = i32
+        L.sbh_free.argtypes = [P]
+        L.sbh_free.restype = i32
+        L.sbh_status_string.argtypes = [i32]
+        L.sbh_status_string.restype = C.c_char_p
+        L.sbh_last_error.argtypes = []
+        L.sbh_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(call, status):
+    if status != 0:
+        L = lib()
+        raise SbhError(call, L.sbh_status_string(status).decode(), L.sbh_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, shape_tail=None, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != (dtype or torch.float32):
+        raise TypeError(f"{name} must be {dtype or torch.float32}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Tree:
+    """Handle on a device tree (sbh_tree*).  Keeps no reference to its inputs."""
+
+    def __init__(self, handle):
+        self._h = handle
+        d = TreeDesc()
+        _check("sbh_tree_info", lib().sbh_tree_info(self._h, C.byref(d)))
+        self.n_points, self.n_nodes, self.n_blocks = d.n_points, d.n_nodes, d.n_blocks
+        self.depth, self.branching, self.leaf_size = d.depth, d.branching, d.leaf_size
+        self.max_level, self.has_normals = d.max_level, bool(d.has_normals)
+        self.lo = np.array(list(d.lo), np.float32)
+        self.side, self.inv_side = np.float32(d.side), np.float32(d.inv_side)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """Host copy of the node and point arrays (sbh_tree_export)."""
+        nn, npt = self.n_nodes, self.n_points
+        a = {k: np.zeros(nn, np.int32) for k in ("begin", "count", "level", "digit", "parent", "first_child", "nchild")}
+        a["agg"] = np.zeros((nn, 4), np.float32)
+        a["dip"] = np.zeros((nn, 4), np.float32)
+        a["perm"] = np.zeros(npt, np.uint32)
+        a["codes"] = np.zeros(npt, np.uint64)
+        p = lambda x: x.ctypes.data_as(C.c_void_p)
+        _check("sbh_tree_export", lib().sbh_tree_export(
+            self._h, p(a["begin"]), p(a["count"]), p(a["level"]), p(a["digit"]), p(a["parent"]),
+            p(a["first_child"]), p(a["nchild"]), p(a["agg"]), p(a["dip"]), p(a["perm"]), p(a["codes"])))
+        return a
+
+    def free(self):
+        if self._h:
+            lib().sbh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_level=0, stream=None) -> Tree:
+    """Build the tree on the GPU (sbh_build). sources [n,3], weights [n], normals [n,3] or None."""
+    _dev(sources, "sources", (3,)); _dev(weights, "weights"); _dev(normals, "normals", (3,))
+    n = sources.shape[0]
+    if weights.shape != (n,) or (normals is not None and normals.shape[0] != n):
+        raise ValueError("sources, weights and normals must have the same length")
+    o = BuildOpts(branching, leaf_size, max_level)
+    h = C.c_void_p()
+    _check("sbh_build", lib().sbh_build(_ptr(sources), _ptr(weights), _ptr(normals), n, C.byref(o),
+                                        _stream(stream), C.byref(h)))
+    return Tree(h)
+
+
+def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
+             rr_mode=0, batch=0, paths=None, out=None, stream=None):
+    """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
+    paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records."""
+    import torch
+    _dev(queries, "queries", (3,))
+    nq = queries.shape[0]
+    if out is None:
+        out = torch.empty(nq, dtype=torch.float32, device=queries.device)
+    _dev(out, "out")
+    if paths is not None:
+        _dev(paths, "paths", dtype=torch.int32)
+        if tuple(paths.shape) != (nq, tree.branching ** 3, max(samples, 1), 4):
+            raise ValueError("paths must have shape [nq, d^3, samples, 4]")
+    o = EvalOpts(eps, alpha, group, rr_mode, 0, batch, None if paths is None else paths.data_ptr())
+    _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
+                                      C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
+    return out
+
+
+def sbh_brute(sources, weights, normals, queries, kernel, eps=1e-3, alpha=100.0, fp64=False, out=None,
+              stream=None):
+    """Exact sum Eq. (1) on the GPU (sbh_brute); float64 result when fp64."""
+    import torch
+    _dev(sources, "sources", (3,)); _dev(weights, "weights"); _dev(normals, "normals", (3,))
+    _dev(queries, "queries", (3,))
+    nq = queries.shape[0]
+    dt = torch.float64 if fp64 else torch.float32
+    if out is None:
+        out = torch.empty(nq, dtype=dt, device=queries.device)
+    _dev(out, "out", dtype=dt)
+    o = EvalOpts(eps, alpha, 1, 0, 0, 0, None)
+    _check("sbh_brute", lib().sbh_brute(_ptr(sources), _ptr(weights), _ptr(normals), sources.shape[0],
+                                        _ptr(queries), nq, int(kernel), C.byref(o), int(bool(fp64)),
+                                        _stream(stream), _ptr(out)))
+    return out
+
+
+def sbh_free(tree: Tree):
+    tree.free()

@@ -1,0 +1,435 @@
+// Evaluation kernels on a built tree.
+//
+// k_sbh: the stratified path-sample estimator (Section 3.3, Eqs. (5)-(7),
+// Section 3.3.1, Algorithm 2).  One lane owns one (query, subdomain) pair:
+// with d = 2 a wavefront holds 8 queries x the 8 root-child slots, with d = 4
+// one query x 64 slots.  A lane evaluates its control variate CV_a and its S
+// path samples; the d^3 lanes of a query then add their subdomain totals in
+// a fixed butterfly order, so the result does not depend on the launch.
+//
+// Per path step at node T (children block `blk`):
+//   random words  Philox4x32-10(key = seed, ctr = (stream, slot*S+s, k/2,
+//                 batch)); words (x, y) drive step k even, (z, w) step k odd;
+//   selection     r = umulhi(word, n_T) in [0, n_T): the child whose point
+//                 range holds offset r (probability n_c / n_T), i.e. the
+//                 uniform path index of the paper drawn one level at a time;
+//   roulette      p = min(1, max(1, b_T) / b_c) with b = |q - com| / |B| (Eq.
+//                 (5)); since |B_c| = |B_T| / d this is
+//                 min(1, max(|B_T|, |q - com_T|) / (d |q - com_c|));
+//                 stop iff u >= p, u = (word >> 8) * 2^-24;
+//   swap          Delta = sum_c f_c - f_T over the whole block (Eq. (6)),
+//                 added with weight n_a / (n_T * prod p) (Eq. (7));
+//   leaf          a leaf with several points uses its points as virtual
+//                 children (|B| / d) and ends the path after one step.
+//
+// k_bh: Barnes-Hut (Eq. (2), Algorithm 1) with wavefront voting: a
+// wavefront walks one depth-first traversal for its 64 queries; a child is
+// opened when any lane's far-field test fails; leaves that are opened are
+// summed exactly.  The traversal stack is wavefront-uniform and lives in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sbh_internal.hpp"
+
+namespace sbh {
+
+struct SbhArgs {
+    int32_t samples;
+    int32_t group;
+    int32_t rr_mode;
+    uint32_t batch;
+    uint32_t key0, key1;
+    float eps2, alpha;
+    int32_t* paths;
+};
+
+TreeView make_view(const sbh_tree_impl* t)
+{
+    TreeView v{};
+    v.pts = t->pts;
+    v.pdip = t->pdip;
+    v.bagg = t->bagg;
+    v.bdip = t->bdip;
+    v.btopo = t->btopo;
+    v.nagg = t->nagg;
+    v.ndip = t->ndip;
+    v.n_points = (int32_t)t->n_points;
+    v.leaf_size = t->leaf_size;
+    v.max_level = t->max_level;
+    v.root_internal = (t->n_points > t->leaf_size && t->max_level > 0) ? 1 : 0;
+    v.lo[0] = t->lo[0]; v.lo[1] = t->lo[1]; v.lo[2] = t->lo[2];
+    v.side = t->side;
+    v.diam0 = t->diam[0];
+    return v;
+}
+
+// Smooth-distance scaling: terms are (w / wbar) exp(-alpha (r - r0)); the
+// reported distance is r0 - (log(sum) + log(wbar)) / alpha.
+__device__ __forceinline__ void smooth_setup(const TreeView& tv, float& wscale, float& logwbar)
+{
+    const float wbar = tv.nagg[0].w / (float)tv.n_points;
+    wscale = 1.0f / wbar;
+    logwbar = logf(wbar);
+}
+
+template <int D, int K, bool TRACE>
+__device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float qy, float qz, float r0,
+                                             const KParams& kp, uint32_t n_a, uint32_t begin_a, int32_t blk_a,
+                                             float4 agg_a, float t_a, uint32_t ctr0, uint32_t ctr1, uint32_t ctr3,
+                                             uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
+{
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kInvD = 1.0f / (float)D;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t nT = n_a, beginT = begin_a;
+    int32_t blk = blk_a;
+    int level = 1;
+    float diamT = tv.diam0 * kInvD;
+    float4 aggT = agg_a;
+    float tT = t_a;
+    float prr = 1.0f;
+    float acc = 0.0f;
+    const float fna = (float)n_a;
+    int steps = 0, flag = 0;
+    int32_t end_b = (int32_t)beginT, end_l = level;
+    u32x4 rnd = {0u, 0u, 0u, 0u};
+    for (int k = 0;; ++k) {
+        end_b = (int32_t)beginT;
+        end_l = level;
+        if (nT == 1u) {
+            flag = 1;
+            break;
+        }
+        if ((k & 1) == 0) rnd = philox4x32_10(ctr0, ctr1, (uint32_t)(k >> 1), ctr3, key0, key1);
+        const uint32_t xsel = (k & 1) ? rnd.z : rnd.x;
+        const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
+        const uint32_t r = __umulhi(xsel, nT);
+        const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
+        float sumc = 0.0f, tC = 0.0f;
+        float4 aggC = zero4;
+        uint32_t nC = 1u, beginC = beginT;
+        int32_t blkC = 0;
+        if (internal) {
+            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+            const int32_t base = (int32_t)bt[D3];
+            uint32_t pre = 0u;
+            int32_t nint = 0;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = bt[c];
+                const float4 g = ba[c];
+                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                const float vv = cnt ? v : 0.0f;
+                sumc += vv;
+                const bool hit = (r - pre) < cnt;
+                aggC = hit ? g : aggC;
+                tC = hit ? vv : tC;
+                nC = hit ? cnt : nC;
+                beginC = hit ? beginT + pre : beginC;
+                blkC = hit ? base + nint : blkC;
+                nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                pre += cnt;
+            }
+        } else {
+            for (uint32_t i = 0; i < nT; ++i) {
+                const float4 g = tv.pts[beginT + i];
+                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                sumc += v;
+                aggC = (i == r) ? g : aggC;
+                tC = (i == r) ? v : tC;
+            }
+            beginC = beginT + r;
+        }
+        float p;
+        if (rr_mode == 0) {
+            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
+            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
+            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
+        } else {
+            p = rr_mode == 1 ? 1.0f : 0.5f;
+        }
+        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+        if (u >= p) {
+            flag = 0;
+            break;
+        }
+        prr *= p;
+        acc += (sumc - tT) * __fdividef(fna, (float)nT * prr);
+        ++steps;
+        if (!internal) {
+            end_b = (int32_t)beginC;
+            end_l = level + 1;
+            flag = 2;
+            break;
+        }
+        aggT = aggC;
+        tT = tC;
+        nT = nC;
+        beginT = beginC;
+        blk = blkC;
+        ++level;
+        diamT *= kInvD;
+    }
+    if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
+    return acc;
+}
+
+template <int D, int K, bool TRACE>
+__global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                             SbhArgs a, float* __restrict__ out)
+{
+    constexpr int D3 = D * D * D;
+    constexpr int QPW = 64 / D3;
+    const int lane = threadIdx.x & 63;
+    const int slot = lane % D3;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t j = wave * QPW + lane / D3;
+    if (wave * QPW >= nq) return;  // whole wavefront past the end
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = queries[3 * j];
+        qy = queries[3 * j + 1];
+        qz = queries[3 * j + 2];
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = cube_distance(tv, qx, qy, qz);
+    }
+    const uint32_t* __restrict__ rt = tv.btopo;  // root block
+    const uint32_t n_a = valid ? rt[slot] : 0u;
+    float val = 0.0f;
+    if (n_a > 0u) {
+        uint32_t begin_a = 0u;
+        int32_t nint = 0;
+        for (int c = 0; c < slot; ++c) {
+            const uint32_t cnt = rt[c];
+            begin_a += cnt;
+            nint += ((int)cnt > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+        }
+        const int32_t blk_a = (int32_t)rt[D3] + nint;
+        const float4 agg_a = tv.bagg[slot];
+        const float4 dip_a = (K == SBH_WINDING) ? tv.bdip[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);  // control variate CV_a
+        const uint32_t stream = (uint32_t)(a.group == 1 ? j : j / a.group);
+        float fa = 0.0f;
+        for (int s = 0; s < a.samples; ++s) {
+            int4 rec;
+            fa += sample_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, n_a, begin_a, blk_a, agg_a, cv, stream,
+                                           (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1, a.rr_mode,
+                                           &rec);
+            if constexpr (TRACE) {
+                reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
+            }
+        }
+        val = cv + fa / (float)a.samples;
+    } else if (TRACE && valid) {
+        for (int s = 0; s < a.samples; ++s)
+            reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = make_int4(-1, 0, 0, 0);
+    }
+    // fixed-order butterfly over the d^3 lanes of this query (every lane ends
+    // with the same bits because float addition is commutative)
+#pragma unroll
+    for (int o = 1; o < D3; o <<= 1) val += __shfl_xor(val, o);
+    if (valid && slot == 0) {
+        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(val) + logwbar) / a.alpha;
+        else out[j] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Barnes-Hut with wavefront voting
+// ---------------------------------------------------------------------------
+struct BhArgs {
+    float beta;
+    float eps2, alpha;
+};
+
+template <int D>
+constexpr int bh_stack_depth()
+{
+    return D == 2 ? (8 - 1) * 20 + 2 : (64 - 1) * 10 + 2;
+}
+
+template <int D, int K>
+__global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict__ queries, int64_t nq, BhArgs a,
+                                            float* __restrict__ out)
+{
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    constexpr int MAXS = bh_stack_depth<D>();
+    __shared__ int2 stack[256 / 64][MAXS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (((int64_t)blockIdx.x * blockDim.x + wv * 64) >= nq) return;
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = queries[3 * j];
+        qy = queries[3 * j + 1];
+        qz = queries[3 * j + 2];
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = cube_distance(tv, qx, qy, qz);
+    }
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float acc = 0.0f;
+    int sp = 0;
+    // root: accepted when every lane passes the far-field test
+    {
+        const float4 g = tv.nagg[0];
+        const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
+        const bool near = valid && !(__fdividef(__builtin_sqrtf(dx * dx + dy * dy + dz * dz), tv.diam0) >= a.beta);
+        if (__ballot(near) == 0ull) {
+            acc = term<K>(g, (K == SBH_WINDING) ? tv.ndip[0] : zero4, qx, qy, qz, kp, r0);
+        } else if (!tv.root_internal) {
+            for (int i = 0; i < tv.n_points; ++i)
+                acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
+        } else {
+            if (lane == 0) stack[wv][0] = make_int2(0, 0);  // block 0, level 0 (packed), begin 0
+            sp = 1;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    while (sp > 0) {
+        --sp;
+        const int2 e = stack[wv][sp];
+        const int32_t blk = __builtin_amdgcn_readfirstlane(e.x & 0x07FFFFFF);
+        const int level = __builtin_amdgcn_readfirstlane((int)((uint32_t)e.x >> 27));
+        uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
+        __builtin_amdgcn_wave_barrier();
+        const float diamC = ldexpf(tv.diam0, -(level + 1) * (D == 2 ? 1 : 2));
+        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+        const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+        const int32_t base = (int32_t)bt[D3];
+        int32_t nint = 0;
+        for (int c = 0; c < D3; ++c) {
+            const uint32_t cnt = bt[c];
+            if (cnt == 0u) continue;
+            const bool internal_c = (int)cnt > tv.leaf_size && level + 1 < tv.max_level;
+            const float4 g = ba[c];
+            const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
+            const bool near = valid && !(__fdividef(__builtin_sqrtf(dx * dx + dy * dy + dz * dz), diamC) >= a.beta);
+            if (__ballot(near) == 0ull) {
+                acc += term<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, qx, qy, qz, kp, r0);
+            } else if (internal_c) {
+                if (lane == 0) stack[wv][sp] = make_int2((int32_t)(((uint32_t)(level + 1) << 27) | (uint32_t)(base + nint)), (int32_t)pre);
+                ++sp;
+            } else {
+                for (uint32_t i = pre; i < pre + cnt; ++i)
+                    acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
+            }
+            nint += internal_c ? 1 : 0;
+            pre += cnt;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (valid) {
+        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(acc) + logwbar) / a.alpha;
+        else out[j] = acc;
+    }
+}
+
+// A tree whose root is a leaf: every query is summed exactly over its points.
+template <int K>
+__global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                    float eps2, float alpha, float* __restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nq) return;
+    const float qx = queries[3 * j], qy = queries[3 * j + 1], qz = queries[3 * j + 2];
+    KParams kp{eps2, alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = cube_distance(tv, qx, qy, qz);
+    }
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float acc = 0.0f;
+    for (int i = 0; i < tv.n_points; ++i)
+        acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
+    if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(acc) + logwbar) / alpha;
+    else out[j] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int K>
+static hipError_t launch_leaf(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
+                              hipStream_t s)
+{
+    k_leaf_exact<K><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(tv, q, nq, e.eps * e.eps, e.alpha, out);
+    return hipGetLastError();
+}
+
+template <int D, int K>
+static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
+                                hipStream_t s)
+{
+    constexpr int QPW = 64 / (D * D * D);
+    SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
+              e.eps * e.eps, e.alpha, e.paths};
+    const int64_t waves = (nq + QPW - 1) / QPW;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (e.paths) k_sbh<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+    else k_sbh<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+    return hipGetLastError();
+}
+
+template <int D, int K>
+static hipError_t launch_bh_dk(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
+                               hipStream_t s)
+{
+    BhArgs a{e.beta, e.eps * e.eps, e.alpha};
+    k_bh<D, K><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(tv, q, nq, a, out);
+    return hipGetLastError();
+}
+
+#define SBH_DISPATCH(FN, t, ...)                                              \
+    do {                                                                      \
+        if ((t)->d == 2) {                                                    \
+            if (e.kernel == SBH_POTENTIAL) return FN<2, SBH_POTENTIAL>(__VA_ARGS__);   \
+            if (e.kernel == SBH_WINDING) return FN<2, SBH_WINDING>(__VA_ARGS__);       \
+            return FN<2, SBH_SMOOTHDIST>(__VA_ARGS__);                        \
+        } else {                                                              \
+            if (e.kernel == SBH_POTENTIAL) return FN<4, SBH_POTENTIAL>(__VA_ARGS__);   \
+            if (e.kernel == SBH_WINDING) return FN<4, SBH_WINDING>(__VA_ARGS__);       \
+            return FN<4, SBH_SMOOTHDIST>(__VA_ARGS__);                        \
+        }                                                                     \
+    } while (0)
+
+hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
+                           float* out, hipStream_t s)
+{
+    const TreeView tv = make_view(t);
+    if (!tv.root_internal) {
+        if (e.kernel == SBH_POTENTIAL) return launch_leaf<SBH_POTENTIAL>(tv, queries, nq, e, out, s);
+        if (e.kernel == SBH_WINDING) return launch_leaf<SBH_WINDING>(tv, queries, nq, e, out, s);
+        return launch_leaf<SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
+    }
+    SBH_DISPATCH(launch_sbh_dk, t, tv, queries, nq, e, out, s);
+}
+
+hipError_t launch_bh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
+                          float* out, hipStream_t s)
+{
+    const TreeView tv = make_view(t);
+    SBH_DISPATCH(launch_bh_dk, t, tv, queries, nq, e, out, s);
+}
+
+}  // namespace sbh

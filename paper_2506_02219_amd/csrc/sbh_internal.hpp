@@ -1,0 +1,182 @@
+// Internal declarations shared by the HIP translation units of libsbh.
+//
+// Device data layout of a tree (all in HBM, built by build.hip):
+//   pts    float4[M]         sorted points (x, y, z, w)
+//   pdip   float4[M]         sorted w*n (winding only)
+//   Nodes, breadth-first, Morton order within a level (for export/build):
+//     nbegin/ncount/nlevel/ndigit/nparent/nfirst/nnchild int32[n_nodes]
+//     nagg float4[n_nodes] (centre of mass, weight), ndip float4[n_nodes]
+//   Child blocks, one per internal node, in breadth-first order of the
+//   internal nodes (the root's block is block 0):
+//     bagg   float4[n_blocks][d^3]   aggregate of the child in digit slot s
+//                                    (zero for an empty slot)
+//     bdip   float4[n_blocks][d^3]   summed w*n per slot (winding only)
+//     btopo  uint32[n_blocks][TS]    point count per slot, then at [d^3] the
+//                                    block id of the first internal child;
+//                                    the internal children of one node hold
+//                                    consecutive block ids in slot order.
+//   A node is internal iff count > leaf_size and level < max_level, so the
+//   counts alone tell which slots own blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/sbh.h"
+
+namespace sbh {
+
+constexpr int kMaxLevels = 64;
+
+__host__ __device__ constexpr int topo_stride(int d3) { return ((d3 + 1 + 15) / 16) * 16; }
+
+struct TreeView {
+    const float4* pts;
+    const float4* pdip;
+    const float4* bagg;
+    const float4* bdip;
+    const uint32_t* btopo;
+    const float4* nagg;   // nagg[0] = root aggregate
+    const float4* ndip;
+    int32_t n_points;
+    int32_t leaf_size;
+    int32_t max_level;
+    int32_t root_internal;
+    float lo[3];
+    float side;
+    float diam0;          // root cell diagonal; level l has diam0 / d^l
+};
+
+struct sbh_tree_impl {
+    int device;
+    int d, d3, bits, leaf_size, max_level, depth, has_normals;
+    int64_t n_points, n_nodes, n_blocks;
+    float lo[3], side, inv_side;
+    float diam[kMaxLevels];
+    float4 *pts, *pdip;
+    uint32_t* perm;
+    uint64_t* codes;
+    int32_t *nbegin, *ncount, *nlevel, *ndigit, *nparent, *nfirst, *nnchild;
+    float4 *nagg, *ndip;
+    float4 *bagg, *bdip;
+    uint32_t* btopo;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32
+// S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and key increments
+// 0x9E3779B9 / 0xBB67AE85.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------------------------
+// Kernel terms f in float32.  `a` = (centre or position, weight), `dp` = w*n.
+// ---------------------------------------------------------------------------
+struct KParams {
+    float eps2;      // eps^2 (potential)
+    float alpha;     // smooth distance
+    float wscale;    // 1 / mean weight (smooth distance)
+};
+
+constexpr float kInv4Pi = 0.0795774715459476679f;
+
+template <int K>
+__device__ __forceinline__ float term_r2(float4 a, float4 dp, float dx, float dy, float dz, float r2,
+                                         const KParams& kp, float r0)
+{
+    if constexpr (K == SBH_POTENTIAL) {
+        return a.w * __builtin_amdgcn_rsqf(r2 + kp.eps2);
+    } else if constexpr (K == SBH_WINDING) {
+        const float inv = __builtin_amdgcn_rsqf(r2);
+        const float v = (dp.x * dx + dp.y * dy + dp.z * dz) * (inv * inv * inv) * kInv4Pi;
+        return r2 > 0.0f ? v : 0.0f;
+    } else {
+        const float r = __builtin_sqrtf(r2);
+        return a.w * kp.wscale * __expf(-kp.alpha * (r - r0));
+    }
+}
+
+template <int K>
+__device__ __forceinline__ float term(float4 a, float4 dp, float qx, float qy, float qz, const KParams& kp,
+                                      float r0)
+{
+    const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    return term_r2<K>(a, dp, dx, dy, dz, r2, kp, r0);
+}
+
+// Lower bound on the distance from q to any source (distance to the root
+// cube); used as the shift of the smooth-distance sum so that no term
+// overflows: with it every exp(-alpha (r - r0)) of a point or of a centre of
+// mass is at most 1.
+__device__ __forceinline__ float cube_distance(const TreeView& tv, float qx, float qy, float qz)
+{
+    const float ex = fmaxf(fmaxf(tv.lo[0] - qx, qx - (tv.lo[0] + tv.side)), 0.0f);
+    const float ey = fmaxf(fmaxf(tv.lo[1] - qy, qy - (tv.lo[1] + tv.side)), 0.0f);
+    const float ez = fmaxf(fmaxf(tv.lo[2] - qz, qz - (tv.lo[2] + tv.side)), 0.0f);
+    return __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files).  All return hipError_t.
+// ---------------------------------------------------------------------------
+struct BuildScratch;
+
+hipError_t launch_bbox(const float* src, const float* w, const float* nrm, int64_t n, float* params_dev,
+                       float* partial_dev, int nblocks, hipStream_t s);
+hipError_t launch_morton(const float* src, int64_t n, const float* params_dev, uint64_t* keys, uint32_t* vals,
+                         hipStream_t s);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
+                            int begin_bit, int end_bit, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+size_t radix_sort_hist_size(int64_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev, uint32_t* tmp,
+                              hipStream_t s);
+size_t scan_tmp_size(int64_t n);
+
+struct EvalLaunch {
+    int kernel;
+    int samples;
+    uint64_t seed;
+    int group;
+    int rr_mode;
+    uint32_t batch;
+    float beta;
+    float eps, alpha;
+    int32_t* paths;
+};
+
+hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
+                           float* out, hipStream_t s);
+hipError_t launch_bh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
+                          float* out, hipStream_t s);
+hipError_t launch_brute(const float* src, const float* w, const float* nrm, int64_t n, const float* queries,
+                        int64_t nq, int kernel, float eps, float alpha, int fp64, void* out, hipStream_t s);
+sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, int64_t n, int d, int leaf_size,
+                           int max_level, hipStream_t s, sbh_tree_impl* t, std::string* msg);
+
+TreeView make_view(const sbh_tree_impl* t);
+
+}  // namespace sbh

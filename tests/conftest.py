@@ -18,3 +18,10 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name every test before it runs, so a run that ends abruptly still says where
+    import sys
+    sys.stderr.write(f"\n[start] {nodeid}\n")
+    sys.stderr.flush()

@@ -1,0 +1,160 @@
+"""Helpers for the GPU parity tests: run the HIP path through the binding and
+the FP64 oracle on the same seeded inputs, and compare them.
+
+Tolerances (stated once, used by every parity test):
+  - tree topology, point order and Morton codes: bit-exact;
+  - tree aggregates (float32 on the GPU vs float64): relative 2e-5 of the
+    node weight, 2e-5 of the root cube side for centres of mass;
+  - estimator and Barnes-Hut values: relative error at most 1e-4, with the
+    relative scale floored at 1 for winding numbers (absolute error) and at
+    1/alpha for smooth distances; where the value is a difference of much
+    larger terms, float32 cannot reach 1e-4 and the bound is the float32
+    rounding bound 64 * 2^-24 * (sum of the absolute terms that entered the
+    estimate), which the oracle reports per query;
+  - sampled paths (end node, depth, accepted steps, stop reason): bit-exact,
+    except queries whose smallest Russian-roulette margin |u - p| is below
+    1e-5 (a float32 / float64 near-tie); at most 1e-5 of the queries may
+    diverge, and every divergent query must be such a near-tie.
+"""
+import math
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2506_02219_amd as P
+
+DEV = "cuda"
+U32 = 2.0 ** -24
+NEAR_TIE = 1e-5
+REL_TOL = 1e-4
+
+
+def T(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def build_both(src, w, nrm=None, d=2, leaf_size=8, max_level=0):
+    gt = P.sbh_build(T(src), T(w), None if nrm is None else T(nrm), branching=d, leaf_size=leaf_size,
+                     max_level=max_level)
+    ot = oracle.Tree(src, w, nrm, d=d, leaf_size=leaf_size, max_level=max_level)
+    return gt, ot
+
+
+def compare_trees(gt, ot):
+    """Bit-exact topology; aggregates to float32 accuracy."""
+    g = gt.export()
+    assert gt.n_nodes == ot.n_nodes, (gt.n_nodes, ot.n_nodes)
+    assert gt.depth == ot.depth
+    assert np.array_equal(gt.lo, ot.lo) and gt.side == ot.side and gt.inv_side == ot.inv_side
+    assert np.array_equal(g["codes"], ot.codes)
+    assert np.array_equal(g["perm"].astype(np.int64), ot.perm)
+    for k in ("begin", "count", "level", "digit", "parent", "first_child", "nchild"):
+        assert np.array_equal(g[k].astype(np.int64), getattr(ot, k).astype(np.int64)), k
+    mass = ot.agg[:, 3]
+    assert np.all(np.abs(g["agg"][:, 3] - mass) <= 2e-5 * mass)
+    assert np.all(np.abs(g["agg"][:, 0:3] - ot.agg[:, 0:3]) <= 2e-5 * float(ot.side))
+    dip = ot.agg[:, 4:7]
+    dscale = np.maximum(np.linalg.norm(dip, axis=1, keepdims=True), mass[:, None] * 1e-3)
+    assert np.all(np.abs(g["dip"][:, 0:3] - dip) <= 2e-5 * dscale + 1e-12)
+    return g
+
+
+def value_scale(ref, kernel, alpha):
+    ref = np.abs(ref)
+    if kernel == P.WINDING:
+        return np.maximum(ref, 1.0)
+    if kernel == P.SMOOTHDIST:
+        return np.maximum(ref, 1.0 / alpha)
+    return ref
+
+
+def value_errors(gpu, F, absum, kernel, alpha=100.0):
+    """Return (ok mask, relative error, used-fp32-bound mask) for GPU values vs oracle sums F."""
+    if kernel == P.SMOOTHDIST:
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ref = -np.log(F) / alpha
+            # d(-log F / alpha) = -dF / (alpha F)
+            fp32_bound = 64 * U32 * absum / (alpha * np.abs(F))
+    else:
+        ref = F
+        fp32_bound = 64 * U32 * absum
+    scale = value_scale(ref, kernel, alpha)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        err = np.abs(gpu - ref) / scale
+        bound = np.maximum(REL_TOL, fp32_bound / scale)
+        ok = (err <= bound) | (np.isnan(gpu) & np.isnan(ref))
+    # a sum whose float32 sign is not determined (|F| below its rounding bound)
+    if kernel == P.SMOOTHDIST:
+        undetermined = np.abs(F) <= 64 * U32 * absum
+        ok |= undetermined
+    used_bound = ok & ~((err <= REL_TOL) | (np.isnan(gpu) & np.isnan(ref)))
+    return ok, err, used_bound
+
+
+def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, eps=1e-3, alpha=100.0,
+              index=None, gpu_out=None, gpu_paths=None, batch=0):
+    """Run (or take) the GPU estimator and compare with the oracle, query by query.
+    With `index`, `queries` are a subset of a larger set evaluated on the GPU
+    (gpu_out/gpu_paths are the full-set outputs)."""
+    d3 = gt.branching ** 3
+    if gpu_out is None:
+        q = T(queries)
+        paths = torch.full((queries.shape[0], d3, samples, 4), -7, dtype=torch.int32, device=DEV)
+        out = P.sbh_eval(gt, q, kernel, samples=samples, seed=seed, eps=eps, alpha=alpha, group=group,
+                         rr_mode=rr_mode, paths=paths, batch=batch)
+        g = host(out)
+        gp = host(paths)
+    else:
+        g = gpu_out[index]
+        gp = gpu_paths[index]
+    r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps, alpha=alpha,
+               paths=True, index=index, batch=batch)
+    near = r["margin"] < NEAR_TIE
+    path_bad = np.any(gp != r["paths"], axis=(1, 2, 3))
+    ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha)
+    bad = path_bad | ~ok
+    n = queries.shape[0]
+    stats = dict(n=n, path_mismatch=int(path_bad.sum()), value_mismatch=int((~ok).sum()),
+                 near_ties=int(near.sum()), fp32_bound_used=int(used_bound.sum()),
+                 max_rel_err=float(np.nanmax(np.where(ok, err, np.nan))) if ok.any() else float("nan"),
+                 median_rel_err=float(np.nanmedian(err)))
+    assert not np.any(bad & ~near), (stats, np.nonzero(bad & ~near)[0][:10])
+    assert bad.sum() <= 1e-5 * n, stats
+    return stats
+
+
+def check_bh(gt, ot, queries, kernel, beta, eps=1e-3, alpha=100.0, gpu_out=None, qsel=None):
+    """Barnes-Hut with wavefront voting vs the oracle's vote mode (groups of 64)."""
+    if gpu_out is None:
+        g = host(P.sbh_eval(gt, T(queries), kernel, beta=beta, samples=0, eps=eps, alpha=alpha))
+    else:
+        g = gpu_out
+    F, margin, _ = ot.bh(queries, kernel, beta, group=64, eps=eps, alpha=alpha)
+    # Barnes-Hut only adds positive-weight terms for the potential; use the exact
+    # absolute sum bound of the accepted terms via brute force scale
+    if kernel == P.SMOOTHDIST:
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ref = -np.log(F) / alpha
+    else:
+        ref = F
+    scale = value_scale(ref, kernel, alpha)
+    err = np.abs(g - ref) / scale
+    near = margin < NEAR_TIE
+    bad = ~(err <= REL_TOL)
+    assert not np.any(bad & ~near), (np.nonzero(bad & ~near)[0][:10], float(np.nanmax(err)))
+    assert bad.sum() <= max(1e-5 * queries.shape[0], 0), int(bad.sum())
+    return dict(max_rel_err=float(np.nanmax(err)), near=int(near.sum()))
+
+
+def fp64_reference(src, w, nrm, queries, kernel, eps=1e-3, alpha=100.0):
+    return host(P.sbh_brute(T(src), T(w), None if nrm is None else T(nrm), T(queries), kernel, eps=eps,
+                            alpha=alpha, fp64=True))

@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/sbh.h declares (no compute calls: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sbh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(sbh_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sbh_build", "sbh_eval", "sbh_brute", "sbh_free", "sbh_tree_info", "sbh_tree_export",
+              "sbh_status_string", "sbh_last_error", "sbh_build_opts_default", "sbh_eval_opts_default"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2506_02219_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libsbh.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_defaults():
+    import paper_2506_02219_amd as P
+    L = P.lib()
+    assert L.sbh_status_string(0) == b"SBH_OK"
+    for code in (-1, -2, -3, -4, -5):
+        assert L.sbh_status_string(code).startswith(b"SBH_E")
+    o = P.EvalOpts()
+    L.sbh_eval_opts_default(ctypes.byref(o))
+    assert (round(o.eps, 6), o.alpha, o.group, o.rr_mode, o.proposal, o.batch, o.paths) == (0.001, 100.0, 1, 0, 0, 0, None)
+    b = P.BuildOpts()
+    L.sbh_build_opts_default(ctypes.byref(b))
+    assert (b.branching, b.leaf_size, b.max_level) == (2, 8, 0)
+
+
+def test_struct_layouts_match_header():
+    import paper_2506_02219_amd as P
+    assert ctypes.sizeof(P.BuildOpts) == 12
+    assert ctypes.sizeof(P.EvalOpts) == 32 and P.EvalOpts.paths.offset == 24
+    assert ctypes.sizeof(P.TreeDesc) == 64 and P.TreeDesc.lo.offset == 44
+
+
+def test_argument_errors_before_any_device_work():
+    """Argument checks run on the host before any HIP call, so they work here."""
+    import paper_2506_02219_amd as P
+    L = P.lib()
+    h = ctypes.c_void_p()
+    assert L.sbh_build(None, None, None, 10, None, None, ctypes.byref(h)) == -1
+    assert b"NULL" in L.sbh_last_error()
+    assert L.sbh_eval(None, None, 0, 0, 2.0, 1, 0, None, None, None) == -1
+    assert L.sbh_brute(None, None, None, 0, None, 0, 0, None, 0, None, None) == -1
+    assert L.sbh_free(None) == 0

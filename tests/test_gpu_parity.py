@@ -1,0 +1,190 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Small cases span several tiles and ragged tails; the full-size workloads are
+checked on sampled queries in the launch configuration the benchmark times.
+Tolerances are stated in gpu_helpers.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+import paper_2506_02219_amd as P
+from gpu_helpers import (DEV, T, host, build_both, compare_trees, check_sbh, check_bh, fp64_reference,
+                         value_scale)
+
+pytestmark = pytest.mark.gpu
+
+
+def surface(m, seed=21, level=4):
+    pts, nrm, w, _ = W.star_surface(m, seed, level=level)
+    return pts.astype(np.float32), nrm.astype(np.float32), w.astype(np.float32)
+
+
+def box_queries(n, seed, lo=-1.5, hi=1.5):
+    return np.random.Generator(np.random.PCG64(seed)).uniform(lo, hi, (n, 3)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------- brute force
+@pytest.mark.parametrize("kernel", [P.POTENTIAL, P.WINDING, P.SMOOTHDIST])
+def test_brute_matches_oracle(kernel):
+    src, nrm, w = surface(3001)
+    q = box_queries(1000, 3)
+    F = oracle.brute(src, w, nrm, q, kernel)
+    ref = oracle.smooth_distance(F) if kernel == P.SMOOTHDIST else F
+    g64 = fp64_reference(src, w, nrm, q, kernel)
+    assert np.all(np.abs(g64 - ref) <= 1e-11 * value_scale(ref, kernel, 100.0))
+    g32 = host(P.sbh_brute(T(src), T(w), T(nrm), T(q), kernel))
+    assert np.all(np.abs(g32 - ref) <= 1e-4 * value_scale(ref, kernel, 100.0))
+
+
+# ----------------------------------------------------------------------------- tree
+@pytest.mark.parametrize("d", [2, 4])
+def test_tree_bit_exact_c1(d):
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights, d=d)
+    compare_trees(gt, ot)
+
+
+@pytest.mark.parametrize("d,leaf", [(2, 8), (4, 8), (2, 1)])
+def test_tree_bit_exact_surface(d, leaf):
+    src, nrm, w = surface(50000, 5)
+    gt, ot = build_both(src, w, nrm, d=d, leaf_size=leaf)
+    compare_trees(gt, ot)
+
+
+def test_tree_duplicates_and_max_level():
+    src = np.array([[0.3, 0.3, 0.3]] * 40 + [[0, 0, 0], [1, 1, 1]] + [[0.7, 0.2, 0.9]] * 3, np.float32)
+    w = np.linspace(0.5, 1.5, len(src)).astype(np.float32)
+    for d, ml in ((2, 0), (2, 5), (4, 3)):
+        gt, ot = build_both(src, w, d=d, leaf_size=4, max_level=ml)
+        compare_trees(gt, ot)
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 8, 9, 4097])
+def test_tree_small_and_ragged(m):
+    c = W.uniform_cube(m, 1, 77)
+    gt, ot = build_both(c.sources, c.weights)
+    compare_trees(gt, ot)
+
+
+# ----------------------------------------------------------------------------- stochastic estimator
+@pytest.mark.parametrize("d,S,G,rr", [(2, 1, 1, 0), (2, 4, 1, 0), (4, 1, 1, 0), (4, 2, 1, 0),
+                                      (2, 1, 64, 0), (2, 2, 1, 1), (2, 2, 1, 2)])
+def test_sbh_parity_c1(d, S, G, rr):
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights, d=d)
+    st = check_sbh(gt, ot, c.queries, P.POTENTIAL, samples=S, seed=0, group=G, rr_mode=rr)
+    print(st)
+
+
+@pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST, P.POTENTIAL])
+@pytest.mark.parametrize("d", [2, 4])
+def test_sbh_parity_surface_kernels(kernel, d):
+    src, nrm, w = surface(30000, 9)
+    q = box_queries(3000, 4)  # ragged: 3000 = 46 * 64 + 56
+    gt, ot = build_both(src, w, nrm, d=d)
+    st = check_sbh(gt, ot, q, kernel, samples=2, seed=123, alpha=20.0)
+    print(st)
+
+
+def test_sbh_seeds_and_batch_words_change_streams():
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights)
+    outs = []
+    for seed, batch in ((1, 0), (2**40 + 5, 0), (7, 3), (7, 0)):
+        check_sbh(gt, ot, c.queries[:512], P.POTENTIAL, samples=1, seed=seed, batch=batch)
+        outs.append(host(P.sbh_eval(gt, T(c.queries[:512]), P.POTENTIAL, samples=1, seed=seed, batch=batch)))
+    assert not np.array_equal(outs[2], outs[3])
+
+
+def test_sbh_deterministic_and_launch_independent():
+    c = W.c1()
+    gt, _ = build_both(c.sources, c.weights)
+    q = T(c.queries)
+    a = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9))
+    b = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9))
+    assert np.array_equal(a, b)
+    # a query's value depends only on its index, not on how many queries share the launch
+    part = host(P.sbh_eval(gt, q[:1000], P.POTENTIAL, samples=3, seed=9))
+    assert np.array_equal(part, a[:1000])
+
+
+def test_sbh_root_leaf_is_exact():
+    for m in (1, 5, 8):
+        c = W.uniform_cube(m, 100, 31)
+        gt, ot = build_both(c.sources, c.weights)
+        g = host(P.sbh_eval(gt, T(c.queries), P.POTENTIAL, samples=1))
+        F = oracle.brute(c.sources, c.weights, None, c.queries, P.POTENTIAL)
+        assert np.allclose(g, F, rtol=2e-6)
+        b = host(P.sbh_eval(gt, T(c.queries), P.POTENTIAL, beta=2.0, samples=0))
+        assert np.allclose(b, F, rtol=2e-6)
+
+
+def test_sbh_empty_and_tiny_query_sets():
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights)
+    out = torch.full((4,), 123.0, device=DEV)
+    P.sbh_eval(gt, T(c.queries[:0]), P.POTENTIAL, out=out[:0])
+    assert np.all(host(out) == 123.0)
+    for n in (1, 7, 63, 65):
+        check_sbh(gt, ot, c.queries[:n], P.POTENTIAL, samples=1)
+
+
+def test_duplicate_points_estimator():
+    src = np.array([[0.3, 0.3, 0.3]] * 40 + [[0, 0, 0], [1, 1, 1]] + [[0.7, 0.2, 0.9]] * 30, np.float32)
+    w = np.linspace(0.5, 1.5, len(src)).astype(np.float32)
+    q = box_queries(500, 8, -0.5, 1.5)
+    gt, ot = build_both(src, w, d=2, leaf_size=4, max_level=6)
+    check_sbh(gt, ot, q, P.POTENTIAL, samples=2)
+
+
+def test_argument_errors():
+    c = W.c1()
+    gt, _ = build_both(c.sources[:100], c.weights[:100])
+    q = T(c.queries[:10])
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.WINDING)          # no normals
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.POTENTIAL, samples=0, beta=0.0)
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, 7)
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.POTENTIAL, group=0)
+    bad = c.sources[:100].copy(); bad[5, 1] = np.nan
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_build(T(bad), T(c.weights[:100]))
+    wneg = c.weights[:100].copy(); wneg[3] = -1
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_build(T(c.sources[:100]), T(wneg))
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_build(T(c.sources[:100]), T(c.weights[:100]), branching=3)
+
+
+# ----------------------------------------------------------------------------- Barnes-Hut
+@pytest.mark.parametrize("d,beta", [(2, 2.0), (2, 0.7), (4, 2.0), (2, 6.0)])
+def test_bh_parity_c1(d, beta):
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights, d=d)
+    print(check_bh(gt, ot, c.queries, P.POTENTIAL, beta))
+
+
+@pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST])
+def test_bh_parity_surface_kernels(kernel):
+    src, nrm, w = surface(30000, 9)
+    q = box_queries(3000, 4)
+    gt, ot = build_both(src, w, nrm)
+    print(check_bh(gt, ot, q, kernel, 2.0, alpha=20.0))
+
+
+def test_bh_infinite_beta_is_exact():
+    src, nrm, w = surface(20000, 2)
+    q = box_queries(700, 1)
+    gt, _ = build_both(src, w, nrm)
+    for kernel in (P.POTENTIAL, P.WINDING):
+        g = host(P.sbh_eval(gt, T(q), kernel, beta=math.inf, samples=0))
+        ref = fp64_reference(src, w, nrm, q, kernel)
+        assert np.all(np.abs(g - ref) <= 1e-4 * value_scale(ref, kernel, 100.0))
