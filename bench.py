@@ -1,0 +1,362 @@
+"""Benchmark: queries/s of the stochastic Barnes-Hut estimator at its own
+median relative error, against deterministic Barnes-Hut at the same error,
+on one MI355X.
+
+Default workload: the learned-vs-plain potential workload, 2^22 area-weighted
+samples of a random star-shaped surface (radius 1 + 0.15 g, g a random
+spherical-harmonic field of degrees 1..6), softened potential (eps = 1e-3),
+queries = the 1000 x 1000 pixel centres of the z=0 plane over [-1.5,1.5]^2,
+S = 1 sample per subdomain, Philox seed 0.  --config c2 (winding numbers,
+2^20 sources) and c3 (smooth distances, 2^22 sources) run the other
+workloads.
+
+A step is one evaluation of every query (sbh_eval) on a tree built once
+before the timed region (the tree build is timed separately and reported as
+build_ms).  The error of a method is the median over a fixed sample of
+queries of |F - F_ref| / max(|F_ref|, floor) against float64 GPU brute force
+(floor 1 for winding numbers, 1/alpha for smooth distances, 0 for the
+potential).  Deterministic Barnes-Hut is swept over beta and its time at the
+stochastic method's error is interpolated in log(time)-log(error).
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    "c1": dict(gen="c1", kernel=0, samples=1, beta=2.0),
+    "c2": dict(gen="c2", kernel=1, samples=1, beta=2.0),
+    "c3": dict(gen="c3", kernel=2, samples=1, beta=2.0),
+    "c5": dict(gen="c5", kernel=0, samples=1, beta=2.0),
+}
+BETAS = [0.2, 0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 40]
+S_SWEEP = [1, 2, 4, 8, 16, 32]
+FP32_PEAK_TFLOPS = 157.3
+# float32 operations per kernel term: differences, squared distance, the
+# kernel itself, the weight; transcendental calls counted as one operation
+TERM_FLOPS = {0: 11, 1: 17, 2: 14}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
+    ap.add_argument("--branching", type=int, default=2, help="tree of the stochastic estimator")
+    ap.add_argument("--bh-branching", type=int, default=2, help="tree of the Barnes-Hut comparator")
+    ap.add_argument("--group", type=int, default=64, help="queries per shared random stream (64: one per wavefront)")
+    ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--err-sample", type=int, default=16384)
+    ap.add_argument("--no-bh", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--no-sweep", action="store_true")
+    return ap.parse_args()
+
+
+def rel_errors(v, ref, kernel, alpha=100.0):
+    ref = np.asarray(ref, np.float64)
+    v = np.asarray(v, np.float64)
+    if kernel == 1:
+        scale = np.maximum(np.abs(ref), 1.0)
+    elif kernel == 2:
+        scale = np.maximum(np.abs(ref), 1.0 / alpha)
+    else:
+        scale = np.abs(ref)
+    e = np.abs(v - ref) / scale
+    return np.where(np.isnan(e), np.inf, e)
+
+
+def csrc_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2506_02219_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "queries are independent, so several GPUs would each evaluate a share of them", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2506_02219_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    cfg = CONFIGS[args.config]
+    kernel = cfg["kernel"]
+    S = args.samples or cfg["samples"]
+    t0 = time.time()
+    cl = getattr(W, cfg["gen"])()
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(cl.sources).to(dev)
+    wts = torch.from_numpy(cl.weights).to(dev)
+    nrm = None if cl.normals is None else torch.from_numpy(cl.normals).to(dev)
+    # the stochastic method sees the queries shuffled (its wavefronts share random streams, so
+    # neighbouring pixels must not share a wavefront); Barnes-Hut runs on the original grid order
+    qry_np, perm = W.shuffle_queries(cl.queries, 4242)
+    qry = torch.from_numpy(qry_np).to(dev)
+    qry_bh = torch.from_numpy(cl.queries).to(dev)
+    N = qry.shape[0]
+    stream = torch.cuda.current_stream()
+
+    # plain device copy of known size: calibrates the HBM counters of a profiled run
+    calib = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    calib2 = torch.empty_like(calib)
+    calib2.copy_(calib)
+
+    # --- tree build (timed separately)
+    def build(d):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        t = P.sbh_build(src, wts, nrm, branching=d, leaf_size=8)
+        torch.cuda.synchronize()
+        return t, (time.perf_counter() - tb) * 1e3
+    tree, build_ms = build(args.branching)
+    tree, build_ms = build(args.branching)  # second build: no first-call overheads
+
+    # --- reference on a fixed query sample
+    rng = np.random.Generator(np.random.PCG64(99))
+    ns = min(args.err_sample, N)
+    sidx = np.sort(rng.choice(N, size=ns, replace=False))
+    sidx_t = torch.from_numpy(sidx).to(dev)
+    ref = P.sbh_brute(src, wts, nrm, qry[sidx_t].contiguous(), kernel, fp64=True).cpu().numpy()
+
+    out = torch.empty(N, dtype=torch.float32, device=dev)
+
+    def run_sbh(tr, samples, group=args.group):
+        P.sbh_eval(tr, qry, kernel, samples=samples, seed=0, group=group, out=out)
+
+    def run_bh(tr, beta):
+        P.sbh_eval(tr, qry_bh, kernel, beta=beta, samples=0, out=out)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    bh_idx_t = torch.from_numpy(perm[sidx]).to(dev)
+
+    def err_of(fn, idx_t=sidx_t):
+        fn()
+        torch.cuda.synchronize()
+        return float(np.median(rel_errors(out[idx_t].cpu().numpy(), ref, kernel)))
+
+    # --- the timed region: K evaluations of every query
+    for _ in range(args.warmup):
+        run_sbh(tree, S)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        run_sbh(tree, S)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    qps = N / (ms_per_step * 1e-3)
+    err_star = err_of(lambda: run_sbh(tree, S))
+
+    # --- algorithmic work of one launch, from the kernel's own path records
+    d = args.branching
+    exp = tree.export()
+
+    def work_of(group):
+        """Bytes and flops the estimator must read / compute for one launch (active lanes only)."""
+        d3 = d ** 3
+        paths = torch.empty((N, d3, S, 4), dtype=torch.int32, device=dev)
+        P.sbh_eval(tree, qry, kernel, samples=S, seed=0, group=group, out=out, paths=paths)
+        torch.cuda.synchronize()
+        rec = paths.cpu().numpy().reshape(-1, 4)
+        del paths
+        rec = rec[rec[:, 0] >= 0]
+        steps_acc = rec[:, 2].astype(np.int64)
+        flags = rec[:, 3]
+        # node lookup by (level, begin)
+        key_nodes = exp["level"].astype(np.int64) * (1 << 32) + exp["begin"].astype(np.int64)
+        order = np.argsort(key_nodes)
+        ks = key_nodes[order]
+        end_key = rec[:, 1].astype(np.int64) * (1 << 32) + rec[:, 0].astype(np.int64)
+        pos = np.minimum(np.searchsorted(ks, end_key), len(ks) - 1)
+        found = ks[pos] == end_key
+        end_count = np.where(found, exp["count"][order][pos], 1).astype(np.int64)
+        end_internal = found & (end_count > 8) & (rec[:, 1] < tree.max_level)
+        wind = kernel == 1
+        blk_bytes = d3 * 16 * (2 if wind else 1) + d3 * 4 + 4
+        pt_bytes = 16 * (2 if wind else 1)
+        # accepted steps read child blocks, except the last one of a path that moved onto a virtual point
+        # (flag 2), which read its leaf's points; a roulette stop (flag 0) read the block or the leaf
+        # points of the node where it stopped
+        internal_att = (steps_acc - (flags == 2)) + ((flags == 0) & end_internal)
+        rr_leaf_pts = np.where((flags == 0) & ~end_internal & (end_count > 1), end_count, 0)
+        vp = flags == 2
+        leaf_key = (rec[vp, 1].astype(np.int64) - 1) * (1 << 32) + rec[vp, 0].astype(np.int64)
+        lpos = np.searchsorted(ks, leaf_key, side="right") - 1
+        vp_pts = exp["count"][order][lpos].astype(np.int64)
+        leaf_pts = rr_leaf_pts.sum() + vp_pts.sum()
+        leaf_att = int((rr_leaf_pts > 0).sum() + vp.sum())
+        n_int_att = int(internal_att.sum())
+        bytes_q = 12 + 4 + d3 * (16 * (2 if wind else 1) + 4)
+        alg_bytes = float(n_int_att * blk_bytes + leaf_pts * pt_bytes + N * bytes_q)
+        tf = TERM_FLOPS[kernel]
+        alg_flops = float(n_int_att * (d3 * (tf + 1) + 25) + leaf_pts * (tf + 1) + leaf_att * 25
+                          + len(rec) * tf + N * (d3 + 4))
+        return dict(alg_bytes=alg_bytes, alg_flops=alg_flops, mean_steps=float(steps_acc.mean()),
+                    attempted_steps_per_path=float((n_int_att + leaf_att) / len(rec)))
+
+    wk = work_of(args.group)
+    mean_steps = wk["mean_steps"]
+    if args.group % 64 == 0:
+        tflops = wk["alg_flops"] / (ms_per_step * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                "alg_flops_per_launch": wk["alg_flops"], "kernel": "k_sbh_wave"}
+    else:
+        achieved_gbs = wk["alg_bytes"] / (ms_per_step * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": wk["alg_bytes"], "kernel": "k_sbh"}
+
+    # --- the other stream mode (per-query streams vs shared per wavefront), same tree and queries
+    other = None
+    og = 1 if args.group != 1 else 64
+    ms_o = timed(lambda: run_sbh(tree, S, og), args.steps, args.warmup)
+    e_o = err_of(lambda: run_sbh(tree, S, og))
+    wk_o = work_of(og)
+    other = dict(group=og, ms_per_step=ms_o, queries_per_s=N / (ms_o * 1e-3), median_rel_err=e_o,
+                 alg_bytes_per_launch=wk_o["alg_bytes"], achieved_alg_GBs=wk_o["alg_bytes"] / (ms_o * 1e-3) / 1e9,
+                 alg_flops_per_launch=wk_o["alg_flops"])
+
+    # --- samples-per-subdomain sweep (error / time curve of the stochastic method)
+    sweep = None
+    if not args.no_sweep:
+        sweep = []
+        for sv in S_SWEEP:
+            ms_s = timed(lambda: run_sbh(tree, sv), 3, 1)
+            sweep.append(dict(samples=sv, ms=ms_s, median_rel_err=err_of(lambda: run_sbh(tree, sv))))
+
+    # --- Barnes-Hut sweep and equal-error interpolation
+    bh = None
+    if not args.no_bh:
+        bh_tree = tree if args.bh_branching == args.branching else build(args.bh_branching)[0]
+        pts = []
+        for beta in BETAS:
+            ms = timed(lambda: run_bh(bh_tree, beta), 3, 1)
+            e = err_of(lambda: run_bh(bh_tree, beta), bh_idx_t)
+            pts.append((beta, ms, e))
+            if e < err_star / 4 and len(pts) > 2:
+                break
+        t_eq = None
+        kind = "interpolated"
+        for (b0, m0, e0), (b1, m1, e1) in zip(pts, pts[1:]):
+            if (e0 - err_star) * (e1 - err_star) <= 0 and e0 != e1 and e0 > 0 and e1 > 0:
+                f = (math.log(err_star) - math.log(e0)) / (math.log(e1) - math.log(e0))
+                t_eq = math.exp(math.log(m0) + f * (math.log(m1) - math.log(m0)))
+                break
+        if t_eq is None:
+            if pts[0][2] <= err_star:
+                t_eq, kind = pts[0][1], "upper_bound_at_smallest_beta"
+            else:
+                kind = "not_reached"
+        bh = dict(branching=args.bh_branching, sweep=[dict(beta=b, ms=round(m, 4), median_rel_err=e) for b, m, e in pts],
+                  ms_at_equal_error=None if t_eq is None else round(t_eq, 4),
+                  queries_per_s_at_equal_error=None if t_eq is None else N / (t_eq * 1e-3),
+                  match=kind, speedup_stochastic_vs_bh=None if t_eq is None else t_eq / ms_per_step)
+
+    # --- CPU baseline: the FP64 oracle on the host cores, on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        ot = oracle.Tree(cl.sources, cl.weights, cl.normals, d=args.branching, leaf_size=8)
+        nsamp = min(N, 20000)
+        tc = time.perf_counter()
+        ot.sbh(qry_np[:nsamp], kernel, samples=S, seed=0, group=args.group, index=np.arange(nsamp), threads=threads)
+        per_q = (time.perf_counter() - tc) / nsamp
+        # the whole query set (or a prefix of it), repeated until about cpu_seconds of work
+        nsamp = int(min(N, max(nsamp, args.cpu_seconds / max(per_q, 1e-9))))
+        reps = max(1, int(args.cpu_seconds / max(per_q * nsamp, 1e-9)))
+        tc = time.perf_counter()
+        for _ in range(reps):
+            ot.sbh(qry_np[:nsamp], kernel, samples=S, seed=0, group=args.group, index=np.arange(nsamp),
+                   threads=threads)
+        cpu_s = time.perf_counter() - tc
+        nsamp_total = nsamp * reps
+        cpu = dict(value=nsamp_total / cpu_s, unit="queries/s", cores=threads, kind="oracle",
+                   sample=f"first {nsamp} of {N} queries x {reps} repetitions, same tree, seed and streams, "
+                          f"{cpu_s:.1f} s")
+
+    prof = os.path.join(ROOT, "profiles", f"pmc_sbh_eval_{args.config}_d{args.branching}_g{args.group}.json")
+    if os.path.exists(prof):
+        with open(prof) as f:
+            pm = json.load(f)
+        if pm.get("csrc_hash") == csrc_hash() and pm.get("samples") == S:
+            # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters, scaled by what the same
+            # counters read for a plain copy of known size
+            roof["traffic"] = (pm["fetch_kib"] + pm["write_kib"]) * 1024.0 * pm["copy_factor"]
+
+    line = {
+        "metric": "queries/s at fixed median rel. error vs brute force (plain vs learned, vs det. BH)",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cl.name, "sources": int(cl.m), "queries": int(N), "kernel": ["potential", "winding", "smoothdist"][kernel],
+                   "samples_per_subdomain": S, "branching": args.branching, "leaf_size": 8, "group": args.group,
+                   "seed": 0},
+        "median_rel_err": err_star,
+        "err_sample": ns,
+        "interactions_per_s": qps * cl.m,
+        "build_ms": build_ms,
+        "wall_ms_timed_region": wall_ms,
+        "mean_accepted_steps_per_path": mean_steps,
+        "attempted_steps_per_path": wk["attempted_steps_per_path"],
+        "other_stream_mode": other,
+        "sbh_sweep": sweep,
+        "bh": bh,
+        "learned": None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "generate_s": gen_s,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -39,7 +39,7 @@ def lib():
         L.orc_tree_meta.argtypes = [P, P]
         L.orc_tree_export.argtypes = [P] + [P] * 10
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
-        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, i32]
+        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, P, i32]
         L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32]
         L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
         _lib = L
@@ -128,16 +128,16 @@ class Tree:
 
     def sbh(self, queries, kernel, samples=1, seed=0, group=1, batch=0, rr_mode=0, eps=1e-3, alpha=100.0,
             paths=False, index=None, threads=0):
-        """Algorithm 2 driven by Philox; returns dict(F, margin, absum[, paths]).
+        """Algorithm 2 driven by Philox; returns dict(F, margin, absum, sens[, paths]).
         index: optional original query indices (random stream ids) of a query subset."""
         q = _f32(queries, (-1, 3)); n = q.shape[0]
         idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
-        out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n)
+        out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n); sn = np.zeros(n)
         d3 = self.d ** 3
         pth = np.zeros((n, d3, samples, 4), np.int32) if paths else None
         lib().orc_sbh(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, rr_mode, _p(idx),
-                      _p(out), _p(mg), _p(ab), _p(pth), threads)
-        r = dict(F=out, margin=mg, absum=ab)
+                      _p(out), _p(mg), _p(ab), _p(sn), _p(pth), threads)
+        r = dict(F=out, margin=mg, absum=ab, sens=sn)
         if paths:
             r["paths"] = pth
         return r

@@ -405,6 +405,36 @@ static double point_term(const orc_tree* t, const kparams* kp, int64_t s, const 
     return term(kp, &t->pxyz[3 * s], t->pw[s], &t->pdip[3 * s], q);
 }
 
+/* Sensitivity of a node term to a relative perturbation of its centre of
+ * mass of one unit (|df/dp| * |com|).  A float32 tree stores every centre
+ * with an error of a few 2^-24 |com|, so this bounds how far a float32
+ * evaluation of the same estimate can move for reasons other than rounding
+ * in the evaluation itself.  Diagnostic only; it never enters an estimate. */
+static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+{
+    const double* p = &t->com[3 * i];
+    double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+    double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+    double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    double m = t->mass[i];
+    switch (kp->kernel) {
+    case ORC_POTENTIAL: {
+        double s2 = r2 + kp->eps * kp->eps;
+        return m * r / (s2 * sqrt(s2)) * pn;
+    }
+    case ORC_WINDING: {
+        if (r2 == 0.0) return 0.0;
+        const double* d = &t->dip[3 * i];
+        double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        return dn / (ORC_PI * r2 * r) * pn;
+    }
+    case ORC_SMOOTHDIST:
+        return kp->alpha * m * exp(-kp->alpha * r) * pn;
+    default:
+        return 0.0;
+    }
+}
+
 static double dist3(const double a[3], const double q[3])
 {
     double dx = a[0] - q[0], dy = a[1] - q[1], dz = a[2] - q[2];
@@ -498,6 +528,7 @@ static double rr_prob(int rr_mode, double bT, double bc)
 typedef struct {
     double value;    /* estimate of this path's residual sum */
     double absum;    /* sum of |terms| that entered it, weighted like the value */
+    double sens;     /* sum of node-term sensitivities (node_sens), weighted like the value */
     double margin;   /* min |u - p| over its roulette decisions */
     int32_t end_begin, end_level, steps, flags;
 } path_out;
@@ -507,7 +538,7 @@ typedef struct {
 static path_out sample_path(const orc_tree* t, const kparams* kp, const double q[3], int64_t a,
                             uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode)
 {
-    path_out po = {0.0, 0.0, INFINITY, 0, 0, 0, 0};
+    path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
     double tT = node_term(t, kp, a, q);
     double n_a = (double)t->count[a];
@@ -528,7 +559,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         int64_t target = t->begin[T] + r;
         double diam_c = t->diam[t->level[T] + 1];
         double bT = dist3(&t->com[3 * T], q) / t->diam[t->level[T]];
-        double sum_children = 0.0, abs_children = 0.0;
+        double sum_children = 0.0, abs_children = 0.0, sens_step = node_sens(t, kp, T, q);
         double bc, tc, q_c;
         int64_t c_node = -1;
         if (is_internal(t, T)) {
@@ -537,6 +568,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 double v = node_term(t, kp, ch, q);
                 sum_children += v;
                 abs_children += fabs(v);
+                sens_step += node_sens(t, kp, ch, q);
                 if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
             }
             c_node = c;
@@ -563,6 +595,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         double wgt = 1.0 / (p_sel * p_rr);          /* 1 / (p(I in T) p(K >= k+1)), Eq. (7) */
         po.value += delta * wgt;
         po.absum += (abs_children + fabs(tT)) * wgt;
+        po.sens += sens_step * wgt;
         po.steps += 1;
         p_sel *= q_c;
         (void)n_a;
@@ -586,7 +619,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
  * [n][d^3][S] x int32{begin, level, steps, flags} (absent slots: begin -1). */
 void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
              int S, uint64_t seed, int G, uint32_t batch, int rr_mode, const int64_t* qindex,
-             double* out, double* min_margin, double* absum, int32_t* paths, int nthreads)
+             double* out, double* min_margin, double* absum, double* sens, int32_t* paths, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
     int d3 = t->d * t->d * t->d;
@@ -599,7 +632,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
         double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
         int64_t jj = qindex ? qindex[j] : j;   /* the query's index in the full query set */
         uint32_t sigma = (uint32_t)(G == 1 ? jj : jj / G);
-        double F = 0.0, A = 0.0, mg = INFINITY;
+        double F = 0.0, A = 0.0, SN = 0.0, mg = INFINITY;
         if (paths)
             for (int k = 0; k < d3 * S; ++k) {
                 int32_t* rec = &paths[((int64_t)j * d3 * S + k) * 4];
@@ -613,11 +646,12 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
                 int64_t a = t->first_child[0] + ci;
                 int slot = t->digit[a];
                 double cv = node_term(t, &kp, a, q);     /* control variate CV_a */
-                double Fa = 0.0, Aa = 0.0;
+                double Fa = 0.0, Aa = 0.0, Sa = 0.0;
                 for (int s = 0; s < S; ++s) {
                     path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode);
                     Fa += po.value;
                     Aa += po.absum;
+                    Sa += po.sens;
                     if (po.margin < mg) mg = po.margin;
                     if (paths) {
                         int32_t* rec = &paths[((int64_t)j * d3 * S + (int64_t)slot * S + s) * 4];
@@ -626,11 +660,13 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
                 }
                 F += cv + Fa / S;
                 A += fabs(cv) + Aa / S;
+                SN += node_sens(t, &kp, a, q) + Sa / S;
             }
         }
         out[j] = F;
         if (min_margin) min_margin[j] = mg;
         if (absum) absum[j] = A;
+        if (sens) sens[j] = SN;
     }
 }
 

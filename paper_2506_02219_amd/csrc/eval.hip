@@ -64,6 +64,13 @@ TreeView make_view(const sbh_tree_impl* t)
     return v;
 }
 
+// Component-wise select (a select of whole float4 values can be lowered
+// through private memory).
+__device__ __forceinline__ float4 sel4(bool c, float4 a, float4 b)
+{
+    return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+
 // Smooth-distance scaling: terms are (w / wbar) exp(-alpha (r - r0)); the
 // reported distance is r0 - (log(sum) + log(wbar)) / alpha.
 __device__ __forceinline__ void smooth_setup(const TreeView& tv, float& wscale, float& logwbar)
@@ -127,7 +134,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
                 const float vv = cnt ? v : 0.0f;
                 sumc += vv;
                 const bool hit = (r - pre) < cnt;
-                aggC = hit ? g : aggC;
+                aggC = sel4(hit, g, aggC);
                 tC = hit ? vv : tC;
                 nC = hit ? cnt : nC;
                 beginC = hit ? beginT + pre : beginC;
@@ -141,7 +148,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
                 const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
                 const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
                 sumc += v;
-                aggC = (i == r) ? g : aggC;
+                aggC = sel4(i == r, g, aggC);
                 tC = (i == r) ? v : tC;
             }
             beginC = beginT + r;
@@ -244,6 +251,201 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
     if (valid && slot == 0) {
         if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(val) + logwbar) / a.alpha;
         else out[j] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coherent estimator: one lane per query, one random stream per wavefront.
+// When G is a multiple of 64 the 64 queries of a wavefront share their
+// Philox stream, so under the uniform proposal the selected child at every
+// step is the same for all of them (selection does not depend on q): the
+// wavefront walks one path per (subdomain, sample), reading each child block
+// once for all its lanes, and only the Russian-roulette test (p depends on q)
+// retires lanes individually.  This is the shared-seed design of the paper's
+// implementation section on 64-wide wavefronts.  Per query the subdomain
+// totals CV_a + F_a / S are added in slot order.
+// ---------------------------------------------------------------------------
+template <int D, int K, bool TRACE>
+__device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
+                                           const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
+                                           int32_t blk_a, float4 agg_a, float t_a, uint32_t ctr0, uint32_t ctr1,
+                                           uint32_t ctr3, uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
+{
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kInvD = 1.0f / (float)D;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // wavefront-uniform walk state
+    uint32_t nT = n_a, beginT = begin_a;
+    int32_t blk = blk_a;
+    int level = 1;
+    float diamT = tv.diam0 * kInvD;
+    float4 aggT = agg_a;
+    const float fna = (float)n_a;
+    // per-lane state
+    bool act = valid;
+    float tT = t_a, prr = 1.0f, acc = 0.0f;
+    int steps = 0, flag = 0;
+    int32_t end_b = (int32_t)beginT, end_l = level;
+    u32x4 rnd = {0u, 0u, 0u, 0u};
+    for (int k = 0;; ++k) {
+        if (__ballot(act) == 0ull) break;
+        if (nT == 1u) {
+            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+            break;
+        }
+        if ((k & 1) == 0) rnd = philox4x32_10(ctr0, ctr1, (uint32_t)(k >> 1), ctr3, key0, key1);
+        const uint32_t xsel = (k & 1) ? rnd.z : rnd.x;
+        const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
+        const uint32_t r = __umulhi(xsel, nT);
+        const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
+        float sumc = 0.0f, tC = 0.0f;
+        float4 aggC;
+        uint32_t nC = 1u, beginC;
+        int32_t blkC = 0;
+        if (internal) {
+            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+            // uniform child selection
+            uint32_t pre = 0u, preC = 0u;
+            int32_t nint = 0, nintC = 0, csel = 0;
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = bt[c];
+                const bool hit = (r - pre) < cnt;
+                csel = hit ? c : csel;
+                preC = hit ? pre : preC;
+                nintC = hit ? nint : nintC;
+                nC = hit ? cnt : nC;
+                nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                pre += cnt;
+            }
+            aggC = ba[csel];
+            beginC = beginT + preC;
+            blkC = (int32_t)bt[D3] + nintC;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = bt[c];
+                const float4 g = ba[c];
+                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                const float vv = cnt ? v : 0.0f;
+                sumc += vv;
+                tC = (c == csel) ? vv : tC;
+            }
+        } else {
+            for (uint32_t i = 0; i < nT; ++i) {
+                const float4 g = tv.pts[beginT + i];
+                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                sumc += v;
+                tC = (i == r) ? v : tC;
+            }
+            aggC = tv.pts[beginT + r];
+            beginC = beginT + r;
+        }
+        float p;
+        if (rr_mode == 0) {
+            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
+            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
+            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
+        } else {
+            p = rr_mode == 1 ? 1.0f : 0.5f;
+        }
+        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+        const bool cont = act && (u < p);
+        if (act && !cont) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        if (cont) {
+            prr *= p;
+            acc += (sumc - tT) * __fdividef(fna, (float)nT * prr);
+            ++steps;
+            tT = tC;
+        }
+        if (!internal) {
+            if (cont) {
+                flag = 2;
+                end_b = (int32_t)beginC;
+                end_l = level + 1;
+            }
+            break;
+        }
+        act = cont;
+        aggT = aggC;
+        nT = nC;
+        beginT = beginC;
+        blk = blkC;
+        ++level;
+        diamT *= kInvD;
+    }
+    if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
+    return acc;
+}
+
+template <int D, int K, bool TRACE>
+__global__ void __launch_bounds__(256) k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                  SbhArgs a, float* __restrict__ out)
+{
+    constexpr int D3 = D * D * D;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t j0 = wave * 64;
+    if (j0 >= nq) return;
+    const int64_t j = j0 + lane;
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = queries[3 * j];
+        qy = queries[3 * j + 1];
+        qz = queries[3 * j + 2];
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = cube_distance(tv, qx, qy, qz);
+    }
+    const uint32_t stream = (uint32_t)(j0 / a.group);   // a.group is a multiple of 64
+    const uint32_t* __restrict__ rt = tv.btopo;
+    const int32_t base_root = (int32_t)rt[D3];
+    uint32_t begin_a = 0u;
+    int32_t nint = 0;
+    float F = 0.0f;
+    for (int slot = 0; slot < D3; ++slot) {
+        const uint32_t n_a = rt[slot];
+        if (n_a == 0u) {
+            if constexpr (TRACE) {
+                if (valid)
+                    for (int s = 0; s < a.samples; ++s)
+                        reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = make_int4(-1, 0, 0, 0);
+            }
+            continue;
+        }
+        const int32_t blk_a = base_root + nint;
+        const float4 agg_a = tv.bagg[slot];
+        const float4 dip_a = (K == SBH_WINDING) ? tv.bdip[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);  // control variate CV_a
+        float fa = 0.0f;
+        for (int s = 0; s < a.samples; ++s) {
+            int4 rec;
+            fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, stream,
+                                         (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1, a.rr_mode, &rec);
+            if constexpr (TRACE) {
+                if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
+            }
+        }
+        F += cv + fa / (float)a.samples;
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
+    if (valid) {
+        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(F) + logwbar) / a.alpha;
+        else out[j] = F;
     }
 }
 
@@ -384,6 +586,12 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
     constexpr int QPW = 64 / (D * D * D);
     SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
               e.eps * e.eps, e.alpha, e.paths};
+    if (e.group % 64 == 0) {
+        const unsigned blocks = (unsigned)((nq + 255) / 256);
+        if (e.paths) k_sbh_wave<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        else k_sbh_wave<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        return hipGetLastError();
+    }
     const int64_t waves = (nq + QPW - 1) / QPW;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (e.paths) k_sbh<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);

@@ -7,10 +7,13 @@ Tolerances (stated once, used by every parity test):
     node weight, 2e-5 of the root cube side for centres of mass;
   - estimator and Barnes-Hut values: relative error at most 1e-4, with the
     relative scale floored at 1 for winding numbers (absolute error) and at
-    1/alpha for smooth distances; where the value is a difference of much
-    larger terms, float32 cannot reach 1e-4 and the bound is the float32
-    rounding bound 64 * 2^-24 * (sum of the absolute terms that entered the
-    estimate), which the oracle reports per query;
+    1/alpha for smooth distances.  Where float32 cannot reach 1e-4 the bound
+    is the float32 error bound of the estimate, 2^-24 * (64 * absum + 16 *
+    sens): absum is the sum of the absolute terms that entered the estimate
+    (rounding in the evaluation) and sens the sum of the node terms'
+    sensitivities |df/dp| |com| (float32 storage of the tree's centres of
+    mass), both weighted like the estimate and reported by the oracle per
+    query.  At most 1% of the queries may need this allowance;
   - sampled paths (end node, depth, accepted steps, stop reason): bit-exact,
     except queries whose smallest Russian-roulette margin |u - p| is below
     1e-5 (a float32 / float64 near-tie); at most 1e-5 of the queries may
@@ -77,16 +80,17 @@ def value_scale(ref, kernel, alpha):
     return ref
 
 
-def value_errors(gpu, F, absum, kernel, alpha=100.0):
+def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
     """Return (ok mask, relative error, used-fp32-bound mask) for GPU values vs oracle sums F."""
+    dF = U32 * (64 * absum + (0 if sens is None else 16 * sens))
     if kernel == P.SMOOTHDIST:
         with np.errstate(invalid="ignore", divide="ignore"):
             ref = -np.log(F) / alpha
             # d(-log F / alpha) = -dF / (alpha F)
-            fp32_bound = 64 * U32 * absum / (alpha * np.abs(F))
+            fp32_bound = dF / (alpha * np.abs(F))
     else:
         ref = F
-        fp32_bound = 64 * U32 * absum
+        fp32_bound = dF
     scale = value_scale(ref, kernel, alpha)
     with np.errstate(invalid="ignore", divide="ignore"):
         err = np.abs(gpu - ref) / scale
@@ -94,7 +98,7 @@ def value_errors(gpu, F, absum, kernel, alpha=100.0):
         ok = (err <= bound) | (np.isnan(gpu) & np.isnan(ref))
     # a sum whose float32 sign is not determined (|F| below its rounding bound)
     if kernel == P.SMOOTHDIST:
-        undetermined = np.abs(F) <= 64 * U32 * absum
+        undetermined = np.abs(F) <= dF
         ok |= undetermined
     used_bound = ok & ~((err <= REL_TOL) | (np.isnan(gpu) & np.isnan(ref)))
     return ok, err, used_bound
@@ -120,15 +124,18 @@ def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, ep
                paths=True, index=index, batch=batch)
     near = r["margin"] < NEAR_TIE
     path_bad = np.any(gp != r["paths"], axis=(1, 2, 3))
-    ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha)
+    ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha, r["sens"])
     bad = path_bad | ~ok
     n = queries.shape[0]
     stats = dict(n=n, path_mismatch=int(path_bad.sum()), value_mismatch=int((~ok).sum()),
                  near_ties=int(near.sum()), fp32_bound_used=int(used_bound.sum()),
                  max_rel_err=float(np.nanmax(np.where(ok, err, np.nan))) if ok.any() else float("nan"),
                  median_rel_err=float(np.nanmedian(err)))
-    assert not np.any(bad & ~near), (stats, np.nonzero(bad & ~near)[0][:10])
+    worst = np.nonzero(bad & ~near)[0][:5]
+    assert not np.any(bad & ~near), (stats, [(int(i), float(g[i]), float(r["F"][i]), float(r["absum"][i]),
+                                              float(r["sens"][i])) for i in worst])
     assert bad.sum() <= 1e-5 * n, stats
+    assert used_bound.sum() <= 0.01 * n, stats
     return stats
 
 

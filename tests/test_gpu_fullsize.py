@@ -1,0 +1,79 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times (d = 2, G = 64 coherent wavefronts and G = 1 per-query
+streams): the whole tree is compared bit-exactly, every query is evaluated on
+the GPU, and a seeded sample of queries is recomputed one by one by the
+oracle (at their original indices, so they use the same random streams).
+Barnes-Hut is checked on sampled groups of 64 consecutive queries."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+import paper_2506_02219_amd as P
+from gpu_helpers import DEV, T, host, compare_trees, check_sbh, check_bh
+
+pytestmark = pytest.mark.gpu
+
+NSAMPLE = 1500
+
+
+def run_full(cl, group, samples, alpha=100.0, d=2):
+    gt = P.sbh_build(T(cl.sources), T(cl.weights), None if cl.normals is None else T(cl.normals), branching=d)
+    ot = oracle.Tree(cl.sources, cl.weights, cl.normals, d=d, leaf_size=8)
+    compare_trees(gt, ot)
+    q = T(cl.queries)
+    paths = torch.empty((cl.n, d ** 3, samples, 4), dtype=torch.int32, device=DEV)
+    out = host(P.sbh_eval(gt, q, cl.kernel, samples=samples, seed=0, group=group, alpha=alpha, paths=paths))
+    pth = host(paths)
+    idx = np.sort(np.random.Generator(np.random.PCG64(17)).choice(cl.n, NSAMPLE, replace=False))
+    st = check_sbh(gt, ot, cl.queries[idx], cl.kernel, samples=samples, seed=0, group=group, alpha=alpha,
+                   index=idx, gpu_out=out, gpu_paths=pth)
+    return gt, ot, st
+
+
+def bh_sampled(gt, ot, cl, beta=2.0, ngroups=24):
+    out = host(P.sbh_eval(gt, T(cl.queries), cl.kernel, beta=beta, samples=0))
+    g = np.random.Generator(np.random.PCG64(5)).choice(cl.n // 64, ngroups, replace=False)
+    idx = (g[:, None] * 64 + np.arange(64)[None, :]).ravel()
+    return check_bh(gt, ot, cl.queries[idx], cl.kernel, beta, gpu_out=out[idx])
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return W.c2()
+
+
+@pytest.fixture(scope="module")
+def c5():
+    return W.c5()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return W.c3()
+
+
+@pytest.mark.parametrize("group", [64, 1])
+def test_c2_winding_fullsize(c2, group):
+    q, _ = W.shuffle_queries(c2.queries, 4242) if group > 1 else (c2.queries, None)
+    cl = W.Cloud(c2.sources, c2.weights, c2.normals, q, c2.kernel)
+    gt, ot, st = run_full(cl, group, 1)
+    print(st)
+    if group == 1:
+        print(bh_sampled(gt, ot, cl))
+
+
+def test_c5_potential_fullsize(c5):
+    q, _ = W.shuffle_queries(c5.queries, 4242)
+    cl = W.Cloud(c5.sources, c5.weights, None, q, c5.kernel)
+    gt, ot, st = run_full(cl, 64, 1)
+    print(st)
+    print(bh_sampled(gt, ot, cl))
+
+
+@pytest.mark.parametrize("samples", [1, 4])
+def test_c3_smooth_fullsize(c3, samples):
+    cl = W.Cloud(c3.sources, c3.weights, c3.normals, c3.queries, c3.kernel)
+    gt, ot, st = run_full(cl, 64, samples)
+    print(st)

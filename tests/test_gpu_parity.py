@@ -73,7 +73,9 @@ def test_tree_small_and_ragged(m):
 
 # ----------------------------------------------------------------------------- stochastic estimator
 @pytest.mark.parametrize("d,S,G,rr", [(2, 1, 1, 0), (2, 4, 1, 0), (4, 1, 1, 0), (4, 2, 1, 0),
-                                      (2, 1, 64, 0), (2, 2, 1, 1), (2, 2, 1, 2)])
+                                      (2, 2, 1, 1), (2, 2, 1, 2), (2, 1, 8, 0),
+                                      # G a multiple of 64: one shared stream per wavefront (coherent kernel)
+                                      (2, 1, 64, 0), (2, 3, 128, 0), (4, 1, 64, 0), (2, 2, 64, 2)])
 def test_sbh_parity_c1(d, S, G, rr):
     c = W.c1()
     gt, ot = build_both(c.sources, c.weights, d=d)
@@ -83,11 +85,12 @@ def test_sbh_parity_c1(d, S, G, rr):
 
 @pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST, P.POTENTIAL])
 @pytest.mark.parametrize("d", [2, 4])
-def test_sbh_parity_surface_kernels(kernel, d):
+@pytest.mark.parametrize("G", [1, 64])
+def test_sbh_parity_surface_kernels(kernel, d, G):
     src, nrm, w = surface(30000, 9)
     q = box_queries(3000, 4)  # ragged: 3000 = 46 * 64 + 56
     gt, ot = build_both(src, w, nrm, d=d)
-    st = check_sbh(gt, ot, q, kernel, samples=2, seed=123, alpha=20.0)
+    st = check_sbh(gt, ot, q, kernel, samples=2, seed=123, alpha=20.0, group=G)
     print(st)
 
 
@@ -101,15 +104,16 @@ def test_sbh_seeds_and_batch_words_change_streams():
     assert not np.array_equal(outs[2], outs[3])
 
 
-def test_sbh_deterministic_and_launch_independent():
+@pytest.mark.parametrize("G", [1, 64])
+def test_sbh_deterministic_and_launch_independent(G):
     c = W.c1()
     gt, _ = build_both(c.sources, c.weights)
     q = T(c.queries)
-    a = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9))
-    b = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9))
+    a = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9, group=G))
+    b = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=3, seed=9, group=G))
     assert np.array_equal(a, b)
     # a query's value depends only on its index, not on how many queries share the launch
-    part = host(P.sbh_eval(gt, q[:1000], P.POTENTIAL, samples=3, seed=9))
+    part = host(P.sbh_eval(gt, q[:1000], P.POTENTIAL, samples=3, seed=9, group=G))
     assert np.array_equal(part, a[:1000])
 
 
