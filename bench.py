@@ -322,7 +322,7 @@ def main():
         if pm.get("csrc_hash") == csrc_hash() and pm.get("samples") == S:
             # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters, scaled by what the same
             # counters read for a plain copy of known size
-            roof["traffic"] = (pm["fetch_kib"] + pm["write_kib"]) * 1024.0 * pm["copy_factor"]
+            roof["traffic"] = (pm["fetch_kib"] * pm["fetch_factor"] + pm["write_kib"] * pm["write_factor"]) * 1024.0
 
     line = {
         "metric": "queries/s at fixed median rel. error vs brute force (plain vs learned, vs det. BH)",

@@ -114,45 +114,36 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
         const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
         const uint32_t r = __umulhi(xsel, nT);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
-        float sumc = 0.0f, tC = 0.0f;
-        float4 aggC = zero4;
-        uint32_t nC = 1u, beginC = beginT;
+        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+        const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+        float4 aggC;
+        uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
+        int csel = 0;
         if (internal) {
-            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
-            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
-            const int32_t base = (int32_t)bt[D3];
-            uint32_t pre = 0u;
-            int32_t nint = 0;
+            // child selection from the point counts alone
+            uint32_t pre = 0u, preC = 0u;
+            int32_t nint = 0, nintC = 0;
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
                 const uint32_t cnt = bt[c];
-                const float4 g = ba[c];
-                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                const float vv = cnt ? v : 0.0f;
-                sumc += vv;
                 const bool hit = (r - pre) < cnt;
-                aggC = sel4(hit, g, aggC);
-                tC = hit ? vv : tC;
+                csel = hit ? c : csel;
+                preC = hit ? pre : preC;
+                nintC = hit ? nint : nintC;
                 nC = hit ? cnt : nC;
-                beginC = hit ? beginT + pre : beginC;
-                blkC = hit ? base + nint : blkC;
                 nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
                 pre += cnt;
             }
+            aggC = ba[csel];
+            beginC = beginT + preC;
+            blkC = (int32_t)bt[D3] + nintC;
         } else {
-            for (uint32_t i = 0; i < nT; ++i) {
-                const float4 g = tv.pts[beginT + i];
-                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
-                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                sumc += v;
-                aggC = sel4(i == r, g, aggC);
-                tC = (i == r) ? v : tC;
-            }
+            aggC = tv.pts[beginT + r];
             beginC = beginT + r;
         }
+        // roulette first (Eq. (5)); a lane that stops never reads the rest of the block
         float p;
         if (rr_mode == 0) {
             const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
@@ -167,6 +158,28 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
         if (u >= p) {
             flag = 0;
             break;
+        }
+        // contribution swap, Eq. (6)
+        float sumc = 0.0f, tC = 0.0f;
+        if (internal) {
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = bt[c];
+                const float4 g = ba[c];
+                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                const float vv = cnt ? v : 0.0f;
+                sumc += vv;
+                tC = (c == csel) ? vv : tC;
+            }
+        } else {
+            for (uint32_t i = 0; i < nT; ++i) {
+                const float4 g = tv.pts[beginT + i];
+                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
+                sumc += v;
+                tC = (i == r) ? v : tC;
+            }
         }
         prr *= p;
         acc += (sumc - tT) * __fdividef(fna, (float)nT * prr);
@@ -299,17 +312,17 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
         const uint32_t r = __umulhi(xsel, nT);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
-        float sumc = 0.0f, tC = 0.0f;
+        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+        const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
         float4 aggC;
         uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
+        int csel = 0;
         if (internal) {
-            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
-            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
-            // uniform child selection
+            // uniform child selection from the point counts alone
             uint32_t pre = 0u, preC = 0u;
-            int32_t nint = 0, nintC = 0, csel = 0;
+            int32_t nint = 0, nintC = 0;
             for (int c = 0; c < D3; ++c) {
                 const uint32_t cnt = bt[c];
                 const bool hit = (r - pre) < cnt;
@@ -323,6 +336,32 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             aggC = ba[csel];
             beginC = beginT + preC;
             blkC = (int32_t)bt[D3] + nintC;
+        } else {
+            aggC = tv.pts[beginT + r];
+            beginC = beginT + r;
+        }
+        // roulette first (Eq. (5)): the swap is only needed by lanes that continue
+        float p;
+        if (rr_mode == 0) {
+            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
+            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
+            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
+        } else {
+            p = rr_mode == 1 ? 1.0f : 0.5f;
+        }
+        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+        const bool cont = act && (u < p);
+        if (act && !cont) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        if (__ballot(cont) == 0ull) break;
+        // contribution swap, Eq. (6)
+        float sumc = 0.0f, tC = 0.0f;
+        if (internal) {
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
                 const uint32_t cnt = bt[c];
@@ -341,25 +380,6 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 sumc += v;
                 tC = (i == r) ? v : tC;
             }
-            aggC = tv.pts[beginT + r];
-            beginC = beginT + r;
-        }
-        float p;
-        if (rr_mode == 0) {
-            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
-            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
-            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
-            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
-        } else {
-            p = rr_mode == 1 ? 1.0f : 0.5f;
-        }
-        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
-        const bool cont = act && (u < p);
-        if (act && !cont) {
-            flag = 0;
-            end_b = (int32_t)beginT;
-            end_l = level;
         }
         if (cont) {
             prr *= p;
@@ -388,7 +408,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
 }
 
 template <int D, int K, bool TRACE>
-__global__ void __launch_bounds__(256) k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq,
                                                   SbhArgs a, float* __restrict__ out)
 {
     constexpr int D3 = D * D * D;
