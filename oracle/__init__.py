@@ -39,9 +39,18 @@ def lib():
         L.orc_tree_meta.argtypes = [P, P]
         L.orc_tree_export.argtypes = [P] + [P] * 10
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
-        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, P, i32]
-        L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32]
+        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, P, P, i32]
+        L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, P, i32]
         L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
+        L.orc_mlp_nparam.restype = i32
+        L.orc_f16_round.argtypes = [C.c_float]
+        L.orc_f16_round.restype = C.c_float
+        L.orc_mlp_features.argtypes = [P, P, P, P, i64, P]
+        L.orc_mlp_forward.argtypes = [P, P, i64, i32, P]
+        L.orc_mlp_loss_grad.argtypes = [P, P, P, P, i64, i32, P]
+        L.orc_mlp_loss_grad.restype = f64
+        L.orc_child_targets.argtypes = [P, P, P, i64, i32, f64, f64, P, P]
+        L.orc_mlp_pairs.argtypes = [P, i64, u64, i32, P, P]
         _lib = L
     return _lib
 
@@ -127,29 +136,91 @@ class Tree:
         return out, mg, vis
 
     def sbh(self, queries, kernel, samples=1, seed=0, group=1, batch=0, rr_mode=0, eps=1e-3, alpha=100.0,
-            paths=False, index=None, threads=0):
+            paths=False, index=None, params=None, threads=0):
         """Algorithm 2 driven by Philox; returns dict(F, margin, absum, sens[, paths]).
         index: optional original query indices (random stream ids) of a query subset."""
         q = _f32(queries, (-1, 3)); n = q.shape[0]
         idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
+        prm = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
         out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n); sn = np.zeros(n)
         d3 = self.d ** 3
         pth = np.zeros((n, d3, samples, 4), np.int32) if paths else None
-        lib().orc_sbh(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, rr_mode, _p(idx),
+        lib().orc_sbh(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, rr_mode, _p(idx), _p(prm),
                       _p(out), _p(mg), _p(ab), _p(sn), _p(pth), threads)
         r = dict(F=out, margin=mg, absum=ab, sens=sn)
         if paths:
             r["paths"] = pth
         return r
 
-    def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, threads=0):
-        """Exact expectation of the one-sample estimator (Theorem 1)."""
+    def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, params=None, threads=0):
+        """Exact expectation of the one-sample estimator (Theorem 1), optionally with the learned proposal."""
         q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
-        lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(out), threads)
+        prm = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(prm), _p(out), threads)
         return out
+
+    def mlp_features(self, nodes, n_a, queries):
+        """Proposal features of (node, query) pairs; n_a = point count of each pair's subdomain."""
+        nd = np.ascontiguousarray(nodes, np.int64); na = np.ascontiguousarray(n_a, np.int64)
+        q = _f32(queries, (-1, 3)); out = np.zeros((len(nd), 8), np.float32)
+        lib().orc_mlp_features(self._h, _p(nd), _p(na), _p(q), len(nd), _p(out))
+        return out
+
+    def mlp_pairs(self, nq, seed=0, lmax=None):
+        """Training (query, node) pairs along uniform paths: node [nq, d^3, lmax] (-1 = none), n_a."""
+        lmax = self.max_level if lmax is None else lmax
+        d3 = self.d ** 3
+        nd = np.zeros((nq, d3, lmax), np.int64); na = np.zeros((nq, d3, lmax), np.int64)
+        lib().orc_mlp_pairs(self._h, nq, seed, lmax, _p(nd), _p(na))
+        return nd, na
+
+    def training_set(self, queries, kernel, seed=0, lmax=None, eps=1e-3, alpha=100.0):
+        """Features, targets and child counts of every training pair (rows [nq*d^3*lmax], valid mask)."""
+        q = _f32(queries, (-1, 3))
+        nd, na = self.mlp_pairs(q.shape[0], seed, lmax)
+        rows = nd.reshape(-1)
+        valid = rows >= 0
+        qi = np.repeat(np.arange(q.shape[0]), nd.shape[1] * nd.shape[2])
+        X = np.zeros((rows.size, 8), np.float32); Tg = np.zeros_like(X); Cn = np.zeros_like(X)
+        if valid.any():
+            X[valid] = self.mlp_features(rows[valid], na.reshape(-1)[valid], q[qi[valid]])
+            Tg[valid], Cn[valid] = self.child_targets(rows[valid], q[qi[valid]], kernel, eps, alpha)
+        return X, Tg, Cn, valid
+
+    def child_targets(self, nodes, queries, kernel, eps=1e-3, alpha=100.0):
+        """Normalised per-slot residual targets and child counts for internal nodes."""
+        nd = np.ascontiguousarray(nodes, np.int64); q = _f32(queries, (-1, 3))
+        tg = np.zeros((len(nd), 8), np.float32); cn = np.zeros((len(nd), 8), np.float32)
+        lib().orc_child_targets(self._h, _p(nd), _p(q), len(nd), kernel, eps, alpha, _p(tg), _p(cn))
+        return tg, cn
 
     def refine_all(self, queries, kernel, eps=1e-3, alpha=100.0):
         """Telescoping sum with every node refined (Eqs. (3)-(4))."""
         q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
         lib().orc_refine_all(self._h, _p(q), q.shape[0], kernel, eps, alpha, _p(out))
         return out
+
+
+MLP_NPARAM = 1608
+MLP_LAMBDA = 0.125
+
+
+def f16_round(x):
+    return float(lib().orc_f16_round(float(x)))
+
+
+def mlp_forward(params, x, mode=1):
+    """Logits of the proposal network for feature rows x [n, 8] (mode 1: binary16 emulation)."""
+    prm = np.ascontiguousarray(params, np.float32); xx = _f32(x, (-1, 8))
+    z = np.zeros((xx.shape[0], 8))
+    lib().orc_mlp_forward(_p(prm), _p(xx), xx.shape[0], mode, _p(z))
+    return z
+
+
+def mlp_loss_grad(params, x, targets, counts, mode=0):
+    """Mean soft cross-entropy and its float64 gradient."""
+    prm = np.ascontiguousarray(params, np.float32); xx = _f32(x, (-1, 8))
+    tg = _f32(targets, (-1, 8)); cn = _f32(counts, (-1, 8))
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().orc_mlp_loss_grad(_p(prm), _p(xx), _p(tg), _p(cn), xx.shape[0], mode, _p(g))
+    return loss, g

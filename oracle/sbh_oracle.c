@@ -509,6 +509,162 @@ void orc_bh(const orc_tree* t, const float* qry, int64_t n, int kernel, double e
     }
 }
 
+/* ======================================================================== */
+/* Learned child proposal (importance sampling of the path index, which     */
+/* Section 3.3 leaves open).  A node-level MLP 8 -> 32 -> 32 -> 8 (ReLU)     */
+/* maps features of (node, query) to one logit per child slot (d = 2).       */
+/* Proposal: pi_c = n_c exp(z_c) / sum n exp(z) over non-empty slots (so a   */
+/* zero network is the uniform path index), mixed defensively:              */
+/*   q_c = (1 - LAMBDA) pi_c + LAMBDA n_c / n_T,                             */
+/* so every non-empty child keeps q_c > 0 and Theorem 1 still applies.      */
+/* Parameters (float32, 1608): W1[32][8] b1[32] W2[32][32] b2[32]            */
+/* W3[8][32] b3[8].  Inference uses the weight matrices rounded to binary16  */
+/* and binary16 inputs and hidden activations with float32 sums, which this */
+/* oracle emulates (mode 1); mode 0 is plain float64 for gradient checks.   */
+/* ======================================================================== */
+#define MLP_IN 8
+#define MLP_H 32
+#define MLP_OUT 8
+#define MLP_OFF_W1 0
+#define MLP_OFF_B1 (MLP_OFF_W1 + MLP_H * MLP_IN)
+#define MLP_OFF_W2 (MLP_OFF_B1 + MLP_H)
+#define MLP_OFF_B2 (MLP_OFF_W2 + MLP_H * MLP_H)
+#define MLP_OFF_W3 (MLP_OFF_B2 + MLP_H)
+#define MLP_OFF_B3 (MLP_OFF_W3 + MLP_OUT * MLP_H)
+#define MLP_NPARAM (MLP_OFF_B3 + MLP_OUT)
+#define MLP_LAMBDA 0.125
+
+int orc_mlp_nparam(void) { return MLP_NPARAM; }
+
+/* nearest IEEE binary16 value of x (ties to even), as a float; overflow to inf */
+static float f16_round(float x)
+{
+    if (!(x == x) || x == 0.0f || isinf(x)) return x;
+    int e;
+    double m = frexp((double)x, &e);   /* x = m 2^e, 0.5 <= |m| < 1 */
+    (void)m;
+    int ex = e - 1;                    /* x = m' 2^ex, 1 <= |m'| < 2 */
+    if (ex < -14) ex = -14;            /* subnormal range: fixed quantum 2^-24 */
+    double quantum = ldexp(1.0, ex - 10);
+    double r = nearbyint((double)x / quantum) * quantum;   /* default rounding: to nearest even */
+    if (fabs(r) > 65504.0) return x > 0 ? INFINITY : -INFINITY;
+    return (float)r;
+}
+
+float orc_f16_round(float x) { return f16_round(x); }
+
+/* Features of (node T, query q), float32 with a fixed operation order:
+ *   cell centre cen = lo + (2 i + 1) h (i the integer cell index at T's level,
+ *   h half the cell side), r = (q - cen) / h, rho = |r|:
+ *   f0..2 = r / (1 + rho), f3 = rho / (1 + rho), f4 = level / max_level,
+ *   f5 = n_T / n_a (a = the path's subdomain), f6 = |sum w n| / sum w (0 without
+ *   normals), f7 = min(rho, 16) / 16. */
+static void mlp_features(const orc_tree* t, int64_t T, int64_t n_a, const float qf[3], float f[8])
+{
+    int lev = t->level[T];
+    int oct = t->bits * lev / 3;             /* octree levels of the cell */
+    uint64_t pre = oct > 0 ? (t->codes[t->begin[T]] >> (60 - 3 * oct)) : 0;
+    uint32_t ix = 0, iy = 0, iz = 0;
+    for (int k = 0; k < oct; ++k) {
+        ix |= (uint32_t)((pre >> (3 * k)) & 1u) << k;
+        iy |= (uint32_t)((pre >> (3 * k + 1)) & 1u) << k;
+        iz |= (uint32_t)((pre >> (3 * k + 2)) & 1u) << k;
+    }
+    float h = ldexpf(t->side, -oct - 1);
+    float cx = t->lo[0] + (float)(2u * ix + 1u) * h;
+    float cy = t->lo[1] + (float)(2u * iy + 1u) * h;
+    float cz = t->lo[2] + (float)(2u * iz + 1u) * h;
+    float rx = (qf[0] - cx) / h, ry = (qf[1] - cy) / h, rz = (qf[2] - cz) / h;
+    float rho = sqrtf((rx * rx + ry * ry) + rz * rz);
+    float den = 1.0f + rho;
+    f[0] = rx / den;
+    f[1] = ry / den;
+    f[2] = rz / den;
+    f[3] = rho / den;
+    f[4] = (float)lev / (float)t->max_level;
+    f[5] = (float)t->count[T] / (float)n_a;
+    if (t->has_normals) {
+        float dx = (float)t->dip[3 * T], dy = (float)t->dip[3 * T + 1], dz = (float)t->dip[3 * T + 2];
+        f[6] = sqrtf((dx * dx + dy * dy) + dz * dz) / (float)t->mass[T];
+    } else {
+        f[6] = 0.0f;
+    }
+    f[7] = (rho < 16.0f ? rho : 16.0f) / 16.0f;
+}
+
+/* Logits.  mode 1: binary16 weights / inputs / hidden activations, each dot
+ * product summed exactly and rounded once to float32, bias added in float32;
+ * mode 0: float64 throughout.  Optional outputs keep the activations. */
+static void mlp_forward(const float* prm, const float x[8], int mode, double z[8], double h1o[32], double h2o[32])
+{
+    double xin[MLP_IN], h1[MLP_H], h2[MLP_H];
+    for (int k = 0; k < MLP_IN; ++k) xin[k] = mode ? f16_round(x[k]) : (double)x[k];
+    for (int n = 0; n < MLP_H; ++n) {
+        double s = 0.0;
+        for (int k = 0; k < MLP_IN; ++k) {
+            double w = mode ? f16_round(prm[MLP_OFF_W1 + n * MLP_IN + k]) : prm[MLP_OFF_W1 + n * MLP_IN + k];
+            s += w * xin[k];
+        }
+        double a;
+        if (mode) { float af = (float)s; af = af + prm[MLP_OFF_B1 + n]; a = af > 0.0f ? f16_round(af) : 0.0; }
+        else { a = s + prm[MLP_OFF_B1 + n]; a = a > 0.0 ? a : 0.0; }
+        h1[n] = a;
+    }
+    for (int n = 0; n < MLP_H; ++n) {
+        double s = 0.0;
+        for (int k = 0; k < MLP_H; ++k) {
+            double w = mode ? f16_round(prm[MLP_OFF_W2 + n * MLP_H + k]) : prm[MLP_OFF_W2 + n * MLP_H + k];
+            s += w * h1[k];
+        }
+        double a;
+        if (mode) { float af = (float)s; af = af + prm[MLP_OFF_B2 + n]; a = af > 0.0f ? f16_round(af) : 0.0; }
+        else { a = s + prm[MLP_OFF_B2 + n]; a = a > 0.0 ? a : 0.0; }
+        h2[n] = a;
+    }
+    for (int c = 0; c < MLP_OUT; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < MLP_H; ++k) {
+            double w = mode ? f16_round(prm[MLP_OFF_W3 + c * MLP_H + k]) : prm[MLP_OFF_W3 + c * MLP_H + k];
+            s += w * h2[k];
+        }
+        if (mode) { float af = (float)s; af = af + prm[MLP_OFF_B3 + c]; z[c] = af; }
+        else z[c] = s + prm[MLP_OFF_B3 + c];
+    }
+    if (h1o) for (int n = 0; n < MLP_H; ++n) h1o[n] = h1[n];
+    if (h2o) for (int n = 0; n < MLP_H; ++n) h2o[n] = h2[n];
+}
+
+/* softmax with the count prior over the non-empty slots */
+static void prior_softmax(const double z[8], const double cnt[8], double pi[8])
+{
+    double zmax = -INFINITY, s = 0.0;
+    for (int c = 0; c < MLP_OUT; ++c) if (cnt[c] > 0 && z[c] > zmax) zmax = z[c];
+    for (int c = 0; c < MLP_OUT; ++c) { pi[c] = cnt[c] > 0 ? cnt[c] * exp(z[c] - zmax) : 0.0; s += pi[c]; }
+    for (int c = 0; c < MLP_OUT; ++c) pi[c] /= s;
+}
+
+/* q_c for the (up to 8) children of internal node T */
+static void learned_q(const orc_tree* t, const float* prm, int64_t T, int64_t n_a, const double q[3], double qc[8],
+                      int slot_of_child[8], int* nk)
+{
+    float qf[3] = {(float)q[0], (float)q[1], (float)q[2]};
+    float f[8];
+    double z[8], cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8];
+    mlp_features(t, T, n_a, qf, f);
+    mlp_forward(prm, f, 1, z, NULL, NULL);
+    *nk = t->nchild[T];
+    for (int i = 0; i < t->nchild[T]; ++i) {
+        int64_t ch = t->first_child[T] + i;
+        slot_of_child[i] = t->digit[ch];
+        cnt[t->digit[ch]] = (double)t->count[ch];
+    }
+    prior_softmax(z, cnt, pi);
+    for (int i = 0; i < t->nchild[T]; ++i) {
+        int s = slot_of_child[i];
+        qc[i] = (1.0 - MLP_LAMBDA) * pi[s] + MLP_LAMBDA * cnt[s] / (double)t->count[T];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Stochastic path estimator: Eqs. (5)-(7), Section 3.3.1, Algorithm 2.       */
 /* ------------------------------------------------------------------------ */
@@ -536,7 +692,8 @@ typedef struct {
 /* One path sample rooted at subdomain node `a` (Algorithm 2, inner loop).
  * counter = (sigma, a_slot*S + s, step/2, batch), key = (seed lo, seed hi). */
 static path_out sample_path(const orc_tree* t, const kparams* kp, const double q[3], int64_t a,
-                            uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode)
+                            uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode,
+                            const float* prm)
 {
     path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
@@ -571,10 +728,26 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 sens_step += node_sens(t, kp, ch, q);
                 if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
             }
+            q_c = (double)t->count[c] / (double)nT;
+            if (prm) {
+                /* learned proposal: inverse-CDF selection over the slots with a 24-bit uniform */
+                double qv[8];
+                int slots[8], nk;
+                learned_q(t, prm, T, (int64_t)n_a, q, qv, slots, &nk);
+                double u_sel = (double)(x_sel >> 8) * (1.0 / 16777216.0), cum = 0.0;
+                int ci = nk - 1;
+                for (int i = 0; i < nk; ++i) {
+                    cum += qv[i];
+                    double mg = fabs(u_sel - cum);
+                    if (i < nk - 1 && mg < po.margin) po.margin = mg;
+                    if (u_sel < cum) { ci = i; break; }
+                }
+                c = t->first_child[T] + ci;
+                q_c = qv[ci];
+            }
             c_node = c;
             bc = dist3(&t->com[3 * c], q) / diam_c;
             tc = node_term(t, kp, c, q);
-            q_c = (double)t->count[c] / (double)nT;
         } else {
             /* leaf with several points: the points are virtual children */
             for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) {
@@ -618,7 +791,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
  * roulette margin, conditioning sum, and per-path records laid out
  * [n][d^3][S] x int32{begin, level, steps, flags} (absent slots: begin -1). */
 void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
-             int S, uint64_t seed, int G, uint32_t batch, int rr_mode, const int64_t* qindex,
+             int S, uint64_t seed, int G, uint32_t batch, int rr_mode, const int64_t* qindex, const float* prm,
              double* out, double* min_margin, double* absum, double* sens, int32_t* paths, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
@@ -648,7 +821,8 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
                 double cv = node_term(t, &kp, a, q);     /* control variate CV_a */
                 double Fa = 0.0, Aa = 0.0, Sa = 0.0;
                 for (int s = 0; s < S; ++s) {
-                    path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode);
+                    path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode,
+                                              prm);
                     Fa += po.value;
                     Aa += po.absum;
                     Sa += po.sens;
@@ -679,7 +853,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
 /* V(a).  Exponential in nothing: one visit per node per query.             */
 /* ------------------------------------------------------------------------ */
 static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3], int64_t T, double tT,
-                         double ps, double pr, int rr_mode)
+                         double ps, double pr, int rr_mode, const float* prm, int64_t n_a)
 {
     int64_t nT = t->count[T];
     if (nT == 1) return 0.0;
@@ -691,11 +865,14 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
             sum += node_term(t, kp, ch, q);
         double delta = sum - tT;
+        double qv[8];
+        int slots[8], nk;
+        if (prm) learned_q(t, prm, T, n_a, q, qv, slots, &nk);
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
-            double qc = (double)t->count[ch] / (double)nT;
+            double qc = prm ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
             double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / diam_c);
             double tc = node_term(t, kp, ch, q);
-            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode));
+            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prm, n_a));
         }
     } else {
         double sum = 0.0;
@@ -711,7 +888,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
 }
 
 void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
-                    int rr_mode, double* out, int nthreads)
+                    int rr_mode, const float* prm, double* out, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
 #ifdef _OPENMP
@@ -725,7 +902,7 @@ void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, 
         for (int ci = 0; ci < t->nchild[0]; ++ci) {
             int64_t a = t->first_child[0] + ci;
             double cv = node_term(t, &kp, a, q);
-            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode);
+            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode, prm, t->count[a]);
         }
         out[j] = F;
     }
@@ -757,5 +934,136 @@ void orc_refine_all(const orc_tree* t, const float* qry, int64_t n, int kernel, 
             F += sum - node_term(t, &kp, T, q);
         }
         out[j] = F;
+    }
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Learned-proposal training support (batch entry points).                  */
+/* ------------------------------------------------------------------------ */
+
+/* Features for (node, query) pairs; n_a = count of each pair's subdomain. */
+void orc_mlp_features(const orc_tree* t, const int64_t* node, const int64_t* n_a, const float* qry, int64_t n,
+                      float* out)
+{
+    for (int64_t i = 0; i < n; ++i) mlp_features(t, node[i], n_a[i], &qry[3 * i], &out[8 * i]);
+}
+
+/* Logits for a batch of feature rows (mode 1 binary16 emulation, 0 float64). */
+void orc_mlp_forward(const float* prm, const float* x, int64_t n, int mode, double* z)
+{
+    for (int64_t i = 0; i < n; ++i) mlp_forward(prm, &x[8 * i], mode, &z[8 * i], NULL, NULL);
+}
+
+/* Mean soft cross-entropy  L = -(1/n) sum_i sum_c t_ic log pi_ic  over the
+ * non-empty slots (cnt > 0) and its gradient with respect to the float32
+ * parameters (float64 back-propagation through the forward of `mode`). */
+double orc_mlp_loss_grad(const float* prm, const float* x, const float* tgt, const float* cnt, int64_t n, int mode,
+                         double* grad)
+{
+    for (int k = 0; k < MLP_NPARAM; ++k) grad[k] = 0.0;
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double z[8], h1[32], h2[32], pi[8], c8[8], dz[8], dh2[32], dh1[32], xin[8];
+        mlp_forward(prm, &x[8 * i], mode, z, h1, h2);
+        for (int c = 0; c < 8; ++c) c8[c] = cnt[8 * i + c];
+        prior_softmax(z, c8, pi);
+        for (int c = 0; c < 8; ++c) {
+            double tc = tgt[8 * i + c];
+            if (c8[c] > 0) {
+                if (tc > 0) loss -= tc * log(pi[c]);
+                dz[c] = (pi[c] - tc) / (double)n;
+            } else {
+                dz[c] = 0.0;
+            }
+        }
+        for (int k = 0; k < 8; ++k) xin[k] = mode ? f16_round(x[8 * i + k]) : (double)x[8 * i + k];
+#define WV(off) (mode ? (double)f16_round(prm[off]) : (double)prm[off])
+        for (int k = 0; k < 32; ++k) {
+            double sacc = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                grad[MLP_OFF_W3 + c * 32 + k] += dz[c] * h2[k];
+                sacc += dz[c] * WV(MLP_OFF_W3 + c * 32 + k);
+            }
+            dh2[k] = h2[k] > 0 ? sacc : 0.0;
+        }
+        for (int c = 0; c < 8; ++c) grad[MLP_OFF_B3 + c] += dz[c];
+        for (int k = 0; k < 32; ++k) {
+            double sacc = 0.0;
+            for (int m = 0; m < 32; ++m) {
+                grad[MLP_OFF_W2 + m * 32 + k] += dh2[m] * h1[k];
+                sacc += dh2[m] * WV(MLP_OFF_W2 + m * 32 + k);
+            }
+            dh1[k] = h1[k] > 0 ? sacc : 0.0;
+        }
+        for (int m = 0; m < 32; ++m) grad[MLP_OFF_B2 + m] += dh2[m];
+        for (int m = 0; m < 32; ++m) {
+            for (int k = 0; k < 8; ++k) grad[MLP_OFF_W1 + m * 8 + k] += dh1[m] * xin[k];
+            grad[MLP_OFF_B1 + m] += dh1[m];
+        }
+#undef WV
+    }
+    return loss / (double)n;
+}
+
+/* Training targets: for internal node `node[i]` and query i, the residual of
+ * every child slot, r_c = |sum_{j in c} f(p_j, q) - f_LOD(c, q)| (brute force
+ * over the child's points), normalised to sum 1 (n_c / n_T when all are 0);
+ * cnt receives the child point counts per slot. */
+void orc_child_targets(const orc_tree* t, const int64_t* node, const float* qry, int64_t n, int kernel, double eps,
+                       double alpha, float* tgt, float* cnt)
+{
+    kparams kp = {kernel, eps, alpha};
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        double q[3] = {qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
+        int64_t T = node[i];
+        double r[8] = {0, 0, 0, 0, 0, 0, 0, 0}, rs = 0.0;
+        for (int c = 0; c < 8; ++c) cnt[8 * i + c] = 0.0f;
+        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+            int s = t->digit[ch];
+            double ex = leaf_exact(t, &kp, ch, q);
+            r[s] = fabs(ex - node_term(t, &kp, ch, q));
+            rs += r[s];
+            cnt[8 * i + s] = (float)t->count[ch];
+        }
+        for (int c = 0; c < 8; ++c)
+            tgt[8 * i + c] = rs > 0 ? (float)(r[c] / rs) : cnt[8 * i + c] / (float)t->count[T];
+    }
+}
+
+/* Training pairs for the proposal network.  For every training query j and
+ * non-empty root child (slot a) a path is walked from a with the uniform
+ * path index, using the Philox stream (j, a, step/2, 0xFFFFFFFF) (the batch
+ * word all ones keeps it apart from estimation streams; word 2*(step&1) of
+ * the block selects), down to a leaf; every internal node on the way is one
+ * (query, node) pair.  Layout [nq][d^3][lmax] with node = -1 for an unused
+ * row; na = the path's subdomain count. */
+void orc_mlp_pairs(const orc_tree* t, int64_t nq, uint64_t seed, int lmax, int64_t* node_out, int64_t* na_out)
+{
+    int d3 = t->d * t->d * t->d;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < nq * d3 * lmax; ++i) { node_out[i] = -1; na_out[i] = 0; }
+    if (!is_internal(t, 0)) return;
+    for (int64_t j = 0; j < nq; ++j) {
+        for (int ci = 0; ci < t->nchild[0]; ++ci) {
+            int64_t a = t->first_child[0] + ci;
+            int slot = t->digit[a];
+            int64_t T = a;
+            for (int k = 0; k < lmax && is_internal(t, T); ++k) {
+                int64_t row = (j * d3 + slot) * lmax + k;
+                node_out[row] = T;
+                na_out[row] = t->count[a];
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)slot, (uint32_t)(k >> 1), 0xFFFFFFFFu}, rnd[4];
+                orc_philox4x32_10(ctr, key, rnd);
+                int64_t r = (int64_t)(((uint64_t)rnd[2 * (k & 1)] * (uint64_t)t->count[T]) >> 32);
+                int64_t target = t->begin[T] + r, c = -1;
+                for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
+                    if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
+                T = c;
+            }
+        }
     }
 }
