@@ -63,7 +63,37 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
+    ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
+    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--train-batch", type=int, default=8192)
+    ap.add_argument("--train-lr", type=float, default=2e-3)
     return ap.parse_args()
+
+
+def _training_surface(seed):
+    import workloads as W
+    pts, _, w, _ = W.star_surface(1 << 22, seed)
+    return np.ascontiguousarray(pts, np.float32), np.ascontiguousarray(w, np.float32)
+
+
+def training_surfaces(seeds):
+    """The held-out training clouds, generated in forked CPU workers (before the GPU is touched)."""
+    import multiprocessing as mp
+    procs = max(1, min(len(seeds), 16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(procs) as pool:
+        return pool.map(_training_surface, seeds)
+
+
+def log_interp(xs, ys, x):
+    """y at x on the piecewise log-log curve through (xs, ys) (xs in any order); None outside."""
+    pts = sorted(zip(xs, ys))
+    for (x0, y0), (x1, y1) in zip(pts, pts[1:]):
+        if x0 <= x <= x1 and x0 > 0 and x1 > x0 and y0 > 0 and y1 > 0:
+            f = (math.log(x) - math.log(x0)) / (math.log(x1) - math.log(x0))
+            return math.exp(math.log(y0) + f * (math.log(y1) - math.log(y0)))
+    return None
 
 
 def rel_errors(v, ref, kernel, alpha=100.0):
@@ -104,6 +134,12 @@ def main():
     cfg = CONFIGS[args.config]
     kernel = cfg["kernel"]
     S = args.samples or cfg["samples"]
+    do_learned = args.config == "c5" and not args.no_learned and args.branching == 2
+    train_clouds, train_gen_s = None, 0.0
+    if do_learned:
+        t0 = time.time()
+        train_clouds = training_surfaces(W.c5_training_seeds()[:args.train_seeds])
+        train_gen_s = time.time() - t0
     t0 = time.time()
     cl = getattr(W, cfg["gen"])()
     gen_s = time.time() - t0
@@ -292,6 +328,66 @@ def main():
                   queries_per_s_at_equal_error=None if t_eq is None else N / (t_eq * 1e-3),
                   match=kind, speedup_stochastic_vs_bh=None if t_eq is None else t_eq / ms_per_step)
 
+    # --- learned proposal: trained on the held-out surfaces, evaluated on this one
+    learned = None
+    if do_learned:
+        from paper_2506_02219_amd import learned as L
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        Xs, Ts, Cs = [], [], []
+        for i, (tp, tw) in enumerate(train_clouds):
+            tt = P.sbh_build(torch.from_numpy(tp).to(dev), torch.from_numpy(tw).to(dev), None, branching=2,
+                             leaf_size=8)
+            r = np.random.Generator(np.random.PCG64(7000 + i))
+            tq = np.zeros((args.train_queries, 3), np.float32)
+            tq[:, :2] = r.uniform(-1.5, 1.5, (args.train_queries, 2))
+            X, Tg, Cn = L.training_rows(tt, torch.from_numpy(tq).to(dev), kernel, seed=8000 + i)
+            Xs.append(X); Ts.append(Tg); Cs.append(Cn)
+            tt.free()
+        X, Tg, Cn = torch.cat(Xs), torch.cat(Ts), torch.cat(Cs)
+        del Xs, Ts, Cs, train_clouds
+        torch.cuda.synchronize()
+        rows_ms = (time.perf_counter() - tl) * 1e3
+        prm = L.init_params(1)
+        loss0 = L.mean_loss(prm, X, Tg, Cn)
+        torch.cuda.synchronize()
+        tt0 = time.perf_counter()
+        losses, _ = L.train(prm, X, Tg, Cn, args.train_steps, args.train_batch, args.train_lr, seed=2)
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - tt0) * 1e3
+        loss1 = L.mean_loss(prm, X, Tg, Cn)
+        lc = losses.cpu().numpy()
+
+        def run_learned(samples, group=1):
+            P.sbh_eval(tree, qry, kernel, samples=samples, seed=0, group=group, out=out, mlp=prm)
+
+        lsweep = []
+        for sv in (1, 2, 4):
+            ms_l = timed(lambda: run_learned(sv), args.steps if sv == 1 else 3, args.warmup if sv == 1 else 1)
+            lsweep.append(dict(samples=sv, ms=ms_l, median_rel_err=err_of(lambda: run_learned(sv))))
+        l1 = lsweep[0]
+        # the plain method's time at the learned method's error, interpolated over its samples sweep
+        t_plain = None
+        if sweep:
+            t_plain = log_interp([p["median_rel_err"] for p in sweep], [p["ms"] for p in sweep], l1["median_rel_err"])
+        # the learned method's time at the plain method's error: interpolated over its own sweep, or
+        # (when one sample already beats it) scaled down by the 1/S law of the variance
+        t_learned = log_interp([p["median_rel_err"] for p in lsweep], [p["ms"] for p in lsweep], err_star)
+        how = "interpolated"
+        if t_learned is None and l1["median_rel_err"] <= err_star:
+            t_learned, how = l1["ms"] * (l1["median_rel_err"] / err_star) ** 2, "extrapolated_1_over_S"
+        learned = dict(
+            train_seeds=args.train_seeds, train_queries_per_surface=args.train_queries, train_rows=int(X.shape[0]),
+            train_steps=args.train_steps, train_batch=args.train_batch, lr=args.train_lr,
+            surface_generation_s=train_gen_s, rows_ms=rows_ms, train_ms=train_ms,
+            loss_untrained=loss0, loss_trained=loss1, loss_first_steps=float(lc[:50].mean()),
+            loss_last_steps=float(lc[-50:].mean()), group=1, sweep=lsweep,
+            plain_ms_at_learned_error=t_plain,
+            speedup_learned_vs_plain_at_learned_error=None if t_plain is None else t_plain / l1["ms"],
+            learned_ms_at_plain_error=t_learned, learned_match=how if t_learned is not None else "not_reached",
+            queries_per_s_at_plain_error=None if t_learned is None else N / (t_learned * 1e-3))
+        del X, Tg, Cn
+
     # --- CPU baseline: the FP64 oracle on the host cores, on a bounded sample
     cpu = None
     if not args.no_cpu:
@@ -350,7 +446,7 @@ def main():
         "other_stream_mode": other,
         "sbh_sweep": sweep,
         "bh": bh,
-        "learned": None,
+        "learned": learned,
         "roofline": roof,
         "cpu_baseline": cpu,
         "generate_s": gen_s,

@@ -67,12 +67,14 @@ typedef struct sbh_eval_opts {
     int32_t rr_mode;     /* Russian roulette: 0 = Eq. (5) (default), 1 = p = 1 (none),
                             2 = p = 1/2 (the two comparisons of the supplement) */
     int32_t proposal;    /* child-selection distribution: 0 = uniform path index
-                            (the paper's); other values return SBH_EUNSUPPORTED */
+                            (the paper's, default); 1 = the learned proposal of
+                            sbh_mlp_* with parameters opts->mlp (branching 2 only) */
     uint32_t batch;      /* fourth Philox counter word, for independent batches; default 0 */
     int32_t* paths;      /* optional DEVICE [nq][d^3][samples][4] int32 records of every
                             sampled path: {end begin, end level, accepted steps, stop
                             reason (0 roulette, 1 one-point node, 2 virtual point)};
                             subdomain slots that are empty hold begin = -1.  NULL = off. */
+    const float* mlp;    /* DEVICE [SBH_MLP_NPARAM] network parameters for proposal 1; default NULL */
 } sbh_eval_opts;
 
 typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */
@@ -82,6 +84,15 @@ typedef struct sbh_tree_desc {      /* host copy of a tree's sizes */
     int32_t depth, branching, leaf_size, max_level, has_normals;
     float lo[3], side, inv_side;    /* root cube [lo, lo + side]^3 and fl32(1/side) */
 } sbh_tree_desc;
+
+/* Learned proposal network: 8 features -> 32 -> 32 -> 8 logits with ReLU.
+ * Parameters are float32 [SBH_MLP_NPARAM] = W1[32][8] b1[32] W2[32][32] b2[32]
+ * W3[8][32] b3[8] (row-major, out x in); the kernels evaluate it with binary16
+ * weights, inputs and hidden activations and float32 accumulation (MFMA).
+ * Gradient buffers hold SBH_MLP_GRAD_SIZE floats: the gradient, then the
+ * mean loss, then the number of rows that entered the mean. */
+#define SBH_MLP_NPARAM 1608
+#define SBH_MLP_GRAD_SIZE 1610
 
 /* Fill option structs with the defaults documented above. */
 void sbh_build_opts_default(sbh_build_opts* opts /*host*/);
@@ -123,8 +134,21 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   queries [nq][3]; out [nq] float32 (smooth distance for SBH_SMOOTHDIST).
  *   nq = 0 is a no-op.  Errors: SBH_EINVAL (null pointers, nq < 0, bad
  *   kernel, samples < 0, beta <= 0 or NaN with samples == 0, group < 1,
- *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals),
- *   SBH_EUNSUPPORTED (proposal != 0), SBH_EHIP.
+ *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals, proposal
+ *   not 0 or 1, proposal 1 without opts->mlp), SBH_EUNSUPPORTED (proposal 1
+ *   on a tree with branching 4), SBH_EHIP.
+ *
+ *   Learned proposal (opts->proposal = 1).  Section 3.3 draws the path index
+ *   uniformly; Theorem 1 needs only that every point can be reached, so any
+ *   child distribution q_c > 0 over the non-empty children keeps the
+ *   estimator unbiased when the swap of each step is divided by the product
+ *   of the q's chosen so far (in place of n_T / n_a, Eq. (7)).  At an internal
+ *   node T the network maps the features of (T, q) to logits z_c and
+ *     q_c = (7/8) n_c exp(z_c) / sum_c' n_c' exp(z_c') + (1/8) n_c / n_T;
+ *   the child is the first non-empty slot whose running sum of q exceeds
+ *   u = (x >> 8) 2^-24 of the selection word x (the last non-empty slot if
+ *   rounding leaves the total below u).  Leaves choose a point uniformly.
+ *   An all-zero network is the uniform path index.
  */
 sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel,
                     float beta, int32_t samples, uint64_t seed, const sbh_eval_opts* opts,
@@ -140,6 +164,71 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
 sbh_status sbh_brute(const float* sources, const float* weights, const float* normals, int64_t n,
                      const float* queries, int64_t nq, sbh_kernel kernel, const sbh_eval_opts* opts,
                      int32_t fp64, hipStream_t stream, void* out);
+
+/*
+ * sbh_mlp_forward - logits of the proposal network.
+ *   params [SBH_MLP_NPARAM], features [n][8], logits [n][8] (float32).
+ *   n = 0 is a no-op.  Errors: SBH_EINVAL (NULL argument, n < 0 or >= 2^31),
+ *   SBH_EHIP.
+ */
+sbh_status sbh_mlp_forward(const float* params, const float* features, int64_t n, hipStream_t stream,
+                           float* logits);
+
+/*
+ * sbh_mlp_pairs - training rows for the proposal.  For query j and subdomain
+ * slot a (the root's children, Section 3.3.1) a path is walked from a with
+ * the uniform path index, drawing from Philox4x32-10 with key = seed and
+ * counter = (j, a, step/2, 0xFFFFFFFF) (word 2 (step & 1) selects); every
+ * internal node T on it down to depth max_depth is one row
+ * r = (j * 8 + a) * max_depth + step:
+ *   features [rows][8]  the network inputs of (T, q_j):
+ *                       (dx, dy, dz, rho) / (1 + rho) for the query's offset
+ *                       from the cell centre in half-cell units, level /
+ *                       max_level, n_T / n_a, |sum w n| / sum w (0 without
+ *                       normals), min(rho, 16) / 16
+ *   targets  [rows][8]  per child slot c: |sum over c's points of f - f of c's
+ *                       aggregate| (float64), normalised to sum 1 (n_c / n_T
+ *                       when every residual is 0): the share of T's refinement
+ *                       error that c carries (Eqs. (3)-(4))
+ *   counts   [rows][8]  n_c per slot (0 = empty slot)
+ *   where    [rows][4]  int32 {children block, first point, n_T, level} of T
+ * Rows past the end of a path are all zero with where = {-1, 0, 0, 0}.
+ * rows = nq * 8 * max_depth; 1 <= max_depth <= the tree's max_level.
+ * Kernels and eps / alpha (opts, may be NULL) as for sbh_eval.  Errors:
+ * SBH_EINVAL, SBH_EUNSUPPORTED (branching 4), SBH_EHIP.
+ */
+sbh_status sbh_mlp_pairs(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel, uint64_t seed,
+                         int32_t max_depth, const sbh_eval_opts* opts, hipStream_t stream, float* features,
+                         float* targets, float* counts, int32_t* where);
+
+/*
+ * sbh_mlp_loss_grad - mean over the rows with some non-zero count of the soft
+ * cross-entropy -sum_c t_c log pi_c, pi_c = n_c exp(z_c) / sum n_c' exp(z_c'),
+ * and its gradient with respect to params (back-propagation through the
+ * binary16 forward; deltas in binary16, sums in float32).
+ *   features, targets, counts [n][8] as written by sbh_mlp_pairs;
+ *   grad [SBH_MLP_GRAD_SIZE].  Allocates a stream-ordered workspace of
+ *   about 6.3 KiB per 64 rows.  Errors: SBH_EINVAL (NULL argument, n < 1
+ *   or >= 2^31), SBH_ENOMEM, SBH_EHIP.
+ */
+sbh_status sbh_mlp_loss_grad(const float* params, const float* features, const float* targets, const float* counts,
+                             int64_t n, hipStream_t stream, float* grad);
+
+/*
+ * sbh_mlp_train - `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8,
+ * learning rate lr) on params in place.  Step s (counted from step0, which
+ * sets the bias correction, so that training can be continued) uses the
+ * rows [b (step0 + s) mod n, ...) up to b = min(batch_rows, n) rows or the
+ * end of the set; shuffle the rows beforehand.  adam_state [2][1608]
+ * (first and second moments, zero before the first step); losses [steps]
+ * (optional) receives each step's mean loss.  Allocates a stream-ordered
+ * workspace like sbh_mlp_loss_grad.  Errors: SBH_EINVAL (NULL argument, n
+ * out of range, steps or step0 < 0, batch_rows outside [1, 2^24], lr not
+ * finite and > 0), SBH_ENOMEM, SBH_EHIP.
+ */
+sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features, const float* targets,
+                         const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr, int32_t step0,
+                         hipStream_t stream, float* losses);
 
 /* sbh_tree_info - sizes and root cube of a tree into *info (host). */
 sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info);

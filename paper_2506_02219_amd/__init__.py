@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsbh.so")
 
 POTENTIAL, WINDING, SMOOTHDIST = 0, 1, 2
+MLP_NPARAM, MLP_GRAD_SIZE = 1608, 1610
 KERNELS = {"potential": POTENTIAL, "winding": WINDING, "smoothdist": SMOOTHDIST}
 
 
@@ -26,7 +27,7 @@ class BuildOpts(C.Structure):
 
 class EvalOpts(C.Structure):
     _fields_ = [("eps", C.c_float), ("alpha", C.c_float), ("group", C.c_int32), ("rr_mode", C.c_int32),
-                ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p)]
+                ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p)]
 
 
 class TreeDesc(C.Structure):
@@ -67,6 +68,14 @@ def lib():
         L.sbh_tree_info.restype = i32
         L.sbh_tree_export.argtypes = [P] + [P] * 11
         L.sbh_tree_export.restype = i32
+        L.sbh_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.sbh_mlp_forward.restype = i32
+        L.sbh_mlp_pairs.argtypes = [P, P, i64, i32, u64, i32, P, P, P, P, P, P]
+        L.sbh_mlp_pairs.restype = i32
+        L.sbh_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, P]
+        L.sbh_mlp_loss_grad.restype = i32
+        L.sbh_mlp_train.argtypes = [P, P, P, P, P, i64, i32, i32, f32, i32, P, P]
+        L.sbh_mlp_train.restype = i32
         L.sbh_free.argtypes = [P]
         L.sbh_free.restype = i32
         L.sbh_status_string.argtypes = [i32]
@@ -165,9 +174,10 @@ def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_leve
 
 
 def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
-             rr_mode=0, batch=0, paths=None, out=None, stream=None):
+             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None):
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
-    paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records."""
+    paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records;
+    mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal."""
     import torch
     _dev(queries, "queries", (3,))
     nq = queries.shape[0]
@@ -178,7 +188,12 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
         _dev(paths, "paths", dtype=torch.int32)
         if tuple(paths.shape) != (nq, tree.branching ** 3, max(samples, 1), 4):
             raise ValueError("paths must have shape [nq, d^3, samples, 4]")
-    o = EvalOpts(eps, alpha, group, rr_mode, 0, batch, None if paths is None else paths.data_ptr())
+    if mlp is not None:
+        _dev(mlp, "mlp")
+        if tuple(mlp.shape) != (MLP_NPARAM,):
+            raise ValueError("mlp must have shape [MLP_NPARAM]")
+    o = EvalOpts(eps, alpha, group, rr_mode, 0 if mlp is None else 1, batch,
+                 None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr())
     _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
                                       C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
     return out
@@ -195,11 +210,88 @@ def sbh_brute(sources, weights, normals, queries, kernel, eps=1e-3, alpha=100.0,
     if out is None:
         out = torch.empty(nq, dtype=dt, device=queries.device)
     _dev(out, "out", dtype=dt)
-    o = EvalOpts(eps, alpha, 1, 0, 0, 0, None)
+    o = EvalOpts(eps, alpha, 1, 0, 0, 0, None, None)
     _check("sbh_brute", lib().sbh_brute(_ptr(sources), _ptr(weights), _ptr(normals), sources.shape[0],
                                         _ptr(queries), nq, int(kernel), C.byref(o), int(bool(fp64)),
                                         _stream(stream), _ptr(out)))
     return out
+
+
+def _params(t, name):
+    _dev(t, name)
+    if tuple(t.shape) != (MLP_NPARAM,):
+        raise ValueError(f"{name} must have shape [MLP_NPARAM]")
+    return t
+
+
+def sbh_mlp_forward(params, features, out=None, stream=None):
+    """Logits [n, 8] of the proposal network for feature rows [n, 8] (sbh_mlp_forward)."""
+    import torch
+    _params(params, "params"); _dev(features, "features", (8,))
+    if out is None:
+        out = torch.empty_like(features)
+    _dev(out, "out", (8,))
+    if out.shape[0] != features.shape[0]:
+        raise ValueError("out must have as many rows as features")
+    _check("sbh_mlp_forward", lib().sbh_mlp_forward(_ptr(params), _ptr(features), features.shape[0],
+                                                    _stream(stream), _ptr(out)))
+    return out
+
+
+def sbh_mlp_pairs(tree: Tree, queries, kernel, seed=0, max_depth=None, eps=1e-3, alpha=100.0, stream=None):
+    """Training rows along uniform paths (sbh_mlp_pairs): features, targets, counts [rows, 8] and
+    where [rows, 4] (int32), rows = nq * 8 * max_depth."""
+    import torch
+    _dev(queries, "queries", (3,))
+    depth = tree.max_level if max_depth is None else int(max_depth)
+    rows = queries.shape[0] * 8 * depth
+    dev = queries.device
+    X = torch.empty(rows, 8, dtype=torch.float32, device=dev)
+    Tg = torch.empty_like(X); Cn = torch.empty_like(X)
+    where = torch.empty(rows, 4, dtype=torch.int32, device=dev)
+    o = EvalOpts(eps, alpha, 1, 0, 0, 0, None, None)
+    _check("sbh_mlp_pairs", lib().sbh_mlp_pairs(tree.handle, _ptr(queries), queries.shape[0], int(kernel),
+                                                C.c_uint64(seed), depth, C.byref(o), _stream(stream),
+                                                _ptr(X), _ptr(Tg), _ptr(Cn), _ptr(where)))
+    return X, Tg, Cn, where
+
+
+def sbh_mlp_loss_grad(params, features, targets, counts, out=None, stream=None):
+    """Mean loss and gradient (sbh_mlp_loss_grad): returns [MLP_GRAD_SIZE] (gradient, loss, rows)."""
+    import torch
+    _params(params, "params")
+    for t, nm in ((features, "features"), (targets, "targets"), (counts, "counts")):
+        _dev(t, nm, (8,))
+    n = features.shape[0]
+    if targets.shape[0] != n or counts.shape[0] != n:
+        raise ValueError("features, targets and counts must have the same number of rows")
+    if out is None:
+        out = torch.empty(MLP_GRAD_SIZE, dtype=torch.float32, device=params.device)
+    _dev(out, "out")
+    _check("sbh_mlp_loss_grad", lib().sbh_mlp_loss_grad(_ptr(params), _ptr(features), _ptr(targets), _ptr(counts),
+                                                        n, _stream(stream), _ptr(out)))
+    return out
+
+
+def sbh_mlp_train(params, adam_state, features, targets, counts, steps, batch_rows=4096, lr=1e-3, step0=0,
+                  losses=None, stream=None):
+    """Adam steps on params in place (sbh_mlp_train); adam_state [2 * MLP_NPARAM]; losses [steps] or None."""
+    _params(params, "params"); _dev(adam_state, "adam_state")
+    if tuple(adam_state.shape) != (2 * MLP_NPARAM,):
+        raise ValueError("adam_state must have shape [2 * MLP_NPARAM]")
+    for t, nm in ((features, "features"), (targets, "targets"), (counts, "counts")):
+        _dev(t, nm, (8,))
+    n = features.shape[0]
+    if targets.shape[0] != n or counts.shape[0] != n:
+        raise ValueError("features, targets and counts must have the same number of rows")
+    if losses is not None:
+        _dev(losses, "losses")
+        if losses.numel() < steps:
+            raise ValueError("losses must hold `steps` values")
+    _check("sbh_mlp_train", lib().sbh_mlp_train(_ptr(params), _ptr(adam_state), _ptr(features), _ptr(targets),
+                                                _ptr(counts), n, int(steps), int(batch_rows), float(lr), int(step0),
+                                                _stream(stream), _ptr(losses)))
+    return losses
 
 
 def sbh_free(tree: Tree):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbh.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "build.hip", "eval.hip", "brute.hip"]
+SOURCES = ["api.hip", "build.hip", "eval.hip", "brute.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # keep the compiler from emitting packed fp32 instructions

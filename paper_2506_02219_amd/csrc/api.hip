@@ -1,6 +1,6 @@
 // C ABI of libsbh (declared in include/sbh.h): argument checks, error
 // reporting and ownership.  Every compute step is a kernel in build.hip,
-// eval.hip or brute.hip.
+// eval.hip, brute.hip or mlp.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -58,7 +58,8 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (!(o.alpha > 0.0f) || !std::isfinite(o.alpha)) return fail(SBH_EINVAL, "alpha must be finite and > 0");
     if (o.group < 1) return fail(SBH_EINVAL, "group must be >= 1");
     if (o.rr_mode < 0 || o.rr_mode > 2) return fail(SBH_EINVAL, "rr_mode must be 0, 1 or 2");
-    if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "proposal %d is not available", o.proposal);
+    if (o.proposal != 0 && o.proposal != 1) return fail(SBH_EINVAL, "proposal must be 0 or 1");
+    if (o.proposal == 1 && !o.mlp) return fail(SBH_EINVAL, "the learned proposal needs opts->mlp");
     return SBH_OK;
 }
 
@@ -84,6 +85,7 @@ void sbh_eval_opts_default(sbh_eval_opts* o)
     o->proposal = 0;
     o->batch = 0;
     o->paths = nullptr;
+    o->mlp = nullptr;
 }
 
 const char* sbh_status_string(sbh_status s)
@@ -165,8 +167,13 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     e.eps = o.eps;
     e.alpha = o.alpha;
     e.paths = samples > 0 ? o.paths : nullptr;
-    const hipError_t err = samples > 0 ? sbh::launch_sbh_eval(t, queries, nq, e, out, stream)
-                                       : sbh::launch_bh_eval(t, queries, nq, e, out, stream);
+    const bool learned = samples > 0 && o.proposal == 1;
+    if (learned && t->d != 2) return fail(SBH_EUNSUPPORTED, "sbh_eval: the learned proposal needs branching 2");
+    const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
+    hipError_t err;
+    if (samples == 0) err = sbh::launch_bh_eval(t, queries, nq, e, out, stream);
+    else if (learned && !root_leaf) err = sbh::launch_sbh_learned(t, queries, nq, e, o.mlp, out, stream);
+    else err = sbh::launch_sbh_eval(t, queries, nq, e, out, stream);
     if (err != hipSuccess) return hip_fail(err, "sbh_eval: kernel launch");
     return SBH_OK;
 }
@@ -246,6 +253,96 @@ sbh_status sbh_free(sbh_tree* tree)
     (void)hipDeviceSynchronize();
     free_impl(&tree->impl);
     delete tree;
+    return SBH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned child proposal
+// ---------------------------------------------------------------------------
+sbh_status sbh_mlp_forward(const float* params, const float* features, int64_t n, hipStream_t stream, float* logits)
+{
+    if (n < 0) return fail(SBH_EINVAL, "sbh_mlp_forward: n < 0");
+    if (!params || (n > 0 && (!features || !logits)))
+        return fail(SBH_EINVAL, "sbh_mlp_forward: NULL argument");
+    if (n >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_mlp_forward: n must be < 2^31");
+    const hipError_t e = sbh::launch_mlp_forward(params, features, n, logits, stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_forward: kernel launch");
+    return SBH_OK;
+}
+
+sbh_status sbh_mlp_pairs(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel, uint64_t seed,
+                         int32_t max_depth, const sbh_eval_opts* opts, hipStream_t stream, float* features,
+                         float* targets, float* counts, int32_t* where)
+{
+    if (!tree) return fail(SBH_EINVAL, "sbh_mlp_pairs: tree is NULL");
+    if (nq < 0) return fail(SBH_EINVAL, "sbh_mlp_pairs: nq < 0");
+    const sbh::sbh_tree_impl* t = &tree->impl;
+    if (t->d != 2) return fail(SBH_EUNSUPPORTED, "sbh_mlp_pairs: the learned proposal needs branching 2");
+    if (max_depth < 1 || max_depth > t->max_level)
+        return fail(SBH_EINVAL, "sbh_mlp_pairs: max_depth must be in [1, %d]", t->max_level);
+    if (nq > 0 && (!queries || !features || !targets || !counts || !where))
+        return fail(SBH_EINVAL, "sbh_mlp_pairs: NULL argument");
+    if (nq * 8 * (int64_t)max_depth >= ((int64_t)1 << 31))
+        return fail(SBH_EINVAL, "sbh_mlp_pairs: nq * 8 * max_depth must be < 2^31");
+    if (check_kernel(kernel) != SBH_OK) return SBH_EINVAL;
+    if (kernel == SBH_WINDING && !t->has_normals)
+        return fail(SBH_EINVAL, "sbh_mlp_pairs: the winding kernel needs a tree built with normals");
+    sbh_eval_opts o;
+    sbh_eval_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.eps >= 0.0f) || !(o.alpha > 0.0f) || !std::isfinite(o.eps) || !std::isfinite(o.alpha))
+        return fail(SBH_EINVAL, "sbh_mlp_pairs: bad eps or alpha");
+    if (nq == 0) return SBH_OK;
+    const hipError_t e = sbh::launch_mlp_pairs(t, queries, nq, max_depth, seed, kernel, o.eps, o.alpha, features,
+                                               targets, counts, reinterpret_cast<int4*>(where), stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_pairs: kernel launch");
+    return SBH_OK;
+}
+
+sbh_status sbh_mlp_loss_grad(const float* params, const float* features, const float* targets, const float* counts,
+                             int64_t n, hipStream_t stream, float* grad)
+{
+    if (n < 1) return fail(SBH_EINVAL, "sbh_mlp_loss_grad: n < 1");
+    if (n >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_mlp_loss_grad: n must be < 2^31");
+    if (!params || !features || !targets || !counts || !grad)
+        return fail(SBH_EINVAL, "sbh_mlp_loss_grad: NULL argument");
+    float* partial = nullptr;
+    hipError_t e = hipMallocAsync((void**)&partial, sbh::mlp_partial_floats(n) * sizeof(float), stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_loss_grad: workspace");
+    e = sbh::launch_mlp_grad(params, features, targets, counts, n, 0, n, partial, grad, stream);
+    const hipError_t f = hipFreeAsync(partial, stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_loss_grad: kernel launch");
+    if (f != hipSuccess) return hip_fail(f, "sbh_mlp_loss_grad: workspace release");
+    return SBH_OK;
+}
+
+sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features, const float* targets,
+                         const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr, int32_t step0,
+                         hipStream_t stream, float* losses)
+{
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_mlp_train: n must be in [1, 2^31)");
+    if (!params || !adam_state || !features || !targets || !counts)
+        return fail(SBH_EINVAL, "sbh_mlp_train: NULL argument");
+    if (steps < 0 || step0 < 0) return fail(SBH_EINVAL, "sbh_mlp_train: steps and step0 must be >= 0");
+    if (batch_rows < 1 || batch_rows > (1 << 24)) return fail(SBH_EINVAL, "sbh_mlp_train: batch_rows must be in [1, 2^24]");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(SBH_EINVAL, "sbh_mlp_train: lr must be finite and > 0");
+    if (steps == 0) return SBH_OK;
+    const int64_t b = batch_rows < n ? batch_rows : n;
+    float* work = nullptr;
+    const size_t pf = sbh::mlp_partial_floats(b);
+    hipError_t e = hipMallocAsync((void**)&work, (pf + 1616) * sizeof(float), stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: workspace");
+    float* grad = work + pf;
+    for (int32_t s = 0; s < steps && e == hipSuccess; ++s) {
+        const int64_t row_begin = ((int64_t)(step0 + s) * b) % n;
+        const int64_t rows = (n - row_begin) < b ? (n - row_begin) : b;
+        e = sbh::launch_mlp_grad(params, features, targets, counts, n, row_begin, rows, work, grad, stream);
+        if (e == hipSuccess)
+            e = sbh::launch_mlp_adam(params, adam_state, grad, lr, step0 + s, losses ? losses + s : nullptr, stream);
+    }
+    const hipError_t f = hipFreeAsync(work, stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: kernel launch");
+    if (f != hipSuccess) return hip_fail(f, "sbh_mlp_train: workspace release");
     return SBH_OK;
 }
 

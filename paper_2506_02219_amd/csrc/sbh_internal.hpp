@@ -179,4 +179,18 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
 
 TreeView make_view(const sbh_tree_impl* t);
 
+// learned proposal (mlp.hip)
+constexpr int kMlpParams = 1608;
+hipError_t launch_sbh_learned(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
+                              const float* prm, float* out, hipStream_t s);
+hipError_t launch_mlp_forward(const float* prm, const float* x, int64_t n, float* z, hipStream_t s);
+size_t mlp_partial_floats(int64_t rows);
+hipError_t launch_mlp_grad(const float* prm, const float* X, const float* Tg, const float* Cn, int64_t n,
+                           int64_t row_begin, int64_t rows, float* partial, float* grad, hipStream_t s);
+hipError_t launch_mlp_adam(float* prm, float* state, const float* grad, float lr, int step, float* loss_out,
+                           hipStream_t s);
+hipError_t launch_mlp_pairs(const sbh_tree_impl* t, const float* queries, int64_t nq, int lmax, uint64_t seed,
+                            int kernel, float eps, float alpha, float* X, float* Tg, float* Cn, int4* loc,
+                            hipStream_t s);
+
 }  // namespace sbh

@@ -1,0 +1,66 @@
+"""Training of the learned child proposal on the GPU (sbh_mlp_* entry points).
+
+Section 3.3 samples the path index uniformly; Theorem 1 only needs every
+child to keep a positive probability, so the estimator stays unbiased under
+any proposal that is divided out.  The network (8 features -> 32 -> 32 -> 8
+logits, ReLU) is trained to put the probability of each child in proportion
+to the share of the node's refinement error (Eqs. (3)-(4)) that the child
+carries: targets are the per-child residuals |sum over the child's points -
+the child's aggregate term|, computed exactly on the GPU along uniform
+paths.  The loss is the soft cross-entropy between those shares and the
+count-weighted softmax of the logits; the optimiser is Adam.
+
+Argument marshalling and row bookkeeping only: features, targets, forward,
+backward and the Adam step all run in libsbh's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import MLP_NPARAM, sbh_mlp_loss_grad, sbh_mlp_pairs, sbh_mlp_train
+
+OFF_W1, OFF_B1, OFF_W2, OFF_B2, OFF_W3, OFF_B3 = 0, 256, 288, 1312, 1344, 1600
+
+
+def init_params(seed: int, device="cuda") -> torch.Tensor:
+    """Uniform fan-in initialisation of the two hidden layers; output layer zero,
+    so that the untrained network is exactly the uniform path index."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.zeros(MLP_NPARAM, np.float32)
+    p[OFF_W1:OFF_B1] = rng.uniform(-1, 1, 256) / np.sqrt(8.0)
+    p[OFF_W2:OFF_B2] = rng.uniform(-1, 1, 1024) / np.sqrt(32.0)
+    return torch.from_numpy(p).to(device)
+
+
+def training_rows(tree, queries: torch.Tensor, kernel: int, seed: int, max_depth=None, eps=1e-3, alpha=100.0):
+    """Features, targets and child counts of every internal node on uniform paths
+    from each subdomain of each query (rows past the end of a path removed)."""
+    X, Tg, Cn, where = sbh_mlp_pairs(tree, queries, kernel, seed=seed, max_depth=max_depth, eps=eps, alpha=alpha)
+    keep = torch.nonzero(where[:, 0] >= 0).squeeze(1)
+    return X[keep], Tg[keep], Cn[keep]
+
+
+def train(params: torch.Tensor, X: torch.Tensor, Tg: torch.Tensor, Cn: torch.Tensor, steps: int,
+          batch_rows: int = 8192, lr: float = 2e-3, seed: int = 0, epochs_per_shuffle: int = 1):
+    """Adam on `params` in place over the rows (shuffled with `seed`).  Returns the per-step losses
+    (device tensor) and the final Adam state."""
+    n = X.shape[0]
+    state = torch.zeros(2 * MLP_NPARAM, dtype=torch.float32, device=params.device)
+    losses = torch.zeros(max(steps, 1), dtype=torch.float32, device=params.device)
+    gen = torch.Generator().manual_seed(seed)
+    per_epoch = max(1, (n + batch_rows - 1) // batch_rows)
+    done = 0
+    while done < steps:
+        perm = torch.randperm(n, generator=gen).to(params.device)
+        Xs, Ts, Cs = X[perm].contiguous(), Tg[perm].contiguous(), Cn[perm].contiguous()
+        k = min(steps - done, per_epoch * epochs_per_shuffle)
+        # steps are counted from `done` so that Adam's bias correction continues across shuffles
+        sbh_mlp_train(params, state, Xs, Ts, Cs, steps=k, batch_rows=batch_rows, lr=lr, step0=done,
+                      losses=losses[done:done + k])
+        done += k
+    return losses[:steps], state
+
+
+def mean_loss(params, X, Tg, Cn) -> float:
+    return float(sbh_mlp_loss_grad(params, X, Tg, Cn)[MLP_NPARAM].item())

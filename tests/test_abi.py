@@ -3,6 +3,7 @@ include/sbh.h declares (no compute calls: there is no GPU here)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -20,7 +21,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("sbh_build", "sbh_eval", "sbh_brute", "sbh_free", "sbh_tree_info", "sbh_tree_export",
-              "sbh_status_string", "sbh_last_error", "sbh_build_opts_default", "sbh_eval_opts_default"):
+              "sbh_status_string", "sbh_last_error", "sbh_build_opts_default", "sbh_eval_opts_default",
+              "sbh_mlp_forward", "sbh_mlp_pairs", "sbh_mlp_loss_grad", "sbh_mlp_train"):
         assert n in names
 
 
@@ -41,17 +43,31 @@ def test_status_strings_and_defaults():
         assert L.sbh_status_string(code).startswith(b"SBH_E")
     o = P.EvalOpts()
     L.sbh_eval_opts_default(ctypes.byref(o))
-    assert (round(o.eps, 6), o.alpha, o.group, o.rr_mode, o.proposal, o.batch, o.paths) == (0.001, 100.0, 1, 0, 0, 0, None)
+    assert (round(o.eps, 6), o.alpha, o.group, o.rr_mode, o.proposal, o.batch, o.paths, o.mlp) == \
+        (0.001, 100.0, 1, 0, 0, 0, None, None)
     b = P.BuildOpts()
     L.sbh_build_opts_default(ctypes.byref(b))
     assert (b.branching, b.leaf_size, b.max_level) == (2, 8, 0)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures against sizeof / offsetof of the C header (compiled with gcc)."""
     import paper_2506_02219_amd as P
-    assert ctypes.sizeof(P.BuildOpts) == 12
-    assert ctypes.sizeof(P.EvalOpts) == 32 and P.EvalOpts.paths.offset == 24
-    assert ctypes.sizeof(P.TreeDesc) == 64 and P.TreeDesc.lo.offset == 44
+    src = tmp_path / "layout.c"
+    fields = [("sbh_build_opts", None), ("sbh_eval_opts", None), ("sbh_eval_opts", "paths"),
+              ("sbh_eval_opts", "mlp"), ("sbh_eval_opts", "batch"), ("sbh_tree_desc", None),
+              ("sbh_tree_desc", "lo"), ("sbh_tree_desc", "inv_side")]
+    exprs = ", ".join(f"(long)sizeof({s})" if f is None else f"(long)offsetof({s}, {f})" for s, f in fields)
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sbh.h\"\n"
+                   f"int main(void) {{ long v[] = {{{exprs}}}; for (int i = 0; i < {len(fields)}; ++i) "
+                   "printf(\"%ld \", v[i]); return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+                    "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(P.BuildOpts), ctypes.sizeof(P.EvalOpts), P.EvalOpts.paths.offset, P.EvalOpts.mlp.offset,
+            P.EvalOpts.batch.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset]
+    assert got == want
 
 
 def test_argument_errors_before_any_device_work():
@@ -64,3 +80,13 @@ def test_argument_errors_before_any_device_work():
     assert L.sbh_eval(None, None, 0, 0, 2.0, 1, 0, None, None, None) == -1
     assert L.sbh_brute(None, None, None, 0, None, 0, 0, None, 0, None, None) == -1
     assert L.sbh_free(None) == 0
+    assert L.sbh_mlp_forward(None, None, 4, None, None) == -1
+    assert L.sbh_mlp_pairs(None, None, 4, 0, 0, 3, None, None, None, None, None, None) == -1
+    assert L.sbh_mlp_loss_grad(None, None, None, None, 0, None, None) == -1
+    assert L.sbh_mlp_train(None, None, None, None, None, 0, 1, 64, 1e-3, 0, None, None) == -1
+    o = P.EvalOpts()
+    L.sbh_eval_opts_default(ctypes.byref(o))
+    o.proposal = 1   # learned proposal without parameters
+    one = ctypes.c_void_p(1)
+    assert L.sbh_eval(one, one, 1, 0, 2.0, 1, 0, ctypes.byref(o), None, one) == -1
+    assert b"mlp" in L.sbh_last_error()
