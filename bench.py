@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched evaluation")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -76,6 +77,21 @@ def _training_surface(seed):
     import workloads as W
     pts, _, w, _ = W.star_surface(1 << 22, seed)
     return np.ascontiguousarray(pts, np.float32), np.ascontiguousarray(w, np.float32)
+
+
+def _batch_cloud(spec):
+    import workloads as W
+    cl = W.c4_cloud(spec)
+    return cl.sources, cl.weights, cl.normals, cl.queries, int(spec["kernel"])
+
+
+def batch_clouds():
+    """The 64 clouds of the batched workload, generated in forked CPU workers."""
+    import multiprocessing as mp
+    import workloads as W
+    specs = W.c4_specs()
+    with mp.get_context("fork").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+        return pool.map(_batch_cloud, specs)
 
 
 def training_surfaces(seeds):
@@ -140,6 +156,11 @@ def main():
         t0 = time.time()
         train_clouds = training_surfaces(W.c5_training_seeds()[:args.train_seeds])
         train_gen_s = time.time() - t0
+    c4, c4_gen_s = None, 0.0
+    if not args.no_batch:
+        t0 = time.time()
+        c4 = batch_clouds()
+        c4_gen_s = time.time() - t0
     t0 = time.time()
     cl = getattr(W, cfg["gen"])()
     gen_s = time.time() - t0
@@ -358,35 +379,83 @@ def main():
         loss1 = L.mean_loss(prm, X, Tg, Cn)
         lc = losses.cpu().numpy()
 
-        def run_learned(samples, group=1):
-            P.sbh_eval(tree, qry, kernel, samples=samples, seed=0, group=group, out=out, mlp=prm)
+        def proposal_curve(prop, params):
+            """(samples, ms, median error) of proposal 1 or 2, and its speed at equal error to the plain method"""
+            def run(samples):
+                P.sbh_eval(tree, qry, kernel, samples=samples, seed=0, group=1, out=out, mlp=params, proposal=prop)
+            cur = []
+            for sv in (1, 2, 4):
+                ms_l = timed(lambda: run(sv), args.steps if sv == 1 else 3, args.warmup if sv == 1 else 1)
+                cur.append(dict(samples=sv, ms=ms_l, median_rel_err=err_of(lambda: run(sv))))
+            c1 = cur[0]
+            # the plain method's time at this method's error, interpolated over its samples sweep
+            t_plain = None
+            if sweep:
+                t_plain = log_interp([p["median_rel_err"] for p in sweep], [p["ms"] for p in sweep],
+                                     c1["median_rel_err"])
+            # this method's time at the plain method's error: interpolated over its own sweep, or (when one
+            # sample already beats it) scaled down by the 1/S law of the variance
+            t_eq = log_interp([p["median_rel_err"] for p in cur], [p["ms"] for p in cur], err_star)
+            how = "interpolated"
+            if t_eq is None and c1["median_rel_err"] <= err_star:
+                t_eq, how = c1["ms"] * (c1["median_rel_err"] / err_star) ** 2, "extrapolated_1_over_S"
+            return dict(group=1, sweep=cur, plain_ms_at_this_error=t_plain,
+                        speedup_vs_plain_at_this_error=None if t_plain is None else t_plain / c1["ms"],
+                        ms_at_plain_error=t_eq, match=how if t_eq is not None else "not_reached",
+                        queries_per_s_at_plain_error=None if t_eq is None else N / (t_eq * 1e-3))
 
-        lsweep = []
-        for sv in (1, 2, 4):
-            ms_l = timed(lambda: run_learned(sv), args.steps if sv == 1 else 3, args.warmup if sv == 1 else 1)
-            lsweep.append(dict(samples=sv, ms=ms_l, median_rel_err=err_of(lambda: run_learned(sv))))
-        l1 = lsweep[0]
-        # the plain method's time at the learned method's error, interpolated over its samples sweep
-        t_plain = None
-        if sweep:
-            t_plain = log_interp([p["median_rel_err"] for p in sweep], [p["ms"] for p in sweep], l1["median_rel_err"])
-        # the learned method's time at the plain method's error: interpolated over its own sweep, or
-        # (when one sample already beats it) scaled down by the 1/S law of the variance
-        t_learned = log_interp([p["median_rel_err"] for p in lsweep], [p["ms"] for p in lsweep], err_star)
-        how = "interpolated"
-        if t_learned is None and l1["median_rel_err"] <= err_star:
-            t_learned, how = l1["ms"] * (l1["median_rel_err"] / err_star) ** 2, "extrapolated_1_over_S"
         learned = dict(
             train_seeds=args.train_seeds, train_queries_per_surface=args.train_queries, train_rows=int(X.shape[0]),
             train_steps=args.train_steps, train_batch=args.train_batch, lr=args.train_lr,
             surface_generation_s=train_gen_s, rows_ms=rows_ms, train_ms=train_ms,
             loss_untrained=loss0, loss_trained=loss1, loss_first_steps=float(lc[:50].mean()),
-            loss_last_steps=float(lc[-50:].mean()), group=1, sweep=lsweep,
-            plain_ms_at_learned_error=t_plain,
-            speedup_learned_vs_plain_at_learned_error=None if t_plain is None else t_plain / l1["ms"],
-            learned_ms_at_plain_error=t_learned, learned_match=how if t_learned is not None else "not_reached",
-            queries_per_s_at_plain_error=None if t_learned is None else N / (t_learned * 1e-3))
+            loss_last_steps=float(lc[-50:].mean()),
+            network=proposal_curve(1, prm), score_only=proposal_curve(2, None))
         del X, Tg, Cn
+
+    # --- batched evaluation of 64 clouds of uneven size (one persistent launch, graph replay)
+    batched = None
+    if c4 is not None:
+        trees_b, qs_b, ks_b = [], [], []
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for srcs, ws, ns, qq, kk in c4:
+            trees_b.append(P.sbh_build(torch.from_numpy(srcs).to(dev), torch.from_numpy(ws).to(dev),
+                                       None if ns is None else torch.from_numpy(ns).to(dev), branching=2,
+                                       leaf_size=8))
+            qs_b.append(torch.from_numpy(qq).to(dev))
+            ks_b.append(kk)
+        torch.cuda.synchronize()
+        build_all_ms = (time.perf_counter() - tb0) * 1e3
+        NB = sum(q.shape[0] for q in qs_b)
+        outs_seq = [torch.empty(q.shape[0], dtype=torch.float32, device=dev) for q in qs_b]
+
+        def run_seq():
+            for t_, q_, k_, o_ in zip(trees_b, qs_b, ks_b, outs_seq):
+                P.sbh_eval(t_, q_, k_, samples=S, seed=0, group=64, out=o_)
+
+        ms_seq = timed(run_seq, 5, 1)
+        tp0 = time.perf_counter()
+        plan = P.Batch(trees_b, qs_b, ks_b, samples=S, group=64)
+        plan_ms = (time.perf_counter() - tp0) * 1e3
+        ms_batch = timed(lambda: plan.launch(0, 0), args.steps, args.warmup)
+        plan.launch(0, 0)
+        run_seq()
+        torch.cuda.synchronize()
+        identical = all(bool(torch.equal(torch.nan_to_num(a, nan=1e30), torch.nan_to_num(b, nan=1e30)))
+                        for a, b in zip(plan.outs, outs_seq))
+        batched = dict(workload="64 clouds of log-uniform sizes (sources 2^12..2^20, queries 2^14..2^18), "
+                                "kernels cycling potential / winding / smooth distance",
+                       clouds=len(qs_b), queries=int(NB), sources=int(sum(t_.n_points for t_ in trees_b)),
+                       samples_per_subdomain=S, group=64, generate_s=c4_gen_s, build_all_ms=build_all_ms,
+                       sequential_ms=ms_seq, sequential_queries_per_s=NB / (ms_seq * 1e-3),
+                       batched_ms=ms_batch, batched_queries_per_s=NB / (ms_batch * 1e-3),
+                       speedup_batched_vs_sequential=ms_seq / ms_batch, plan_create_ms=plan_ms,
+                       autotuned=plan.config, identical_to_sequential=identical)
+        plan.free()
+        for t_ in trees_b:
+            t_.free()
+        del trees_b, qs_b, outs_seq, c4
 
     # --- CPU baseline: the FP64 oracle on the host cores, on a bounded sample
     cpu = None
@@ -447,6 +516,7 @@ def main():
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,
+        "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
         "generate_s": gen_s,

@@ -67,8 +67,10 @@ typedef struct sbh_eval_opts {
     int32_t rr_mode;     /* Russian roulette: 0 = Eq. (5) (default), 1 = p = 1 (none),
                             2 = p = 1/2 (the two comparisons of the supplement) */
     int32_t proposal;    /* child-selection distribution: 0 = uniform path index
-                            (the paper's, default); 1 = the learned proposal of
-                            sbh_mlp_* with parameters opts->mlp (branching 2 only) */
+                            (the paper's, default); 1 = the learned proposal with
+                            network parameters opts->mlp; 2 = the score proposal
+                            (the learned one with an all-zero network, evaluated
+                            without it).  1 and 2: branching 2 only. */
     uint32_t batch;      /* fourth Philox counter word, for independent batches; default 0 */
     int32_t* paths;      /* optional DEVICE [nq][d^3][samples][4] int32 records of every
                             sampled path: {end begin, end level, accepted steps, stop
@@ -101,7 +103,8 @@ void sbh_eval_opts_default(sbh_eval_opts* opts /*host*/);
 /*
  * sbh_build - the spatial tree of Section 3.1 (octree-like, per-dimension
  * branching d) with per-node aggregate weight, centre of mass and summed
- * dipole, built on the GPU.
+ * dipole, built on the GPU; each node also keeps the second moment of its
+ * points about the centre of mass (for the learned proposal's features).
  *   sources  [n][3]   source positions p_i (finite)
  *   weights  [n]      source weights m_i (finite, > 0)
  *   normals  [n][3]   unit normals (needed for SBH_WINDING) or NULL
@@ -135,20 +138,25 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   nq = 0 is a no-op.  Errors: SBH_EINVAL (null pointers, nq < 0, bad
  *   kernel, samples < 0, beta <= 0 or NaN with samples == 0, group < 1,
  *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals, proposal
- *   not 0 or 1, proposal 1 without opts->mlp), SBH_EUNSUPPORTED (proposal 1
- *   on a tree with branching 4), SBH_EHIP.
+ *   not 0, 1 or 2, proposal 1 without opts->mlp), SBH_EUNSUPPORTED
+ *   (proposal 1 or 2 on a tree with branching 4), SBH_EHIP.
  *
- *   Learned proposal (opts->proposal = 1).  Section 3.3 draws the path index
- *   uniformly; Theorem 1 needs only that every point can be reached, so any
- *   child distribution q_c > 0 over the non-empty children keeps the
- *   estimator unbiased when the swap of each step is divided by the product
- *   of the q's chosen so far (in place of n_T / n_a, Eq. (7)).  At an internal
- *   node T the network maps the features of (T, q) to logits z_c and
- *     q_c = (7/8) n_c exp(z_c) / sum_c' n_c' exp(z_c') + (1/8) n_c / n_T;
- *   the child is the first non-empty slot whose running sum of q exceeds
- *   u = (x >> 8) 2^-24 of the selection word x (the last non-empty slot if
- *   rounding leaves the total below u).  Leaves choose a point uniformly.
- *   An all-zero network is the uniform path index.
+ *   Learned and score proposals (opts->proposal = 1, 2).  Section 3.3 draws
+ *   the path index uniformly and leaves importance sampling open; Theorem 1
+ *   needs only that every point can be reached, so any child distribution
+ *   q_c > 0 over the non-empty children keeps the estimator unbiased when
+ *   the swap of each step is divided by the product of the q's chosen so far
+ *   (in place of n_T / n_a, Eq. (7)).  At an internal node T each child c
+ *   has the quadrupole score m_c s_c^2 / (|p_c - q|^2 + s_c^2)^(3/2) (weight,
+ *   centre of mass, second moment) -- a bound on the size of c's residual
+ *   under the 1/r kernel -- and the feature f_c = max(-1, ln(score_c / max
+ *   score) / 16) (-1 for empty slots).  The network (proposal 1) maps f to
+ *   logits z = NN(f) + 16 f; proposal 2 uses z = 16 f.  Then
+ *     q_c = (7/8) exp(z_c) / sum_c' exp(z_c') + (1/8) n_c / n_T
+ *   over the non-empty slots; the child is the first non-empty slot whose
+ *   running sum of q exceeds u = (x >> 8) 2^-24 of the selection word x (the
+ *   last non-empty slot if rounding leaves the total below u).  Leaves choose
+ *   a point uniformly.
  */
 sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel,
                     float beta, int32_t samples, uint64_t seed, const sbh_eval_opts* opts,
@@ -181,11 +189,8 @@ sbh_status sbh_mlp_forward(const float* params, const float* features, int64_t n
  * counter = (j, a, step/2, 0xFFFFFFFF) (word 2 (step & 1) selects); every
  * internal node T on it down to depth max_depth is one row
  * r = (j * 8 + a) * max_depth + step:
- *   features [rows][8]  the network inputs of (T, q_j):
- *                       (dx, dy, dz, rho) / (1 + rho) for the query's offset
- *                       from the cell centre in half-cell units, level /
- *                       max_level, n_T / n_a, |sum w n| / sum w (0 without
- *                       normals), min(rho, 16) / 16
+ *   features [rows][8]  the network inputs of (T, q_j): per child slot the
+ *                       relative log quadrupole score (see sbh_eval)
  *   targets  [rows][8]  per child slot c: |sum over c's points of f - f of c's
  *                       aggregate| (float64), normalised to sum 1 (n_c / n_T
  *                       when every residual is 0): the share of T's refinement
@@ -230,6 +235,67 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
                          const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr, int32_t step0,
                          hipStream_t stream, float* losses);
 
+/* ------------------------------------------------------------------------
+ * Batched persistent evaluation: many trees and query sets (of uneven
+ * sizes) evaluated by one persistent launch per branching factor, replayed
+ * from a HIP graph.  A work item is a run of tile_waves wavefront-tiles (64
+ * consecutive queries each) of one cloud; every wavefront takes items from a
+ * device counter until none are left.  Each tile runs the same code as
+ * sbh_eval with samples >= 1 and opts->group a multiple of 64, so every
+ * cloud's output is bit-identical to its own sbh_eval call with the same
+ * seed, batch word and options.
+ * ------------------------------------------------------------------------ */
+typedef struct sbh_batch sbh_batch;   /* opaque plan */
+
+typedef struct sbh_batch_item {
+    const sbh_tree* tree;
+    const float* queries;   /* DEVICE [nq][3] */
+    float* out;             /* DEVICE [nq] */
+    int64_t nq;             /* 0 <= nq < 2^31 */
+    int32_t kernel;         /* sbh_kernel */
+    int32_t reserved;       /* 0 */
+} sbh_batch_item;
+
+typedef struct sbh_batch_config {
+    int32_t tile_waves;      /* wavefront-tiles per work item, 1..1024 */
+    int32_t waves_per_simd;  /* persistent grid: 256 workgroups of 4 wavefronts per unit, 1..8 */
+    int32_t heavy_first;     /* 1: work items of the costliest clouds (queries x depth) first */
+    float ms;                /* autotuned plans: measured time of one batch; else 0 */
+} sbh_batch_config;
+
+/*
+ * sbh_batch_create - validate the items, copy their descriptors to the
+ * device and capture the launch sequence in a HIP graph.
+ *   items (host) [count], 1 <= count <= 2^20; samples >= 1; opts as for
+ *   sbh_eval with group a multiple of 64, proposal 0 and no path records
+ *   (NULL: the defaults with group 64).
+ *   config (host): the launch configuration, or NULL to autotune: every
+ *   candidate (tile_waves 1, 2, 4, 8; waves_per_simd 4, 8; heavy_first 0, 1)
+ *   is timed on the batch itself (seed 0) and the fastest kept; this writes
+ *   the outputs and synchronises `stream`.
+ * The plan keeps pointers to the trees, queries and outputs, which must
+ * stay valid (and the trees alive) until sbh_batch_free.  It allocates
+ * 2 x 16 bytes of launch state and the descriptors on the current device.
+ * Errors: SBH_EINVAL, SBH_EUNSUPPORTED (proposal != 0), SBH_ENOMEM, SBH_EHIP.
+ */
+sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t samples, const sbh_eval_opts* opts,
+                            const sbh_batch_config* config, hipStream_t stream, sbh_batch** out);
+
+/*
+ * sbh_batch_launch - evaluate every item with Philox key `seed` and fourth
+ * counter word `batch` (as opts->batch of sbh_eval): sets the key in the
+ * graph's first node and replays the graph on `stream`.  Allocates nothing.
+ * Launches of one plan that overlap (several streams) race on its launch
+ * state.  Errors: SBH_EINVAL (NULL plan), SBH_EHIP.
+ */
+sbh_status sbh_batch_launch(sbh_batch* batch_plan, uint64_t seed, uint32_t batch, hipStream_t stream);
+
+/* sbh_batch_get_config - the plan's launch configuration into *cfg (host). */
+sbh_status sbh_batch_get_config(const sbh_batch* batch_plan, sbh_batch_config* cfg);
+
+/* sbh_batch_free - release a plan (waits for the device). NULL is a no-op. */
+sbh_status sbh_batch_free(sbh_batch* batch_plan);
+
 /* sbh_tree_info - sizes and root cube of a tree into *info (host). */
 sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info);
 
@@ -244,12 +310,13 @@ sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info);
  *                     (first_child = -1 for a leaf)
  *   agg  [n_nodes][4] centre of mass (x, y, z) and total weight
  *   dip  [n_nodes][4] summed w n (x, y, z), 0
+ *   spread2 [n_nodes] second moment sum w |p - com|^2 / total weight
  * Point arrays have n_points entries: perm (sorted position -> input index)
  * and codes (the 60-bit Morton codes, sorted).  Synchronises the null stream.
  */
 sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count, int32_t* level,
                            int32_t* digit, int32_t* parent, int32_t* first_child, int32_t* nchild,
-                           float* agg, float* dip, uint32_t* perm, uint64_t* codes);
+                           float* agg, float* dip, uint32_t* perm, uint64_t* codes, float* spread2);
 
 /* sbh_free - release a tree (waits for the device to finish using it). NULL is a no-op. */
 sbh_status sbh_free(sbh_tree* tree);

@@ -37,7 +37,7 @@ def lib():
         L.orc_tree_num_nodes.argtypes = [P]
         L.orc_tree_num_nodes.restype = i64
         L.orc_tree_meta.argtypes = [P, P]
-        L.orc_tree_export.argtypes = [P] + [P] * 10
+        L.orc_tree_export.argtypes = [P] + [P] * 11
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
         L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, P, P, i32]
         L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, P, i32]
@@ -45,12 +45,12 @@ def lib():
         L.orc_mlp_nparam.restype = i32
         L.orc_f16_round.argtypes = [C.c_float]
         L.orc_f16_round.restype = C.c_float
-        L.orc_mlp_features.argtypes = [P, P, P, P, i64, P]
+        L.orc_mlp_features.argtypes = [P, P, P, i64, P]
         L.orc_mlp_forward.argtypes = [P, P, i64, i32, P]
         L.orc_mlp_loss_grad.argtypes = [P, P, P, P, i64, i32, P]
         L.orc_mlp_loss_grad.restype = f64
         L.orc_child_targets.argtypes = [P, P, P, i64, i32, f64, f64, P, P]
-        L.orc_mlp_pairs.argtypes = [P, i64, u64, i32, P, P]
+        L.orc_mlp_pairs.argtypes = [P, i64, u64, i32, P]
         _lib = L
     return _lib
 
@@ -112,11 +112,11 @@ class Tree:
         self.begin = np.zeros(n, np.int64); self.count = np.zeros(n, np.int64)
         self.level = np.zeros(n, np.int32); self.first_child = np.zeros(n, np.int64)
         self.nchild = np.zeros(n, np.int32); self.digit = np.zeros(n, np.int32)
-        self.parent = np.zeros(n, np.int64); self.agg = np.zeros((n, 8))
+        self.parent = np.zeros(n, np.int64); self.agg = np.zeros((n, 8)); self.spread2 = np.zeros(n)
         self.perm = np.zeros(self.m, np.int64); self.codes = np.zeros(self.m, np.uint64)
         lib().orc_tree_export(self._h, _p(self.begin), _p(self.count), _p(self.level), _p(self.first_child),
                               _p(self.nchild), _p(self.digit), _p(self.parent), _p(self.agg), _p(self.perm),
-                              _p(self.codes))
+                              _p(self.codes), _p(self.spread2))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -159,31 +159,32 @@ class Tree:
         lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(prm), _p(out), threads)
         return out
 
-    def mlp_features(self, nodes, n_a, queries):
-        """Proposal features of (node, query) pairs; n_a = point count of each pair's subdomain."""
-        nd = np.ascontiguousarray(nodes, np.int64); na = np.ascontiguousarray(n_a, np.int64)
-        q = _f32(queries, (-1, 3)); out = np.zeros((len(nd), 8), np.float32)
-        lib().orc_mlp_features(self._h, _p(nd), _p(na), _p(q), len(nd), _p(out))
+    def mlp_features(self, nodes, queries):
+        """Proposal features (float64 [n, 8]) of (internal node, query) pairs."""
+        nd = np.ascontiguousarray(nodes, np.int64)
+        q = _f32(queries, (-1, 3)); out = np.zeros((len(nd), 8))
+        lib().orc_mlp_features(self._h, _p(nd), _p(q), len(nd), _p(out))
         return out
 
     def mlp_pairs(self, nq, seed=0, lmax=None):
-        """Training (query, node) pairs along uniform paths: node [nq, d^3, lmax] (-1 = none), n_a."""
+        """Training (query, node) pairs along uniform paths: node [nq, d^3, lmax] (-1 = none)."""
         lmax = self.max_level if lmax is None else lmax
         d3 = self.d ** 3
-        nd = np.zeros((nq, d3, lmax), np.int64); na = np.zeros((nq, d3, lmax), np.int64)
-        lib().orc_mlp_pairs(self._h, nq, seed, lmax, _p(nd), _p(na))
-        return nd, na
+        nd = np.zeros((nq, d3, lmax), np.int64)
+        lib().orc_mlp_pairs(self._h, nq, seed, lmax, _p(nd))
+        return nd
 
     def training_set(self, queries, kernel, seed=0, lmax=None, eps=1e-3, alpha=100.0):
-        """Features, targets and child counts of every training pair (rows [nq*d^3*lmax], valid mask)."""
+        """Features (float32), targets and child counts of every training pair
+        (rows [nq*d^3*lmax], valid mask)."""
         q = _f32(queries, (-1, 3))
-        nd, na = self.mlp_pairs(q.shape[0], seed, lmax)
+        nd = self.mlp_pairs(q.shape[0], seed, lmax)
         rows = nd.reshape(-1)
         valid = rows >= 0
         qi = np.repeat(np.arange(q.shape[0]), nd.shape[1] * nd.shape[2])
         X = np.zeros((rows.size, 8), np.float32); Tg = np.zeros_like(X); Cn = np.zeros_like(X)
         if valid.any():
-            X[valid] = self.mlp_features(rows[valid], na.reshape(-1)[valid], q[qi[valid]])
+            X[valid] = self.mlp_features(rows[valid], q[qi[valid]]).astype(np.float32)
             Tg[valid], Cn[valid] = self.child_targets(rows[valid], q[qi[valid]], kernel, eps, alpha)
         return X, Tg, Cn, valid
 

@@ -167,6 +167,7 @@ typedef struct orc_tree {
     int64_t *begin, *count, *first_child, *parent;
     int32_t *level, *nchild, *digit;
     double *mass, *com, *dip; /* com, dip: [n][3] */
+    double* spr;              /* second moment sum w |p - com|^2 / mass */
     double diam[64];          /* |B| per level */
 } orc_tree;
 
@@ -222,7 +223,7 @@ void orc_tree_free(orc_tree* t)
     free(t->pxyz); free(t->pw); free(t->pdip); free(t->perm); free(t->codes);
     free(t->begin); free(t->count); free(t->first_child); free(t->parent);
     free(t->level); free(t->nchild); free(t->digit);
-    free(t->mass); free(t->com); free(t->dip);
+    free(t->mass); free(t->com); free(t->dip); free(t->spr);
     free(t);
 }
 
@@ -322,6 +323,7 @@ orc_tree* orc_tree_build(const float* src, const float* w, const float* nrm, int
     t->mass = malloc(nn * sizeof(double));
     t->com = malloc(3 * nn * sizeof(double));
     t->dip = malloc(3 * nn * sizeof(double));
+    t->spr = malloc(nn * sizeof(double));
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 64)
 #endif
@@ -344,6 +346,13 @@ orc_tree* orc_tree_build(const float* src, const float* w, const float* nrm, int
         t->dip[3 * i] = dx;
         t->dip[3 * i + 1] = dy;
         t->dip[3 * i + 2] = dz;
+        double s2 = 0.0;
+        for (int64_t s = t->begin[i]; s < t->begin[i] + t->count[i]; ++s) {
+            double ex = t->pxyz[3 * s] - t->com[3 * i], ey = t->pxyz[3 * s + 1] - t->com[3 * i + 1],
+                   ez = t->pxyz[3 * s + 2] - t->com[3 * i + 2];
+            s2 += t->pw[s] * (ex * ex + ey * ey + ez * ez);
+        }
+        t->spr[i] = s2 / ms;
     }
     /* cell diagonal per level */
     double dl = 1.0;
@@ -365,10 +374,10 @@ void orc_tree_meta(const orc_tree* t, double* meta)
     meta[9] = (double)t->m;
 }
 
-/* agg: [n][8] = com xyz, mass, dip xyz, |B| */
+/* agg: [n][8] = com xyz, mass, dip xyz, |B|; spread2: [n] second moments */
 void orc_tree_export(const orc_tree* t, int64_t* begin, int64_t* count, int32_t* level,
                      int64_t* first_child, int32_t* nchild, int32_t* digit, int64_t* parent,
-                     double* agg, int64_t* perm, uint64_t* codes)
+                     double* agg, int64_t* perm, uint64_t* codes, double* spread2)
 {
     for (int64_t i = 0; i < t->n_nodes; ++i) {
         if (begin) begin[i] = t->begin[i];
@@ -388,6 +397,7 @@ void orc_tree_export(const orc_tree* t, int64_t* begin, int64_t* count, int32_t*
             agg[8 * i + 6] = t->dip[3 * i + 2];
             agg[8 * i + 7] = t->diam[t->level[i]];
         }
+        if (spread2) spread2[i] = t->spr[i];
     }
     for (int64_t s = 0; s < t->m; ++s) {
         if (perm) perm[s] = t->perm[s];
@@ -435,11 +445,13 @@ static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const d
     }
 }
 
-static double dist3(const double a[3], const double q[3])
+static double dist2(const double a[3], const double q[3])
 {
     double dx = a[0] - q[0], dy = a[1] - q[1], dz = a[2] - q[2];
-    return sqrt(dx * dx + dy * dy + dz * dz);
+    return dx * dx + dy * dy + dz * dz;
 }
+
+static double dist3(const double a[3], const double q[3]) { return sqrt(dist2(a, q)); }
 
 static double leaf_exact(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
 {
@@ -512,9 +524,12 @@ void orc_bh(const orc_tree* t, const float* qry, int64_t n, int kernel, double e
 /* ======================================================================== */
 /* Learned child proposal (importance sampling of the path index, which     */
 /* Section 3.3 leaves open).  A node-level MLP 8 -> 32 -> 32 -> 8 (ReLU)     */
-/* maps features of (node, query) to one logit per child slot (d = 2).       */
-/* Proposal: pi_c = n_c exp(z_c) / sum n exp(z) over non-empty slots (so a   */
-/* zero network is the uniform path index), mixed defensively:              */
+/* maps one feature per child slot (d = 2) -- the log of the child's         */
+/* quadrupole score relative to its siblings -- to one logit per slot, with  */
+/* the features also added to the logits (times 16), so that a zero network */
+/* samples in proportion to the scores.                                      */
+/* Proposal: pi_c = exp(z_c) / sum exp(z) over non-empty slots, mixed        */
+/* defensively with the uniform path index:                                  */
 /*   q_c = (1 - LAMBDA) pi_c + LAMBDA n_c / n_T,                             */
 /* so every non-empty child keeps q_c > 0 and Theorem 1 still applies.      */
 /* Parameters (float32, 1608): W1[32][8] b1[32] W2[32][32] b2[32]            */
@@ -553,48 +568,41 @@ static float f16_round(float x)
 
 float orc_f16_round(float x) { return f16_round(x); }
 
-/* Features of (node T, query q), float32 with a fixed operation order:
- *   cell centre cen = lo + (2 i + 1) h (i the integer cell index at T's level,
- *   h half the cell side), r = (q - cen) / h, rho = |r|:
- *   f0..2 = r / (1 + rho), f3 = rho / (1 + rho), f4 = level / max_level,
- *   f5 = n_T / n_a (a = the path's subdomain), f6 = |sum w n| / sum w (0 without
- *   normals), f7 = min(rho, 16) / 16. */
-static void mlp_features(const orc_tree* t, int64_t T, int64_t n_a, const float qf[3], float f[8])
+/* Features of (internal node T, query q): one per child slot k.  For child c
+ * in slot k, with mass m_c, centre of mass p_c and second moment
+ * s_c^2 = sum w |p - p_c|^2 / m_c,
+ *   score_c = m_c s_c^2 / (|p_c - q|^2 + s_c^2)^(3/2)
+ * is the size of the quadrupole term of c's residual under the 1/r kernel
+ * (softened inside c's spread), and
+ *   f_k = max(-1, ln(score_c / max_c' score_c') / 16),
+ * -1 for an empty slot (and for every slot when all scores are 0). */
+static void mlp_features(const orc_tree* t, int64_t T, const double q[3], double f[8])
 {
-    int lev = t->level[T];
-    int oct = t->bits * lev / 3;             /* octree levels of the cell */
-    uint64_t pre = oct > 0 ? (t->codes[t->begin[T]] >> (60 - 3 * oct)) : 0;
-    uint32_t ix = 0, iy = 0, iz = 0;
-    for (int k = 0; k < oct; ++k) {
-        ix |= (uint32_t)((pre >> (3 * k)) & 1u) << k;
-        iy |= (uint32_t)((pre >> (3 * k + 1)) & 1u) << k;
-        iz |= (uint32_t)((pre >> (3 * k + 2)) & 1u) << k;
+    double sc[8];
+    double smax = 0.0;
+    for (int k = 0; k < 8; ++k) { sc[k] = -1.0; f[k] = -1.0; }
+    for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+        double r2 = dist2(&t->com[3 * ch], q);
+        double s2 = t->spr[ch];
+        double v = t->mass[ch] * s2 / pow(r2 + s2, 1.5);
+        if (!(r2 + s2 > 0.0)) v = 0.0;
+        sc[t->digit[ch]] = v;
+        if (v > smax) smax = v;
     }
-    float h = ldexpf(t->side, -oct - 1);
-    float cx = t->lo[0] + (float)(2u * ix + 1u) * h;
-    float cy = t->lo[1] + (float)(2u * iy + 1u) * h;
-    float cz = t->lo[2] + (float)(2u * iz + 1u) * h;
-    float rx = (qf[0] - cx) / h, ry = (qf[1] - cy) / h, rz = (qf[2] - cz) / h;
-    float rho = sqrtf((rx * rx + ry * ry) + rz * rz);
-    float den = 1.0f + rho;
-    f[0] = rx / den;
-    f[1] = ry / den;
-    f[2] = rz / den;
-    f[3] = rho / den;
-    f[4] = (float)lev / (float)t->max_level;
-    f[5] = (float)t->count[T] / (float)n_a;
-    if (t->has_normals) {
-        float dx = (float)t->dip[3 * T], dy = (float)t->dip[3 * T + 1], dz = (float)t->dip[3 * T + 2];
-        f[6] = sqrtf((dx * dx + dy * dy) + dz * dz) / (float)t->mass[T];
-    } else {
-        f[6] = 0.0f;
-    }
-    f[7] = (rho < 16.0f ? rho : 16.0f) / 16.0f;
+    if (smax > 0.0)
+        for (int k = 0; k < 8; ++k)
+            if (sc[k] > 0.0) {
+                double l = log(sc[k] / smax) / 16.0;
+                f[k] = l > -1.0 ? l : -1.0;
+            }
 }
 
-/* Logits.  mode 1: binary16 weights / inputs / hidden activations, each dot
- * product summed exactly and rounded once to float32, bias added in float32;
- * mode 0: float64 throughout.  Optional outputs keep the activations. */
+/* Logits z = W3 h2 + b3 + 16 x (the features pass straight to the logits, so
+ * an all-zero network proposes in proportion to the children's scores).
+ * mode 1: binary16 weights / inputs / hidden activations, each dot product
+ * summed exactly and rounded once to float32, bias and skip term added in
+ * float32; mode 0: float64 throughout.  Optional outputs keep the
+ * activations. */
 static void mlp_forward(const float* prm, const float x[8], int mode, double z[8], double h1o[32], double h2o[32])
 {
     double xin[MLP_IN], h1[MLP_H], h2[MLP_H];
@@ -627,38 +635,41 @@ static void mlp_forward(const float* prm, const float x[8], int mode, double z[8
             double w = mode ? f16_round(prm[MLP_OFF_W3 + c * MLP_H + k]) : prm[MLP_OFF_W3 + c * MLP_H + k];
             s += w * h2[k];
         }
-        if (mode) { float af = (float)s; af = af + prm[MLP_OFF_B3 + c]; z[c] = af; }
-        else z[c] = s + prm[MLP_OFF_B3 + c];
+        if (mode) { float af = (float)s; af = af + prm[MLP_OFF_B3 + c]; af = af + 16.0f * x[c]; z[c] = af; }
+        else z[c] = s + prm[MLP_OFF_B3 + c] + 16.0 * (double)x[c];
     }
     if (h1o) for (int n = 0; n < MLP_H; ++n) h1o[n] = h1[n];
     if (h2o) for (int n = 0; n < MLP_H; ++n) h2o[n] = h2[n];
 }
 
-/* softmax with the count prior over the non-empty slots */
-static void prior_softmax(const double z[8], const double cnt[8], double pi[8])
+/* softmax over the non-empty slots (cnt > 0) */
+static void masked_softmax(const double z[8], const double cnt[8], double pi[8])
 {
     double zmax = -INFINITY, s = 0.0;
     for (int c = 0; c < MLP_OUT; ++c) if (cnt[c] > 0 && z[c] > zmax) zmax = z[c];
-    for (int c = 0; c < MLP_OUT; ++c) { pi[c] = cnt[c] > 0 ? cnt[c] * exp(z[c] - zmax) : 0.0; s += pi[c]; }
+    for (int c = 0; c < MLP_OUT; ++c) { pi[c] = cnt[c] > 0 ? exp(z[c] - zmax) : 0.0; s += pi[c]; }
     for (int c = 0; c < MLP_OUT; ++c) pi[c] /= s;
 }
 
-/* q_c for the (up to 8) children of internal node T */
-static void learned_q(const orc_tree* t, const float* prm, int64_t T, int64_t n_a, const double q[3], double qc[8],
+/* q_c for the (up to 8) children of internal node T: the network's softmax
+ * mixed with the uniform path index, q = (1 - lambda) pi + lambda n_c / n_T.
+ * The features enter the network as float32 values. */
+static void learned_q(const orc_tree* t, const float* prm, int64_t T, const double q[3], double qc[8],
                       int slot_of_child[8], int* nk)
 {
-    float qf[3] = {(float)q[0], (float)q[1], (float)q[2]};
-    float f[8];
+    double f[8];
+    float xf[8];
     double z[8], cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8];
-    mlp_features(t, T, n_a, qf, f);
-    mlp_forward(prm, f, 1, z, NULL, NULL);
+    mlp_features(t, T, q, f);
+    for (int k = 0; k < 8; ++k) xf[k] = (float)f[k];
+    mlp_forward(prm, xf, 1, z, NULL, NULL);
     *nk = t->nchild[T];
     for (int i = 0; i < t->nchild[T]; ++i) {
         int64_t ch = t->first_child[T] + i;
         slot_of_child[i] = t->digit[ch];
         cnt[t->digit[ch]] = (double)t->count[ch];
     }
-    prior_softmax(z, cnt, pi);
+    masked_softmax(z, cnt, pi);
     for (int i = 0; i < t->nchild[T]; ++i) {
         int s = slot_of_child[i];
         qc[i] = (1.0 - MLP_LAMBDA) * pi[s] + MLP_LAMBDA * cnt[s] / (double)t->count[T];
@@ -698,7 +709,6 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
     path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
     double tT = node_term(t, kp, a, q);
-    double n_a = (double)t->count[a];
     double p_sel = 1.0;             /* probability that the path index lies in T */
     double p_rr = 1.0;              /* running product of roulette probabilities */
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -733,7 +743,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 /* learned proposal: inverse-CDF selection over the slots with a 24-bit uniform */
                 double qv[8];
                 int slots[8], nk;
-                learned_q(t, prm, T, (int64_t)n_a, q, qv, slots, &nk);
+                learned_q(t, prm, T, q, qv, slots, &nk);
                 double u_sel = (double)(x_sel >> 8) * (1.0 / 16777216.0), cum = 0.0;
                 int ci = nk - 1;
                 for (int i = 0; i < nk; ++i) {
@@ -771,7 +781,6 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         po.sens += sens_step * wgt;
         po.steps += 1;
         p_sel *= q_c;
-        (void)n_a;
         if (c_node < 0) {                           /* moved onto a virtual point */
             po.end_begin = (int32_t)target;
             po.end_level = t->level[T] + 1;
@@ -853,7 +862,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
 /* V(a).  Exponential in nothing: one visit per node per query.             */
 /* ------------------------------------------------------------------------ */
 static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3], int64_t T, double tT,
-                         double ps, double pr, int rr_mode, const float* prm, int64_t n_a)
+                         double ps, double pr, int rr_mode, const float* prm)
 {
     int64_t nT = t->count[T];
     if (nT == 1) return 0.0;
@@ -867,12 +876,12 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         double delta = sum - tT;
         double qv[8];
         int slots[8], nk;
-        if (prm) learned_q(t, prm, T, n_a, q, qv, slots, &nk);
+        if (prm) learned_q(t, prm, T, q, qv, slots, &nk);
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
             double qc = prm ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
             double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / diam_c);
             double tc = node_term(t, kp, ch, q);
-            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prm, n_a));
+            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prm));
         }
     } else {
         double sum = 0.0;
@@ -902,7 +911,7 @@ void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, 
         for (int ci = 0; ci < t->nchild[0]; ++ci) {
             int64_t a = t->first_child[0] + ci;
             double cv = node_term(t, &kp, a, q);
-            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode, prm, t->count[a]);
+            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode, prm);
         }
         out[j] = F;
     }
@@ -942,11 +951,13 @@ void orc_refine_all(const orc_tree* t, const float* qry, int64_t n, int kernel, 
 /* Learned-proposal training support (batch entry points).                  */
 /* ------------------------------------------------------------------------ */
 
-/* Features for (node, query) pairs; n_a = count of each pair's subdomain. */
-void orc_mlp_features(const orc_tree* t, const int64_t* node, const int64_t* n_a, const float* qry, int64_t n,
-                      float* out)
+/* Features (float64) for (internal node, query) pairs. */
+void orc_mlp_features(const orc_tree* t, const int64_t* node, const float* qry, int64_t n, double* out)
 {
-    for (int64_t i = 0; i < n; ++i) mlp_features(t, node[i], n_a[i], &qry[3 * i], &out[8 * i]);
+    for (int64_t i = 0; i < n; ++i) {
+        double q[3] = {qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
+        mlp_features(t, node[i], q, &out[8 * i]);
+    }
 }
 
 /* Logits for a batch of feature rows (mode 1 binary16 emulation, 0 float64). */
@@ -955,9 +966,10 @@ void orc_mlp_forward(const float* prm, const float* x, int64_t n, int mode, doub
     for (int64_t i = 0; i < n; ++i) mlp_forward(prm, &x[8 * i], mode, &z[8 * i], NULL, NULL);
 }
 
-/* Mean soft cross-entropy  L = -(1/n) sum_i sum_c t_ic log pi_ic  over the
- * non-empty slots (cnt > 0) and its gradient with respect to the float32
- * parameters (float64 back-propagation through the forward of `mode`). */
+/* Mean soft cross-entropy  L = -(1/n) sum_i sum_c t_ic log pi_ic,  pi the
+ * softmax of the logits over the non-empty slots (cnt > 0), and its gradient
+ * with respect to the float32 parameters (float64 back-propagation through
+ * the forward of `mode`; the skip term has no parameters). */
 double orc_mlp_loss_grad(const float* prm, const float* x, const float* tgt, const float* cnt, int64_t n, int mode,
                          double* grad)
 {
@@ -967,7 +979,7 @@ double orc_mlp_loss_grad(const float* prm, const float* x, const float* tgt, con
         double z[8], h1[32], h2[32], pi[8], c8[8], dz[8], dh2[32], dh1[32], xin[8];
         mlp_forward(prm, &x[8 * i], mode, z, h1, h2);
         for (int c = 0; c < 8; ++c) c8[c] = cnt[8 * i + c];
-        prior_softmax(z, c8, pi);
+        masked_softmax(z, c8, pi);
         for (int c = 0; c < 8; ++c) {
             double tc = tgt[8 * i + c];
             if (c8[c] > 0) {
@@ -1040,12 +1052,12 @@ void orc_child_targets(const orc_tree* t, const int64_t* node, const float* qry,
  * word all ones keeps it apart from estimation streams; word 2*(step&1) of
  * the block selects), down to a leaf; every internal node on the way is one
  * (query, node) pair.  Layout [nq][d^3][lmax] with node = -1 for an unused
- * row; na = the path's subdomain count. */
-void orc_mlp_pairs(const orc_tree* t, int64_t nq, uint64_t seed, int lmax, int64_t* node_out, int64_t* na_out)
+ * row. */
+void orc_mlp_pairs(const orc_tree* t, int64_t nq, uint64_t seed, int lmax, int64_t* node_out)
 {
     int d3 = t->d * t->d * t->d;
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    for (int64_t i = 0; i < nq * d3 * lmax; ++i) { node_out[i] = -1; na_out[i] = 0; }
+    for (int64_t i = 0; i < nq * d3 * lmax; ++i) node_out[i] = -1;
     if (!is_internal(t, 0)) return;
     for (int64_t j = 0; j < nq; ++j) {
         for (int ci = 0; ci < t->nchild[0]; ++ci) {
@@ -1055,7 +1067,6 @@ void orc_mlp_pairs(const orc_tree* t, int64_t nq, uint64_t seed, int lmax, int64
             for (int k = 0; k < lmax && is_internal(t, T); ++k) {
                 int64_t row = (j * d3 + slot) * lmax + k;
                 node_out[row] = T;
-                na_out[row] = t->count[a];
                 uint32_t ctr[4] = {(uint32_t)j, (uint32_t)slot, (uint32_t)(k >> 1), 0xFFFFFFFFu}, rnd[4];
                 orc_philox4x32_10(ctr, key, rnd);
                 int64_t r = (int64_t)(((uint64_t)rnd[2 * (k & 1)] * (uint64_t)t->count[T]) >> 32);

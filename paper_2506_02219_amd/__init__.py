@@ -30,6 +30,16 @@ class EvalOpts(C.Structure):
                 ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("tree", C.c_void_p), ("queries", C.c_void_p), ("out", C.c_void_p), ("nq", C.c_int64),
+                ("kernel", C.c_int32), ("reserved", C.c_int32)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("tile_waves", C.c_int32), ("waves_per_simd", C.c_int32), ("heavy_first", C.c_int32),
+                ("ms", C.c_float)]
+
+
 class TreeDesc(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_nodes", C.c_int64), ("n_blocks", C.c_int64),
                 ("depth", C.c_int32), ("branching", C.c_int32), ("leaf_size", C.c_int32),
@@ -66,7 +76,7 @@ def lib():
         L.sbh_brute.restype = i32
         L.sbh_tree_info.argtypes = [P, P]
         L.sbh_tree_info.restype = i32
-        L.sbh_tree_export.argtypes = [P] + [P] * 11
+        L.sbh_tree_export.argtypes = [P] + [P] * 12
         L.sbh_tree_export.restype = i32
         L.sbh_mlp_forward.argtypes = [P, P, i64, P, P]
         L.sbh_mlp_forward.restype = i32
@@ -76,6 +86,14 @@ def lib():
         L.sbh_mlp_loss_grad.restype = i32
         L.sbh_mlp_train.argtypes = [P, P, P, P, P, i64, i32, i32, f32, i32, P, P]
         L.sbh_mlp_train.restype = i32
+        L.sbh_batch_create.argtypes = [P, i32, i32, P, P, P, P]
+        L.sbh_batch_create.restype = i32
+        L.sbh_batch_launch.argtypes = [P, u64, u32, P]
+        L.sbh_batch_launch.restype = i32
+        L.sbh_batch_get_config.argtypes = [P, P]
+        L.sbh_batch_get_config.restype = i32
+        L.sbh_batch_free.argtypes = [P]
+        L.sbh_batch_free.restype = i32
         L.sbh_free.argtypes = [P]
         L.sbh_free.restype = i32
         L.sbh_status_string.argtypes = [i32]
@@ -142,10 +160,12 @@ class Tree:
         a["dip"] = np.zeros((nn, 4), np.float32)
         a["perm"] = np.zeros(npt, np.uint32)
         a["codes"] = np.zeros(npt, np.uint64)
+        a["spread2"] = np.zeros(nn, np.float32)
         p = lambda x: x.ctypes.data_as(C.c_void_p)
         _check("sbh_tree_export", lib().sbh_tree_export(
             self._h, p(a["begin"]), p(a["count"]), p(a["level"]), p(a["digit"]), p(a["parent"]),
-            p(a["first_child"]), p(a["nchild"]), p(a["agg"]), p(a["dip"]), p(a["perm"]), p(a["codes"])))
+            p(a["first_child"]), p(a["nchild"]), p(a["agg"]), p(a["dip"]), p(a["perm"]), p(a["codes"]),
+            p(a["spread2"])))
         return a
 
     def free(self):
@@ -174,10 +194,11 @@ def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_leve
 
 
 def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
-             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None):
+             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None):
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
     paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records;
-    mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal."""
+    mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal (1);
+    proposal: 0 uniform path index, 1 learned (needs mlp), 2 score proposal (default: 1 with mlp, else 0)."""
     import torch
     _dev(queries, "queries", (3,))
     nq = queries.shape[0]
@@ -192,7 +213,9 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
         _dev(mlp, "mlp")
         if tuple(mlp.shape) != (MLP_NPARAM,):
             raise ValueError("mlp must have shape [MLP_NPARAM]")
-    o = EvalOpts(eps, alpha, group, rr_mode, 0 if mlp is None else 1, batch,
+    if proposal is None:
+        proposal = 0 if mlp is None else 1
+    o = EvalOpts(eps, alpha, group, rr_mode, int(proposal), batch,
                  None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr())
     _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
                                       C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
@@ -292,6 +315,52 @@ def sbh_mlp_train(params, adam_state, features, targets, counts, steps, batch_ro
                                                 _ptr(counts), n, int(steps), int(batch_rows), float(lr), int(step0),
                                                 _stream(stream), _ptr(losses)))
     return losses
+
+
+class Batch:
+    """A batch plan (sbh_batch*): trees, query sets and outputs of many clouds evaluated by one
+    persistent launch replayed from a HIP graph.  Keeps references to its trees and tensors."""
+
+    def __init__(self, trees, queries, kernels, samples=1, group=64, eps=1e-3, alpha=100.0, rr_mode=0,
+                 config=None, outs=None, stream=None):
+        import torch
+        if not (len(trees) == len(queries) == len(kernels)):
+            raise ValueError("trees, queries and kernels must have the same length")
+        self.trees, self.queries = list(trees), list(queries)
+        self.outs = list(outs) if outs is not None else [torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
+                                                          for q in queries]
+        items = (BatchItem * len(trees))()
+        for i, (t, q, k, o) in enumerate(zip(self.trees, self.queries, kernels, self.outs)):
+            _dev(q, "queries", (3,)); _dev(o, "out")
+            if o.shape[0] != q.shape[0]:
+                raise ValueError("each output must have one value per query")
+            items[i] = BatchItem(t.handle, q.data_ptr(), o.data_ptr(), q.shape[0], int(k), 0)
+        o = EvalOpts(eps, alpha, group, rr_mode, 0, 0, None, None)
+        cfg = None if config is None else BatchConfig(*config, 0.0)
+        h = C.c_void_p()
+        _check("sbh_batch_create", lib().sbh_batch_create(items, len(trees), int(samples), C.byref(o),
+                                                          None if cfg is None else C.byref(cfg), _stream(stream),
+                                                          C.byref(h)))
+        self._h = h
+        c = BatchConfig()
+        _check("sbh_batch_get_config", lib().sbh_batch_get_config(self._h, C.byref(c)))
+        self.config = dict(tile_waves=c.tile_waves, waves_per_simd=c.waves_per_simd, heavy_first=c.heavy_first,
+                           ms=c.ms)
+
+    def launch(self, seed=0, batch=0, stream=None):
+        _check("sbh_batch_launch", lib().sbh_batch_launch(self._h, C.c_uint64(seed), batch, _stream(stream)))
+        return self.outs
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().sbh_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def sbh_free(tree: Tree):

@@ -7,8 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "sbh_internal.hpp"
 
@@ -39,8 +41,8 @@ sbh_status hip_fail(hipError_t e, const char* where)
 
 void free_impl(sbh::sbh_tree_impl* t)
 {
-    void* bufs[] = {t->pts, t->pdip, t->perm, t->codes, t->nbegin, t->ncount, t->nlevel, t->ndigit, t->nparent,
-                    t->nfirst, t->nnchild, t->nagg, t->ndip, t->bagg, t->bdip, t->btopo};
+    void* bufs[] = {t->pts,  t->pdip, t->perm, t->codes, t->nbegin, t->ncount, t->nlevel, t->ndigit, t->nparent,
+                    t->nfirst, t->nnchild, t->nagg, t->ndip, t->nspr, t->bagg, t->bdip, t->bspr, t->btopo};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -58,7 +60,7 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (!(o.alpha > 0.0f) || !std::isfinite(o.alpha)) return fail(SBH_EINVAL, "alpha must be finite and > 0");
     if (o.group < 1) return fail(SBH_EINVAL, "group must be >= 1");
     if (o.rr_mode < 0 || o.rr_mode > 2) return fail(SBH_EINVAL, "rr_mode must be 0, 1 or 2");
-    if (o.proposal != 0 && o.proposal != 1) return fail(SBH_EINVAL, "proposal must be 0 or 1");
+    if (o.proposal < 0 || o.proposal > 2) return fail(SBH_EINVAL, "proposal must be 0, 1 or 2");
     if (o.proposal == 1 && !o.mlp) return fail(SBH_EINVAL, "the learned proposal needs opts->mlp");
     return SBH_OK;
 }
@@ -167,12 +169,13 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     e.eps = o.eps;
     e.alpha = o.alpha;
     e.paths = samples > 0 ? o.paths : nullptr;
-    const bool learned = samples > 0 && o.proposal == 1;
-    if (learned && t->d != 2) return fail(SBH_EUNSUPPORTED, "sbh_eval: the learned proposal needs branching 2");
+    const bool learned = samples > 0 && o.proposal != 0;
+    if (learned && t->d != 2) return fail(SBH_EUNSUPPORTED, "sbh_eval: proposals 1 and 2 need branching 2");
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;
     if (samples == 0) err = sbh::launch_bh_eval(t, queries, nq, e, out, stream);
-    else if (learned && !root_leaf) err = sbh::launch_sbh_learned(t, queries, nq, e, o.mlp, out, stream);
+    else if (learned && !root_leaf)
+        err = sbh::launch_sbh_learned(t, queries, nq, e, o.proposal == 1 ? o.mlp : nullptr, out, stream);
     else err = sbh::launch_sbh_eval(t, queries, nq, e, out, stream);
     if (err != hipSuccess) return hip_fail(err, "sbh_eval: kernel launch");
     return SBH_OK;
@@ -220,7 +223,7 @@ sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info)
 
 sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count, int32_t* level, int32_t* digit,
                            int32_t* parent, int32_t* first_child, int32_t* nchild, float* agg, float* dip,
-                           uint32_t* perm, uint64_t* codes)
+                           uint32_t* perm, uint64_t* codes, float* spread2)
 {
     if (!tree) return fail(SBH_EINVAL, "sbh_tree_export: tree is NULL");
     const sbh::sbh_tree_impl& t = tree->impl;
@@ -233,7 +236,7 @@ sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count,
         {begin, t.nbegin, nn * 4},      {count, t.ncount, nn * 4},       {level, t.nlevel, nn * 4},
         {digit, t.ndigit, nn * 4},      {parent, t.nparent, nn * 4},     {first_child, t.nfirst, nn * 4},
         {nchild, t.nnchild, nn * 4},    {agg, t.nagg, nn * 16},          {dip, t.ndip, nn * 16},
-        {perm, t.perm, np * 4},         {codes, t.codes, np * 8},
+        {perm, t.perm, np * 4},         {codes, t.codes, np * 8},        {spread2, t.nspr, nn * 4},
     };
     for (const Item& it : items) {
         if (!it.dst) continue;
@@ -343,6 +346,253 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
     const hipError_t f = hipFreeAsync(work, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: kernel launch");
     if (f != hipSuccess) return hip_fail(f, "sbh_mlp_train: workspace release");
+    return SBH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched persistent evaluation
+// ---------------------------------------------------------------------------
+struct sbh_batch {
+    int device = 0;
+    int samples = 1;
+    sbh_eval_opts opts{};
+    std::vector<sbh::BatchItem> clouds;   // as given (item_begin filled per configuration)
+    std::vector<double> cost;             // work estimate per cloud
+    sbh::BatchItem* d_items[2] = {nullptr, nullptr};   // d = 2 and d = 4 groups
+    int n_items[2] = {0, 0};
+    uint32_t total[2] = {0u, 0u};
+    sbh::BatchState* d_state = nullptr;   // [2]
+    sbh_batch_config cfg{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t begin_node = nullptr;
+};
+
+namespace {
+
+void batch_release(sbh_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int g = 0; g < 2; ++g)
+        if (b->d_items[g]) (void)hipFree(b->d_items[g]);
+    if (b->d_state) (void)hipFree(b->d_state);
+}
+
+// device descriptors for a configuration: clouds split by branching factor,
+// ordered as the configuration asks, with the prefix of their work items
+hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
+{
+    std::vector<int> order(b->clouds.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    if (c.heavy_first)
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+    for (int g = 0; g < 2; ++g) {
+        std::vector<sbh::BatchItem> v;
+        int64_t next = 0;
+        for (int i : order) {
+            sbh::BatchItem it = b->clouds[i];
+            if (it.d != (g == 0 ? 2 : 4) || it.nq == 0) continue;
+            it.item_begin = next;
+            const int64_t tiles = (it.nq + 63) / 64;
+            next += (tiles + c.tile_waves - 1) / c.tile_waves;
+            v.push_back(it);
+        }
+        b->n_items[g] = (int)v.size();
+        b->total[g] = (uint32_t)next;
+        if (!v.empty()) {
+            const hipError_t e = hipMemcpy(b->d_items[g], v.data(), v.size() * sizeof(sbh::BatchItem),
+                                           hipMemcpyHostToDevice);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t batch_enqueue(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_t s)
+{
+    hipError_t e = sbh::launch_batch_begin(b->d_state, seed, batch, s);
+    const int blocks = 256 * b->cfg.waves_per_simd;   // 256 CUs; a block of 4 wavefronts puts one on each SIMD
+    for (int g = 0; g < 2 && e == hipSuccess; ++g)
+        if (b->total[g] > 0)
+            e = sbh::launch_sbh_batch(g == 0 ? 2 : 4, b->d_items[g], b->n_items[g], b->total[g], b->cfg.tile_waves,
+                                      blocks, b->d_state + g, b->samples, b->opts.group, b->opts.rr_mode,
+                                      b->opts.eps, b->opts.alpha, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t samples, const sbh_eval_opts* opts,
+                            const sbh_batch_config* config, hipStream_t stream, sbh_batch** out)
+{
+    if (!items || !out) return fail(SBH_EINVAL, "sbh_batch_create: NULL argument");
+    if (count < 1 || count > (1 << 20)) return fail(SBH_EINVAL, "sbh_batch_create: count must be in [1, 2^20]");
+    if (samples < 1) return fail(SBH_EINVAL, "sbh_batch_create: samples must be >= 1");
+    sbh_eval_opts o;
+    sbh_eval_opts_default(&o);
+    o.group = 64;
+    if (opts) o = *opts;
+    if (check_eval_opts(o) != SBH_OK) return SBH_EINVAL;
+    if (o.group % 64 != 0) return fail(SBH_EINVAL, "sbh_batch_create: group must be a multiple of 64");
+    if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: only the uniform proposal is batched");
+    if (o.paths) return fail(SBH_EINVAL, "sbh_batch_create: path records are not available in a batch");
+    if (config) {
+        if (config->tile_waves < 1 || config->tile_waves > 1024)
+            return fail(SBH_EINVAL, "sbh_batch_create: tile_waves must be in [1, 1024]");
+        if (config->waves_per_simd < 1 || config->waves_per_simd > 8)
+            return fail(SBH_EINVAL, "sbh_batch_create: waves_per_simd must be in [1, 8]");
+        if (config->heavy_first != 0 && config->heavy_first != 1)
+            return fail(SBH_EINVAL, "sbh_batch_create: heavy_first must be 0 or 1");
+    }
+    int64_t tiles_total = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const sbh_batch_item& it = items[i];
+        if (!it.tree) return fail(SBH_EINVAL, "sbh_batch_create: item %d has no tree", i);
+        if (it.nq < 0 || it.nq >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_batch_create: item %d: bad nq", i);
+        if (it.nq > 0 && (!it.queries || !it.out))
+            return fail(SBH_EINVAL, "sbh_batch_create: item %d: queries and out must not be NULL", i);
+        if (check_kernel(it.kernel) != SBH_OK) return SBH_EINVAL;
+        if (it.kernel == SBH_WINDING && !it.tree->impl.has_normals)
+            return fail(SBH_EINVAL, "sbh_batch_create: item %d: the winding kernel needs normals", i);
+        tiles_total += (it.nq + 63) / 64;
+    }
+    if (tiles_total >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_batch_create: too many queries");
+    sbh_batch* b = new (std::nothrow) sbh_batch();
+    if (!b) return fail(SBH_ENOMEM, "sbh_batch_create: host allocation");
+    b->samples = samples;
+    b->opts = o;
+    (void)hipGetDevice(&b->device);
+    for (int32_t i = 0; i < count; ++i) {
+        const sbh::sbh_tree_impl* t = &items[i].tree->impl;
+        sbh::BatchItem it{};
+        it.tv = sbh::make_view(t);
+        it.queries = items[i].queries;
+        it.out = items[i].out;
+        it.nq = items[i].nq;
+        it.kernel = items[i].kernel;
+        it.d = t->d;
+        it.root_leaf = it.tv.root_internal ? 0 : 1;
+        b->clouds.push_back(it);
+        b->cost.push_back((double)it.nq * (double)(t->depth + 1) * (it.kernel == SBH_WINDING ? 1.5 : 1.0) * samples);
+    }
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < 2 && e == hipSuccess; ++g)
+        e = hipMalloc((void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, 2 * sizeof(sbh::BatchState));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        batch_release(b);
+        delete b;
+        return hip_fail(e, "sbh_batch_create: allocation");
+    }
+    if (config) {
+        b->cfg = *config;
+        b->cfg.ms = 0.0f;
+    } else {
+        // autotune: time every candidate on the batch itself (outputs are written)
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        float best = INFINITY;
+        sbh_batch_config best_cfg{1, 8, 1, 0.0f};
+        const int tws[] = {1, 2, 4, 8};
+        const int wpss[] = {4, 8};
+        for (int heavy = 0; heavy < 2 && e == hipSuccess; ++heavy)
+            for (int tw : tws)
+                for (int wps : wpss) {
+                    if (e != hipSuccess) break;
+                    sbh_batch_config c{tw, wps, heavy, 0.0f};
+                    b->cfg = c;
+                    e = batch_upload(b, c);
+                    if (e == hipSuccess) e = batch_enqueue(b, 0, 0, stream);   // warm-up
+                    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+                    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = batch_enqueue(b, 0, 0, stream);
+                    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.0f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e == hipSuccess && ms / 3.0f < best) {
+                        best = ms / 3.0f;
+                        best_cfg = c;
+                        best_cfg.ms = best;
+                    }
+                }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        b->cfg = best_cfg;
+    }
+    if (e == hipSuccess) e = batch_upload(b, b->cfg);
+    // capture the launch sequence once; sbh_batch_launch replays it
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t le = batch_enqueue(b, 0, 0, b->cap);
+        e = hipStreamEndCapture(b->cap, &b->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+        size_t n = 0;
+        e = hipGraphGetNodes(b->graph, nullptr, &n);
+        std::vector<hipGraphNode_t> nodes(n);
+        if (e == hipSuccess && n > 0) e = hipGraphGetNodes(b->graph, nodes.data(), &n);
+        for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nodes[i], &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(nodes[i], &kp) == hipSuccess && kp.func == sbh::batch_begin_kernel())
+                b->begin_node = nodes[i];
+        }
+        if (e == hipSuccess && !b->begin_node) e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        batch_release(b);
+        delete b;
+        return hip_fail(e, "sbh_batch_create: tuning or graph capture");
+    }
+    *out = b;
+    return SBH_OK;
+}
+
+sbh_status sbh_batch_launch(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_t stream)
+{
+    if (!b) return fail(SBH_EINVAL, "sbh_batch_launch: NULL plan");
+    sbh::BatchState* st = b->d_state;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), bw = batch;
+    void* args[] = {&st, &k0, &k1, &bw};
+    hipKernelNodeParams kp{};
+    kp.func = sbh::batch_begin_kernel();
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->begin_node, &kp);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "sbh_batch_launch");
+    return SBH_OK;
+}
+
+sbh_status sbh_batch_get_config(const sbh_batch* b, sbh_batch_config* cfg)
+{
+    if (!b || !cfg) return fail(SBH_EINVAL, "sbh_batch_get_config: NULL argument");
+    *cfg = b->cfg;
+    return SBH_OK;
+}
+
+sbh_status sbh_batch_free(sbh_batch* b)
+{
+    if (!b) return SBH_OK;
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    delete b;
     return SBH_OK;
 }
 

@@ -480,7 +480,8 @@ __global__ void k_set_base(const uint32_t* __restrict__ cscan_prev, int n_int_pr
 __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ nbegin,
                             const int32_t* __restrict__ ncount, const int32_t* __restrict__ nfirst,
                             const int32_t* __restrict__ nnchild, const float4* __restrict__ pts,
-                            const float4* __restrict__ pdip, float4* __restrict__ nagg, float4* __restrict__ ndip)
+                            const float4* __restrict__ pdip, float4* __restrict__ nagg, float4* __restrict__ ndip,
+                            float* __restrict__ nspr)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -502,18 +503,40 @@ __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ 
             if (ndip) { const float4 q = ndip[c]; dx += q.x; dy += q.y; dz += q.z; }
         }
     }
-    nagg[g] = make_float4(sx / m, sy / m, sz / m, m);
+    const float cx = sx / m, cy = sy / m, cz = sz / m;
+    nagg[g] = make_float4(cx, cy, cz, m);
     if (ndip) ndip[g] = make_float4(dx, dy, dz, 0.0f);
+    // second moment about the centre of mass: from the points of a leaf, from
+    // the children of an internal node (parallel axes: every term >= 0)
+    float s2 = 0.f;
+    if (f < 0) {
+        const int32_t b = nbegin[g], e = b + ncount[g];
+        for (int32_t s = b; s < e; ++s) {
+            const float4 p = pts[s];
+            const float ex = p.x - cx, ey = p.y - cy, ez = p.z - cz;
+            s2 += p.w * (ex * ex + ey * ey + ez * ez);
+        }
+    } else {
+        const int32_t e = f + nnchild[g];
+        for (int32_t c = f; c < e; ++c) {
+            const float4 a = nagg[c];
+            const float ex = a.x - cx, ey = a.y - cy, ez = a.z - cz;
+            s2 += a.w * (nspr[c] + (ex * ex + ey * ey + ez * ez));
+        }
+    }
+    nspr[g] = s2 / m;
 }
 
 __global__ void k_pack(int32_t n_nodes, const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
-                       const float4* __restrict__ nagg, const float4* __restrict__ ndip, float4* __restrict__ bagg,
-                       float4* __restrict__ bdip, int d3)
+                       const float4* __restrict__ nagg, const float4* __restrict__ ndip,
+                       const float* __restrict__ nspr, float4* __restrict__ bagg, float4* __restrict__ bdip,
+                       float* __restrict__ bspr, int d3)
 {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x + 1;
     if (g >= n_nodes) return;
     const int64_t slot = (int64_t)npblk[g] * d3 + ndig[g];
     bagg[slot] = nagg[g];
+    bspr[slot] = nspr[g];
     if (bdip) bdip[slot] = ndip[g];
 }
 
@@ -738,6 +761,7 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     SBH_TRY(hipMalloc(&t->nnchild, n_nodes * 4), "allocating nodes");
     SBH_TRY(hipMalloc(&t->nagg, n_nodes * sizeof(float4)), "allocating nodes");
     if (nrm) SBH_TRY(hipMalloc(&t->ndip, n_nodes * sizeof(float4)), "allocating nodes");
+    SBH_TRY(hipMalloc(&t->nspr, n_nodes * sizeof(float)), "allocating nodes");
     int32_t* npblk = tmp.alloc<int32_t>(n_nodes);
     SBH_ALLOC_OK("allocating parent blocks");
     {
@@ -763,6 +787,8 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     SBH_TRY(hipMalloc(&t->bagg, (size_t)nbk * d3 * sizeof(float4)), "allocating blocks");
     SBH_TRY(hipMemsetAsync(t->btopo, 0, (size_t)nbk * ts * sizeof(uint32_t), s), "blocks clear");
     SBH_TRY(hipMemsetAsync(t->bagg, 0, (size_t)nbk * d3 * sizeof(float4), s), "blocks clear");
+    SBH_TRY(hipMalloc(&t->bspr, (size_t)nbk * d3 * sizeof(float)), "allocating blocks");
+    SBH_TRY(hipMemsetAsync(t->bspr, 0, (size_t)nbk * d3 * sizeof(float), s), "blocks clear");
     if (nrm) {
         SBH_TRY(hipMalloc(&t->bdip, (size_t)nbk * d3 * sizeof(float4)), "allocating blocks");
         SBH_TRY(hipMemsetAsync(t->bdip, 0, (size_t)nbk * d3 * sizeof(float4), s), "blocks clear");
@@ -780,13 +806,13 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         for (int l = 0; l < n_levels; ++l) off[l + 1] = off[l] + lv[l].n;
         for (int l = n_levels - 1; l >= 0; --l) {
             k_aggregate<<<nblk(lv[l].n), 256, 0, s>>>((int32_t)off[l], lv[l].n, t->nbegin, t->ncount, t->nfirst,
-                                                      t->nnchild, t->pts, t->pdip, t->nagg, t->ndip);
+                                                      t->nnchild, t->pts, t->pdip, t->nagg, t->ndip, t->nspr);
             SBH_TRY(hipGetLastError(), "aggregate kernel");
         }
     }
     if (n_nodes > 1) {
-        k_pack<<<nblk(n_nodes - 1), 256, 0, s>>>((int32_t)n_nodes, npblk, t->ndigit, t->nagg, t->ndip, t->bagg,
-                                                 t->bdip, d3);
+        k_pack<<<nblk(n_nodes - 1), 256, 0, s>>>((int32_t)n_nodes, npblk, t->ndigit, t->nagg, t->ndip, t->nspr,
+                                                 t->bagg, t->bdip, t->bspr, d3);
         SBH_TRY(hipGetLastError(), "pack kernel");
     }
     SBH_TRY(hipStreamSynchronize(s), "build sync");

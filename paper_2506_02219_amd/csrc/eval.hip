@@ -51,6 +51,7 @@ TreeView make_view(const sbh_tree_impl* t)
     v.pdip = t->pdip;
     v.bagg = t->bagg;
     v.bdip = t->bdip;
+    v.bspr = t->bspr;
     v.btopo = t->btopo;
     v.nagg = t->nagg;
     v.ndip = t->ndip;
@@ -407,13 +408,14 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     return acc;
 }
 
+// One wavefront-tile of 64 consecutive queries (j = 64 wave + lane) with the
+// shared walk; used by the single-tree kernel and by the batched kernel.
 template <int D, int K, bool TRACE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq,
-                                                  SbhArgs a, float* __restrict__ out)
+__device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
+                                              const SbhArgs& a, float* __restrict__ out, int64_t wave)
 {
     constexpr int D3 = D * D * D;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t j0 = wave * 64;
     if (j0 >= nq) return;
     const int64_t j = j0 + lane;
@@ -467,6 +469,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(F) + logwbar) / a.alpha;
         else out[j] = F;
     }
+}
+
+template <int D, int K, bool TRACE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
+{
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    sbh_wave_tile<D, K, TRACE>(tv, queries, nq, a, out, wave);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,11 +578,9 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
 
 // A tree whose root is a leaf: every query is summed exactly over its points.
 template <int K>
-__global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __restrict__ queries, int64_t nq,
-                                                    float eps2, float alpha, float* __restrict__ out)
+__device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float* __restrict__ queries, int64_t j,
+                                                 float eps2, float alpha, float* __restrict__ out)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nq) return;
     const float qx = queries[3 * j], qy = queries[3 * j + 1], qz = queries[3 * j + 2];
     KParams kp{eps2, alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
@@ -586,6 +594,80 @@ __global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __
         acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
     if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(acc) + logwbar) / alpha;
     else out[j] = acc;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                    float eps2, float alpha, float* __restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nq) return;
+    leaf_exact_query<K>(tv, queries, j, eps2, alpha, out);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent evaluation: many trees and query sets in one launch.
+// A work item is a run of `wpi` wavefront-tiles (64 queries each) of one
+// cloud; every wavefront takes items from a global counter until none are
+// left, so that small clouds fill the machine together and large ones are
+// split.  Each tile runs exactly the code of the single-tree kernels, so a
+// cloud's results do not depend on the batch around it.
+// ---------------------------------------------------------------------------
+// key, batch word and a cleared work counter for both branching-factor groups
+__global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint32_t batch)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 2) {
+        st[threadIdx.x].key0 = key0;
+        st[threadIdx.x].key1 = key1;
+        st[threadIdx.x].batch = batch;
+        st[threadIdx.x].counter = 0u;
+    }
+}
+
+template <int D, int K>
+__device__ __forceinline__ void batch_tile_k(const BatchItem& it, const SbhArgs& a, int64_t wave)
+{
+    if (it.root_leaf) {
+        const int64_t j = wave * 64 + (threadIdx.x & 63);
+        if (j < it.nq) leaf_exact_query<K>(it.tv, it.queries, j, a.eps2, a.alpha, it.out);
+    } else {
+        sbh_wave_tile<D, K, false>(it.tv, it.queries, it.nq, a, it.out, wave);
+    }
+}
+
+// one launch per branching factor present in the batch (items of the other
+// branching factor are given no work items by the host)
+template <int D>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+k_sbh_batch(const BatchItem* __restrict__ items, int count, uint32_t total_items, int wpi, BatchState* st,
+            SbhArgs base)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t t = 0u;
+        if (lane == 0) t = atomicAdd(&st->counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= total_items) break;   // every wavefront ends here once the counter has passed the last item
+        int lo = 0, hi = count - 1;    // the last cloud whose first item is <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].item_begin <= (int64_t)t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchItem it = items[lo];
+        SbhArgs a = base;
+        a.key0 = st->key0;
+        a.key1 = st->key1;
+        a.batch = st->batch;
+        const int64_t w0 = ((int64_t)t - it.item_begin) * wpi;
+        for (int w = 0; w < wpi; ++w) {
+            const int64_t wave = w0 + w;
+            if (wave * 64 >= it.nq) break;
+            if (it.kernel == SBH_POTENTIAL) batch_tile_k<D, SBH_POTENTIAL>(it, a, wave);
+            else if (it.kernel == SBH_WINDING) batch_tile_k<D, SBH_WINDING>(it, a, wave);
+            else batch_tile_k<D, SBH_SMOOTHDIST>(it, a, wave);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -659,5 +741,22 @@ hipError_t launch_bh_eval(const sbh_tree_impl* t, const float* queries, int64_t 
     const TreeView tv = make_view(t);
     SBH_DISPATCH(launch_bh_dk, t, tv, queries, nq, e, out, s);
 }
+
+hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hipStream_t s)
+{
+    k_batch_begin<<<1, 64, 0, s>>>(st, (uint32_t)seed, (uint32_t)(seed >> 32), batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbh_batch(int d, const BatchItem* items, int count, uint32_t total_items, int wpi, int blocks,
+                            BatchState* st, int samples, int group, int rr_mode, float eps, float alpha, hipStream_t s)
+{
+    SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
+    if (d == 2) k_sbh_batch<2><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a);
+    else k_sbh_batch<4><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a);
+    return hipGetLastError();
+}
+
+void* batch_begin_kernel() { return reinterpret_cast<void*>(&k_batch_begin); }
 
 }  // namespace sbh

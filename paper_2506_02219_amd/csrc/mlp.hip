@@ -3,11 +3,15 @@
 //
 // The paper draws the path index uniformly and leaves importance sampling
 // open (Section 3.3); Theorem 1 holds for any child distribution with
-// q_c > 0.  The network turns features of (node, query) into one logit per
-// child slot; the proposal is
-//   pi_c = n_c exp(z_c) / sum_c' n_c' exp(z_c')   over non-empty slots,
+// q_c > 0.  At an internal node the network sees one feature per child slot,
+// the log of the child's quadrupole score relative to its siblings,
+//   score_c = m_c s_c^2 / (|p_c - q|^2 + s_c^2)^(3/2),  f_c = max(-1, ln(score_c / max score) / 16)
+// (m_c weight, p_c centre of mass, s_c^2 second moment; f = -1 for an empty
+// slot), and returns logits z = W3 h2 + b3 + 16 f.  The proposal is
+//   pi_c = exp(z_c) / sum_c' exp(z_c')   over non-empty slots,
 //   q_c  = (1 - 1/8) pi_c + (1/8) n_c / n_T,
-// so an all-zero network is the uniform path index and every non-empty child
+// so an all-zero network samples in proportion to the scores (the "score"
+// proposal, which also runs without the network) and every non-empty child
 // keeps q_c >= n_c / (8 n_T).
 //
 // Parameters: float32 [1608] = W1[32][8] b1[32] W2[32][32] b2[32] W3[8][32]
@@ -78,8 +82,9 @@ __device__ __forceinline__ h4 bias_relu_h(f4 d, const float* b)
     return h;
 }
 
-// Logits of every lane's own sample (features f[8]) for the whole wavefront:
-// four groups of 16 samples, eight MFMAs each.  All 64 lanes must be active.
+// Logits z = W3 h2 + b3 + 16 f of every lane's own sample (features f[8]) for
+// the whole wavefront: four groups of 16 samples, eight MFMAs each.  All 64
+// lanes must be active.
 __device__ __forceinline__ void mlp_forward_wave(const MlpRegs& R, const float f[8], float z[8], int lane)
 {
     const int r = lane & 15, hi = lane >> 4;
@@ -109,40 +114,34 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpRegs& R, const float f
             }
         }
     }
+    for (int k = 0; k < 8; ++k) z[k] += 16.0f * f[k];   // the features pass straight to the logits
 }
 
-// Features of (node T, query q) in a fixed float32 operation order: every
-// operation rounded to nearest even on its own (no contraction into FMA),
-// division and square root correctly rounded.
-__device__ __forceinline__ void mlp_features(const TreeView& tv, int level, uint32_t ix, uint32_t iy, uint32_t iz,
-                                             uint32_t nT, uint32_t n_a, float dip_norm, float qx, float qy, float qz,
-                                             float f[8])
+// Features of (internal node, query q) from the node's child block: the
+// relative log quadrupole score of each slot, -1 for empty slots (and for
+// every slot when all scores are 0).
+__device__ __forceinline__ void score_features(const float4* __restrict__ ba, const float* __restrict__ bs,
+                                               const uint32_t cnt[8], float qx, float qy, float qz, float f[8])
 {
-#pragma clang fp contract(off)
-    const float h = ldexpf(tv.side, -level - 1);   // d = 2: one octree level per tree level
-    const float cx = tv.lo[0] + (float)(2u * ix + 1u) * h;
-    const float cy = tv.lo[1] + (float)(2u * iy + 1u) * h;
-    const float cz = tv.lo[2] + (float)(2u * iz + 1u) * h;
-    const float rx = (qx - cx) / h;
-    const float ry = (qy - cy) / h;
-    const float rz = (qz - cz) / h;
-    const float rho = __builtin_sqrtf((rx * rx + ry * ry) + rz * rz);
-    const float den = 1.0f + rho;
-    f[0] = rx / den;
-    f[1] = ry / den;
-    f[2] = rz / den;
-    f[3] = rho / den;
-    f[4] = (float)level / (float)tv.max_level;
-    f[5] = (float)nT / (float)n_a;
-    f[6] = dip_norm;
-    f[7] = fminf(rho, 16.0f) / 16.0f;
-}
-
-// |sum w n| / sum w of an aggregate, float32 (0 for trees without normals)
-__device__ __forceinline__ float dipole_ratio(float4 agg, float4 dip)
-{
-#pragma clang fp contract(off)
-    return __builtin_sqrtf((dip.x * dip.x + dip.y * dip.y) + dip.z * dip.z) / agg.w;
+    float sc[8];
+    float smax = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 a = ba[c];
+        const float s2 = bs[c];
+        const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+        const float x = dx * dx + dy * dy + dz * dz + s2;
+        const float r = x > 0.0f ? __frsqrt_rn(x) : 0.0f;
+        const float v = cnt[c] ? a.w * s2 * (r * r * r) : 0.0f;
+        sc[c] = v;
+        smax = fmaxf(smax, v);
+    }
+    const float inv = smax > 0.0f ? 1.0f / smax : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        f[c] = sc[c] >= smax && smax > 0.0f ? 0.0f
+             : sc[c] > 0.0f                 ? fmaxf(-1.0f, __logf(sc[c] * inv) * 0.0625f)
+                                            : -1.0f;
 }
 
 // q_c for the eight slots from the logits and the slot counts; empty slots 0.
@@ -153,11 +152,11 @@ __device__ __forceinline__ void learned_probs(const float z[8], const uint32_t c
         if (cnt[c]) zmax = fmaxf(zmax, z[c]);
     float e[8], s = 0.0f;
     for (int c = 0; c < 8; ++c) {
-        e[c] = cnt[c] ? (float)cnt[c] * expf(z[c] - zmax) : 0.0f;
+        e[c] = cnt[c] ? __expf(z[c] - zmax) : 0.0f;
         s += e[c];
     }
-    const float inv = 1.0f / s, fn = (float)nT;
-    for (int c = 0; c < 8; ++c) qv[c] = cnt[c] ? (1.0f - kLambda) * e[c] * inv + kLambda * (float)cnt[c] / fn : 0.0f;
+    const float inv = 1.0f / s, fn = 1.0f / (float)nT;
+    for (int c = 0; c < 8; ++c) qv[c] = cnt[c] ? (1.0f - kLambda) * e[c] * inv + kLambda * (float)cnt[c] * fn : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -202,6 +201,7 @@ struct TrainLds {
     _Float16 w3[16 * 32];   // W3 padded to 16 outputs
     _Float16 x[64 * 16], h1[64 * 32], h2[64 * 32], dz[64 * 16], dh2[64 * 32], dh1[64 * 32];
     float zf[64 * 16], dh2f[64 * 32], dh1f[64 * 32];
+    float xf[64 * 8];   // float32 features (skip term)
 };
 
 constexpr int kGradStride = 1608 + 8;   // partial-gradient row: 1608 parameters, then the loss
@@ -228,7 +228,9 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ prm, 
         tg[k] = valid ? Tg[8 * row + k] : 0.0f;
         cn[k] = valid ? Cn[8 * row + k] : 0.0f;
         csum += cn[k];
-        S.x[l * 16 + k] = valid ? (_Float16)X[8 * row + k] : (_Float16)0.0f;
+        const float xv = valid ? X[8 * row + k] : 0.0f;
+        S.xf[l * 8 + k] = xv;
+        S.x[l * 16 + k] = (_Float16)xv;
         S.x[l * 16 + 8 + k] = (_Float16)0.0f;
     }
     valid = valid && csum > 0.0f;
@@ -256,10 +258,17 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ prm, 
         __syncthreads();
         f4 o = mfma_lds(S.w3, 32, 1, S.h2 + s0 * 32, 1, 32, zero);
         o = mfma_lds(S.w3 + 16, 32, 1, S.h2 + s0 * 32 + 16, 1, 32, o);
-        for (int i = 0; i < 4; ++i) S.zf[(s0 + r) * 16 + q + i] = o[i] + (q + i < 8 ? prm[kOffB3 + q + i] : 0.0f);
+        for (int i = 0; i < 4; ++i) {
+            float v = 0.0f;
+            if (q + i < 8) {
+                v = o[i] + prm[kOffB3 + q + i];
+                v = v + 16.0f * S.xf[(s0 + r) * 8 + q + i];
+            }
+            S.zf[(s0 + r) * 16 + q + i] = v;
+        }
         __syncthreads();
     }
-    // loss and dL/dz for this lane's row: soft cross-entropy against the count-prior softmax
+    // loss and dL/dz for this lane's row: soft cross-entropy against the softmax over non-empty slots
     float loss = 0.0f;
     {
         float zmax = -INFINITY;
@@ -267,7 +276,7 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ prm, 
             if (cn[c] > 0.0f) zmax = fmaxf(zmax, S.zf[l * 16 + c]);
         float e[8], s = 0.0f;
         for (int c = 0; c < 8; ++c) {
-            e[c] = cn[c] > 0.0f ? cn[c] * expf(S.zf[l * 16 + c] - zmax) : 0.0f;
+            e[c] = cn[c] > 0.0f ? expf(S.zf[l * 16 + c] - zmax) : 0.0f;
             s += e[c];
         }
         for (int c = 0; c < 16; ++c) {
@@ -404,9 +413,7 @@ __global__ void k_mlp_pairs(TreeView tv, const float* __restrict__ queries, int6
         nint += ((int)rt[c] > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
     }
     int32_t blk = (int32_t)rt[8] + nint;
-    uint32_t nT = n_a, ix = slot & 1, iy = (slot >> 1) & 1, iz = (slot >> 2) & 1;
-    float4 dipT = tv.bdip ? tv.bdip[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 aggT = tv.bagg[slot];
+    uint32_t nT = n_a;
     int level = 1;
     u32x4 rnd = {0u, 0u, 0u, 0u};
     for (int k = 0; k < lmax; ++k) {
@@ -421,39 +428,31 @@ __global__ void k_mlp_pairs(TreeView tv, const float* __restrict__ queries, int6
             nT = 0u;
             continue;
         }
-        float f[8];
-        mlp_features(tv, level, ix, iy, iz, nT, n_a, tv.bdip ? dipole_ratio(aggT, dipT) : 0.0f, qx, qy, qz, f);
         const uint32_t* bt = tv.btopo + (int64_t)blk * topo_stride(8);
+        uint32_t cnt[8];
+        for (int c = 0; c < 8; ++c) cnt[c] = bt[c];
+        float f[8];
+        score_features(tv.bagg + (int64_t)blk * 8, tv.bspr + (int64_t)blk * 8, cnt, qx, qy, qz, f);
         for (int c = 0; c < 8; ++c) {
             X[8 * row + c] = f[c];
-            Cn[8 * row + c] = (float)bt[c];
+            Cn[8 * row + c] = (float)cnt[c];
         }
         loc[row] = make_int4(blk, (int32_t)beginT, (int32_t)nT, level);
         if ((k & 1) == 0) rnd = philox4x32_10((uint32_t)j, (uint32_t)slot, (uint32_t)(k >> 1), 0xFFFFFFFFu, key0, key1);
         const uint32_t r = __umulhi((k & 1) ? rnd.z : rnd.x, nT);
-        uint32_t pre = 0u;
-        int32_t ni = 0;
-        int csel = 0;
-        uint32_t preC = 0u, nC = 0u;
-        int32_t niC = 0;
+        uint32_t pre = 0u, preC = 0u, nC = 0u;
+        int32_t ni = 0, niC = 0;
         for (int c = 0; c < 8; ++c) {
-            const uint32_t cnt = bt[c];
-            const bool hit = (r - pre) < cnt;
-            csel = hit ? c : csel;
+            const bool hit = (r - pre) < cnt[c];
             preC = hit ? pre : preC;
             niC = hit ? ni : niC;
-            nC = hit ? cnt : nC;
-            ni += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
-            pre += cnt;
+            nC = hit ? cnt[c] : nC;
+            ni += ((int)cnt[c] > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+            pre += cnt[c];
         }
-        aggT = tv.bagg[(int64_t)blk * 8 + csel];
-        if (tv.bdip) dipT = tv.bdip[(int64_t)blk * 8 + csel];
         beginT += preC;
         nT = nC;
         blk = (int32_t)bt[8] + niC;
-        ix = 2u * ix + (csel & 1);
-        iy = 2u * iy + ((csel >> 1) & 1);
-        iz = 2u * iz + ((csel >> 2) & 1);
         ++level;
     }
 }
@@ -527,14 +526,16 @@ __global__ void __launch_bounds__(256) k_mlp_targets(TreeView tv, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// Estimator with the learned proposal (d = 2).  Lanes as in the per-query
-// kernel (8 queries x 8 subdomain slots per wavefront, every lane its own
-// path); the walk is a wavefront-uniform loop so that the network runs on
-// MFMA for all 64 lanes at once, every step at which some lane stands on an
-// internal node.  Internal nodes: inverse-CDF selection of a slot from q_c
-// with a 24-bit uniform; leaves: uniform point as in the plain estimator.
-// The swap of a step is weighted by 1 / (prod q * prod p) (Eq. (7) with
-// p(I in T) the product of the selection probabilities).
+// Estimator with the learned (NET) or score proposal (d = 2).  Lanes as in
+// the per-query kernel (8 queries x 8 subdomain slots per wavefront, every
+// lane its own path); the walk is a wavefront-uniform loop so that the
+// network runs on MFMA for all 64 lanes at once, every step at which some
+// lane stands on an internal node.  At an internal node the child block is
+// scanned first (its terms give the swap, its aggregates the features), then
+// a slot is drawn by inverse CDF from q_c with a 24-bit uniform, then the
+// roulette of Eq. (5); at a leaf a point is drawn uniformly.  The swap of a
+// step is weighted by 1 / (prod q * prod p) (Eq. (7) with p(I in T) the
+// product of the selection probabilities).
 // ---------------------------------------------------------------------------
 struct LearnArgs {
     int32_t samples;
@@ -547,7 +548,7 @@ struct LearnArgs {
     const float* prm;
 };
 
-template <int K, bool TRACE>
+template <int K, bool TRACE, bool NET>
 __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* __restrict__ queries, int64_t nq,
                                                      LearnArgs a, float* __restrict__ out)
 {
@@ -558,7 +559,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
     const int slot = lane & 7;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t j = wave * 8 + (lane >> 3);
-    if (wave * 8 >= nq) return;
+    if (wave * 8 >= nq) return;   // whole wavefront past the end
     const bool valid = j < nq;
     float qx = 0.f, qy = 0.f, qz = 0.f;
     if (valid) {
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         qz = queries[3 * j + 2];
     }
     MlpRegs R;
-    mlp_load_regs(R, a.prm, lane);
+    if constexpr (NET) mlp_load_regs(R, a.prm, lane);
     KParams kp{a.eps2, a.alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
@@ -590,7 +591,6 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
     if (tv.bdip) dip_a = tv.bdip[slot];
     const float cv = n_a ? term<K>(agg_a, (K == SBH_WINDING) ? dip_a : zero4, qx, qy, qz, kp, r0) : 0.0f;
     const uint32_t stream = (uint32_t)(a.group == 1 ? j : j / a.group);
-    const float fna = (float)n_a;
     float fa = 0.0f;
     u32x4 rnd = {0u, 0u, 0u, 0u};
     for (int s = 0; s < a.samples; ++s) {
@@ -599,9 +599,8 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         int32_t blk = blk_a;
         int level = 1;
         float diamT = tv.diam0 * 0.5f;
-        float4 aggT = agg_a, dipT = dip_a;
+        float4 aggT = agg_a;
         float tT = cv, prr = 1.0f, psel = 1.0f, acc = 0.0f;
-        uint32_t ix = slot & 1, iy = (slot >> 1) & 1, iz = (slot >> 2) & 1;
         int steps = 0, flag = 0;
         int32_t end_b = (int32_t)beginT, end_l = level;
         const uint32_t ctr1 = (uint32_t)(slot * a.samples + s);
@@ -617,25 +616,39 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
             const uint32_t xsel = (k & 1) ? rnd.z : rnd.x;
             const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
             const bool internal = act && (int)nT > tv.leaf_size && level < tv.max_level;
-            float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (__ballot(internal) != 0ull) {
-                float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                if (internal)
-                    mlp_features(tv, level, ix, iy, iz, nT, n_a, tv.bdip ? dipole_ratio(aggT, dipT) : 0.0f, qx, qy,
-                                 qz, f);
-                mlp_forward_wave(R, f, z, lane);
-            }
-            if (!act) continue;
             const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
             const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
-            float4 aggC, dipC = zero4;
+            uint32_t cnt[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+            float tv8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float sumc = 0.0f;
+            if (internal) {
+                // the child block: terms for the swap, scores for the proposal
+                const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+#pragma unroll
+                for (int c = 0; c < D3; ++c) {
+                    cnt[c] = bt[c];
+                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                    const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                    tv8[c] = cnt[c] ? v : 0.0f;
+                    sumc += tv8[c];
+                }
+                score_features(ba, tv.bspr + (int64_t)blk * D3, cnt, qx, qy, qz, f);
+            }
+            float z[8];
+            if constexpr (NET) {
+                if (__ballot(internal) != 0ull) mlp_forward_wave(R, f, z, lane);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) z[c] = 16.0f * f[c];
+            }
+            if (!act) continue;
+            float4 aggC;
             uint32_t nC = 1u, beginC;
             int32_t blkC = 0;
             int csel = 0;
-            float qsel;
+            float qsel, tC = 0.0f;
             if (internal) {
-                uint32_t cnt[8];
-                for (int c = 0; c < 8; ++c) cnt[c] = bt[c];
                 float qv[8];
                 learned_probs(z, cnt, nT, qv);
                 const float u_sel = (float)(xsel >> 8) * 5.9604644775390625e-8f;
@@ -645,7 +658,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 uint32_t pre = 0u, preC = 0u, preL = 0u, nL = 0u;
                 int32_t ni = 0, niC = 0, niL = 0;
                 int last = 0;
-                float qL = 0.0f;
+                float qL = 0.0f, tL = 0.0f;
                 bool found = false;
                 nC = 0u;
                 qsel = 0.0f;
@@ -657,6 +670,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                     niL = ne ? ni : niL;
                     nL = ne ? cnt[c] : nL;
                     qL = ne ? qv[c] : qL;
+                    tL = ne ? tv8[c] : tL;
                     cum += qv[c];
                     const bool hit = !found && ne && u_sel < cum;
                     csel = hit ? c : csel;
@@ -664,6 +678,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                     niC = hit ? ni : niC;
                     nC = hit ? cnt[c] : nC;
                     qsel = hit ? qv[c] : qsel;
+                    tC = hit ? tv8[c] : tC;
                     found = found || hit;
                     ni += ((int)cnt[c] > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
                     pre += cnt[c];
@@ -674,9 +689,9 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                     niC = niL;
                     nC = nL;
                     qsel = qL;
+                    tC = tL;
                 }
                 aggC = ba[csel];
-                if (tv.bdip) dipC = tv.bdip[(int64_t)blk * D3 + csel];
                 beginC = beginT + preC;
                 blkC = (int32_t)bt[D3] + niC;
             } else {
@@ -704,26 +719,11 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 act = false;
                 continue;
             }
-            float sumc = 0.0f, tC = 0.0f;
-            if (internal) {
-                const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-#pragma unroll
-                for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = bt[c];
-                    const float4 g = ba[c];
-                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                    const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                    const float vv = cnt ? v : 0.0f;
-                    sumc += vv;
-                    tC = (c == csel) ? vv : tC;
-                }
-            } else {
+            if (!internal) {   // leaf: its points are the virtual children
                 for (uint32_t i = 0; i < nT; ++i) {
                     const float4 g = tv.pts[beginT + i];
                     const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
-                    const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                    sumc += v;
-                    tC = (i == (uint32_t)csel) ? v : tC;
+                    sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
                 }
             }
             prr *= p;
@@ -738,16 +738,12 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 continue;
             }
             aggT = aggC;
-            dipT = dipC;
             tT = tC;
             nT = nC;
             beginT = beginC;
             blk = blkC;
             ++level;
             diamT *= 0.5f;
-            ix = 2u * ix + (csel & 1);
-            iy = 2u * iy + ((csel >> 1) & 1);
-            iz = 2u * iz + ((csel >> 2) & 1);
         }
         if constexpr (TRACE) {
             if (valid)
@@ -756,7 +752,6 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         }
         fa += acc;
     }
-    (void)fna;
     float val = n_a ? cv + fa / (float)a.samples : 0.0f;
 #pragma unroll
     for (int o = 1; o < D3; o <<= 1) val += __shfl_xor(val, o);
@@ -824,14 +819,20 @@ hipError_t launch_sbh_learned(const sbh_tree_impl* t, const float* queries, int6
                 e.eps * e.eps, e.alpha, e.paths, prm};
     const int64_t waves = (nq + 7) / 8;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-#define SBH_LAUNCH_L(KK)                                                             \
-    do {                                                                             \
-        if (e.paths) k_sbh_learned<KK, true><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);  \
-        else k_sbh_learned<KK, false><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);         \
+#define SBH_LAUNCH_L(KK, NN)                                                                     \
+    do {                                                                                         \
+        if (e.paths) k_sbh_learned<KK, true, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);  \
+        else k_sbh_learned<KK, false, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);         \
     } while (0)
-    if (e.kernel == SBH_POTENTIAL) SBH_LAUNCH_L(SBH_POTENTIAL);
-    else if (e.kernel == SBH_WINDING) SBH_LAUNCH_L(SBH_WINDING);
-    else SBH_LAUNCH_L(SBH_SMOOTHDIST);
+#define SBH_LAUNCH_K(NN)                                        \
+    do {                                                        \
+        if (e.kernel == SBH_POTENTIAL) SBH_LAUNCH_L(SBH_POTENTIAL, NN);    \
+        else if (e.kernel == SBH_WINDING) SBH_LAUNCH_L(SBH_WINDING, NN);   \
+        else SBH_LAUNCH_L(SBH_SMOOTHDIST, NN);                  \
+    } while (0)
+    if (prm) SBH_LAUNCH_K(true);
+    else SBH_LAUNCH_K(false);
+#undef SBH_LAUNCH_K
 #undef SBH_LAUNCH_L
     return hipGetLastError();
 }

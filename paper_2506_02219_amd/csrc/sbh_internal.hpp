@@ -5,12 +5,14 @@
 //   pdip   float4[M]         sorted w*n (winding only)
 //   Nodes, breadth-first, Morton order within a level (for export/build):
 //     nbegin/ncount/nlevel/ndigit/nparent/nfirst/nnchild int32[n_nodes]
-//     nagg float4[n_nodes] (centre of mass, weight), ndip float4[n_nodes]
+//     nagg float4[n_nodes] (centre of mass, weight), ndip float4[n_nodes],
+//     nspr float[n_nodes] (second moment sum w |p - com|^2 / weight)
 //   Child blocks, one per internal node, in breadth-first order of the
 //   internal nodes (the root's block is block 0):
 //     bagg   float4[n_blocks][d^3]   aggregate of the child in digit slot s
 //                                    (zero for an empty slot)
 //     bdip   float4[n_blocks][d^3]   summed w*n per slot (winding only)
+//     bspr   float[n_blocks][d^3]    second moment per slot (zero for an empty slot)
 //     btopo  uint32[n_blocks][TS]    point count per slot, then at [d^3] the
 //                                    block id of the first internal child;
 //                                    the internal children of one node hold
@@ -37,6 +39,7 @@ struct TreeView {
     const float4* pdip;
     const float4* bagg;
     const float4* bdip;
+    const float* bspr;
     const uint32_t* btopo;
     const float4* nagg;   // nagg[0] = root aggregate
     const float4* ndip;
@@ -60,7 +63,9 @@ struct sbh_tree_impl {
     uint64_t* codes;
     int32_t *nbegin, *ncount, *nlevel, *ndigit, *nparent, *nfirst, *nnchild;
     float4 *nagg, *ndip;
+    float* nspr;
     float4 *bagg, *bdip;
+    float* bspr;
     uint32_t* btopo;
 };
 
@@ -178,6 +183,23 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
                            int max_level, hipStream_t s, sbh_tree_impl* t, std::string* msg);
 
 TreeView make_view(const sbh_tree_impl* t);
+
+// batched persistent evaluation (eval.hip)
+struct BatchItem {          // one cloud of a batch (device copy)
+    TreeView tv;
+    const float* queries;
+    float* out;
+    int64_t nq;
+    int64_t item_begin;     // index of the cloud's first work item
+    int32_t kernel, d, root_leaf, pad;
+};
+struct BatchState {         // per-launch key and batch word, and the work counter (one per branching group)
+    uint32_t key0, key1, batch, counter;
+};
+hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hipStream_t s);
+hipError_t launch_sbh_batch(int d, const BatchItem* items, int count, uint32_t total_items, int wpi, int blocks,
+                            BatchState* st, int samples, int group, int rr_mode, float eps, float alpha, hipStream_t s);
+void* batch_begin_kernel();
 
 // learned proposal (mlp.hip)
 constexpr int kMlpParams = 1608;

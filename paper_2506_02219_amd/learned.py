@@ -3,12 +3,14 @@
 Section 3.3 samples the path index uniformly; Theorem 1 only needs every
 child to keep a positive probability, so the estimator stays unbiased under
 any proposal that is divided out.  The network (8 features -> 32 -> 32 -> 8
-logits, ReLU) is trained to put the probability of each child in proportion
-to the share of the node's refinement error (Eqs. (3)-(4)) that the child
-carries: targets are the per-child residuals |sum over the child's points -
-the child's aggregate term|, computed exactly on the GPU along uniform
-paths.  The loss is the soft cross-entropy between those shares and the
-count-weighted softmax of the logits; the optimiser is Adam.
+logits, ReLU, plus 16 times the features) takes each child's relative log
+quadrupole score and is trained to put the probability of each child in
+proportion to the share of the node's refinement error (Eqs. (3)-(4)) that
+the child carries: targets are the per-child residuals |sum over the child's
+points - the child's aggregate term|, computed exactly on the GPU along
+uniform paths.  The loss is the soft cross-entropy between those shares and
+the softmax of the logits over the non-empty children; the optimiser is
+Adam.  With a zero output layer the network is the score proposal.
 
 Argument marshalling and row bookkeeping only: features, targets, forward,
 backward and the Adam step all run in libsbh's kernels.

@@ -68,6 +68,12 @@ def compare_trees(gt, ot):
     dip = ot.agg[:, 4:7]
     dscale = np.maximum(np.linalg.norm(dip, axis=1, keepdims=True), mass[:, None] * 1e-3)
     assert np.all(np.abs(g["dip"][:, 0:3] - dip) <= 2e-5 * dscale + 1e-12)
+    # second moments: sums of non-negative float32 terms (1e-4 relative), and offsets p - com
+    # taken from float32 coordinates: an error delta of a few ulps of the coordinates moves
+    # |p - com|^2 by about 2 s delta + delta^2
+    s2 = ot.spread2
+    delta = 2.0 ** -21 * (np.abs(ot.agg[:, :3]).max(axis=1) + float(ot.side))
+    assert np.all(np.abs(g["spread2"] - s2) <= 1e-4 * s2 + 4 * np.sqrt(s2) * delta + 4 * delta ** 2)
     return g
 
 
@@ -106,24 +112,27 @@ def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
 
 def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, eps=1e-3, alpha=100.0,
               index=None, gpu_out=None, gpu_paths=None, batch=0, mlp=None, near_tie=NEAR_TIE,
-              max_divergent=1e-5):
+              max_divergent=1e-5, proposal=None):
     """Run (or take) the GPU estimator and compare with the oracle, query by query.
     With `index`, `queries` are a subset of a larger set evaluated on the GPU
     (gpu_out/gpu_paths are the full-set outputs).  mlp: float32 network
-    parameters (numpy) for the learned proposal on both sides."""
+    parameters (numpy) for the learned proposal on both sides; proposal=2 runs the
+    score proposal on the GPU against the oracle's all-zero network."""
     d3 = gt.branching ** 3
     if gpu_out is None:
         q = T(queries)
         paths = torch.full((queries.shape[0], d3, samples, 4), -7, dtype=torch.int32, device=DEV)
         out = P.sbh_eval(gt, q, kernel, samples=samples, seed=seed, eps=eps, alpha=alpha, group=group,
-                         rr_mode=rr_mode, paths=paths, batch=batch, mlp=None if mlp is None else T(mlp))
+                         rr_mode=rr_mode, paths=paths, batch=batch, mlp=None if mlp is None else T(mlp),
+                         proposal=proposal)
         g = host(out)
         gp = host(paths)
     else:
         g = gpu_out[index]
         gp = gpu_paths[index]
     r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps, alpha=alpha,
-               paths=True, index=index, batch=batch, params=mlp)
+               paths=True, index=index, batch=batch,
+               params=np.zeros(oracle.MLP_NPARAM, np.float32) if proposal == 2 else mlp)
     near = r["margin"] < near_tie
     path_bad = np.any(gp != r["paths"], axis=(1, 2, 3))
     ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha, r["sens"])

@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("sbh_build", "sbh_eval", "sbh_brute", "sbh_free", "sbh_tree_info", "sbh_tree_export",
               "sbh_status_string", "sbh_last_error", "sbh_build_opts_default", "sbh_eval_opts_default",
-              "sbh_mlp_forward", "sbh_mlp_pairs", "sbh_mlp_loss_grad", "sbh_mlp_train"):
+              "sbh_mlp_forward", "sbh_mlp_pairs", "sbh_mlp_loss_grad", "sbh_mlp_train",
+              "sbh_batch_create", "sbh_batch_launch", "sbh_batch_get_config", "sbh_batch_free"):
         assert n in names
 
 
@@ -56,7 +57,9 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [("sbh_build_opts", None), ("sbh_eval_opts", None), ("sbh_eval_opts", "paths"),
               ("sbh_eval_opts", "mlp"), ("sbh_eval_opts", "batch"), ("sbh_tree_desc", None),
-              ("sbh_tree_desc", "lo"), ("sbh_tree_desc", "inv_side")]
+              ("sbh_tree_desc", "lo"), ("sbh_tree_desc", "inv_side"), ("sbh_batch_item", None),
+              ("sbh_batch_item", "nq"), ("sbh_batch_item", "kernel"), ("sbh_batch_config", None),
+              ("sbh_batch_config", "ms")]
     exprs = ", ".join(f"(long)sizeof({s})" if f is None else f"(long)offsetof({s}, {f})" for s, f in fields)
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sbh.h\"\n"
                    f"int main(void) {{ long v[] = {{{exprs}}}; for (int i = 0; i < {len(fields)}; ++i) "
@@ -66,7 +69,9 @@ def test_struct_layouts_match_header(tmp_path):
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(P.BuildOpts), ctypes.sizeof(P.EvalOpts), P.EvalOpts.paths.offset, P.EvalOpts.mlp.offset,
-            P.EvalOpts.batch.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset]
+            P.EvalOpts.batch.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset,
+            ctypes.sizeof(P.BatchItem), P.BatchItem.nq.offset, P.BatchItem.kernel.offset, ctypes.sizeof(P.BatchConfig),
+            P.BatchConfig.ms.offset]
     assert got == want
 
 
@@ -90,3 +95,11 @@ def test_argument_errors_before_any_device_work():
     one = ctypes.c_void_p(1)
     assert L.sbh_eval(one, one, 1, 0, 2.0, 1, 0, ctypes.byref(o), None, one) == -1
     assert b"mlp" in L.sbh_last_error()
+    h = ctypes.c_void_p()
+    assert L.sbh_batch_create(None, 1, 1, None, None, None, ctypes.byref(h)) == -1
+    items = (P.BatchItem * 1)()
+    assert L.sbh_batch_create(items, 0, 1, None, None, None, ctypes.byref(h)) == -1
+    assert L.sbh_batch_create(items, 1, 1, None, None, None, ctypes.byref(h)) == -1   # no tree
+    assert b"no tree" in L.sbh_last_error()
+    assert L.sbh_batch_launch(None, 0, 0, None) == -1
+    assert L.sbh_batch_free(None) == 0

@@ -1,11 +1,12 @@
 """GPU parity of the learned child proposal: MFMA network, training rows,
-loss gradient, Adam training and the estimator that uses it.
+loss gradient, Adam training and the estimators that use it (learned and
+score proposals).
 
 Section 3.3 draws the path index uniformly; the learned proposal replaces
 that draw by q_c > 0 (Theorem 1 still holds).  Tolerances:
-  - features, counts, row locations and the valid mask: bit-exact (the same
-    float32 operation order on both sides), the dipole feature to 8 float32
-    ulps (float32 vs float64 node aggregates);
+  - counts, row locations and the valid mask: bit-exact;
+  - features (relative log scores in [-1, 0]): 2e-6 absolute (float32 scores
+    from float32 aggregates against float64);
   - targets: the residual |exact - LOD| of a child is a difference of nearly
     equal sums when the child is far away, and the GPU takes the child's
     aggregate from float32 storage (the oracle's is float64).  Rounding the
@@ -20,11 +21,15 @@ that draw by q_c > 0 (Theorem 1 still holds).  Tolerances:
     plus float32 rounding; 99% of rows within 1e-5 (1 + |z|);
   - gradient: deltas in binary16 (relative 2^-11 each): relative L2 error
     below 5e-3, loss to 1e-4;
-  - estimator with an exactly representable network (logits identical on
-    both sides): the strict bar of the uniform estimator; with a general
-    network: at most 1% of queries may take a different child where the
-    oracle's selection margin |u - sum q| is below 5e-3 (a logit flip as
-    above), every other query to the uniform estimator's bar.
+  - estimator with the score proposal or an exactly representable network
+    (logits that differ only by the float32 rounding of the features, about
+    1e-6): values to the uniform estimator's bar; a query may take another
+    child only where the oracle's smallest margin (roulette or selection,
+    |u - sum q|) is below 1e-5.  A query makes about 40 selections with up to
+    7 boundaries each, so such near-ties are more frequent than for the
+    uniform estimator: at most 0.3% of queries may diverge;
+  - with a general network: at most 1% of queries may take a different child
+    where the margin is below 5e-3 (a logit flip as above).
 """
 import math
 
@@ -114,15 +119,14 @@ def test_training_rows_match_oracle(kind):
     X, Tg, Cn, where = host(X), host(Tg), host(Cn), host(where)
     Xo, Tgo, Cno, valid = ot.training_set(q, kernel, seed=seed)
     assert np.array_equal(where[:, 0] >= 0, valid)
-    nd, _ = ot.mlp_pairs(q.shape[0], seed)
+    nd = ot.mlp_pairs(q.shape[0], seed)
     node = nd.reshape(-1)[valid]
     assert np.array_equal(where[valid, 1], ot.begin[node])
     assert np.array_equal(where[valid, 2], ot.count[node])
     assert np.array_equal(where[valid, 3], ot.level[node])
     assert np.array_equal(Cn, Cno)
-    assert np.array_equal(X[:, [0, 1, 2, 3, 4, 5, 7]], Xo[:, [0, 1, 2, 3, 4, 5, 7]])
-    ulp = np.spacing(np.abs(Xo[:, 6]).astype(np.float32))
-    assert np.all(np.abs(X[:, 6] - Xo[:, 6]) <= 8 * ulp)
+    assert np.all(np.abs(X - Xo) <= 2e-6), float(np.abs(X - Xo).max())
+    assert np.all(X[valid] >= -1) and np.all(X[valid].max(axis=1) == 0)
     assert np.all(X[~valid] == 0) and np.all(Tg[~valid] == 0)
     terr = np.abs(Tg - Tgo).max(axis=1)[valid]
     assert np.all(terr <= 4e-3), float(terr.max())
@@ -203,10 +207,9 @@ def test_training_lowers_the_loss_on_real_rows():
     losses = torch.zeros(300, device=DEV)
     P.sbh_mlp_train(p, st, X, Tg, Cn, steps=300, batch_rows=1024, lr=3e-3, losses=losses)
     after = float(host(P.sbh_mlp_loss_grad(p, X, Tg, Cn))[1608])
-    # the cross-entropy is bounded below by the targets' entropy: compare the KL parts
-    t = host(Tg).astype(np.float64)
-    H = float(np.mean(np.sum(np.where(t > 0, -t * np.log(np.where(t > 0, t, 1.0)), 0.0), axis=1)))
-    assert after - H < 0.8 * (before - H), (before, after, H)
+    # the start is the score proposal (zero output layer); training must improve on it
+    print(dict(before=before, after=after))
+    assert after < before - 1e-3, (before, after)
     assert np.all(np.isfinite(host(losses)))
 
 
@@ -215,15 +218,16 @@ def test_estimator_exact_network_strict_parity(samples, group):
     cl = W.c1()
     gt, ot = build_both(cl.sources, cl.weights)
     prm = dyadic_constant_params(41)
-    st = check_sbh(gt, ot, cl.queries[:1500], P.POTENTIAL, samples=samples, seed=5, group=group, mlp=prm)
-    assert st["path_mismatch"] <= 1
+    print(check_sbh(gt, ot, cl.queries[:1500], P.POTENTIAL, samples=samples, seed=5, group=group, mlp=prm,
+                    max_divergent=3e-3))
 
 
 @pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST])
 def test_estimator_exact_network_surface_kernels(kernel):
     pts, nrm, w, q = surface_cloud()
     gt, ot = build_both(pts, w, nrm)
-    check_sbh(gt, ot, q[:1000], kernel, samples=2, seed=6, alpha=20.0, mlp=dyadic_constant_params(42))
+    print(check_sbh(gt, ot, q[:1000], kernel, samples=2, seed=6, alpha=20.0, mlp=dyadic_constant_params(42),
+                    max_divergent=3e-3))
 
 
 @pytest.mark.parametrize("rr_mode", [1, 2])
@@ -231,7 +235,20 @@ def test_estimator_exact_network_roulette_ablations(rr_mode):
     cl = W.c1()
     gt, ot = build_both(cl.sources, cl.weights)
     check_sbh(gt, ot, cl.queries[:800], P.POTENTIAL, samples=1, seed=7, rr_mode=rr_mode,
-              mlp=dyadic_constant_params(43))
+              mlp=dyadic_constant_params(43), max_divergent=3e-3)
+
+
+@pytest.mark.parametrize("kernel", [P.POTENTIAL, P.WINDING])
+@pytest.mark.parametrize("samples,group", [(1, 1), (3, 5)])
+def test_score_proposal_parity(kernel, samples, group):
+    """Proposal 2 (no network) against the oracle's all-zero network."""
+    if kernel == P.POTENTIAL:
+        cl = W.c1()
+        src, w, nrm, q = cl.sources, cl.weights, None, cl.queries[:2000]
+    else:
+        src, nrm, w, q = surface_cloud()
+    gt, ot = build_both(src, w, nrm)
+    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=9, group=group, proposal=2, max_divergent=3e-3))
 
 
 @pytest.mark.parametrize("kind", ["cube", "surface"])

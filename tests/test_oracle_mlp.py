@@ -4,10 +4,15 @@ index, which Section 3.3 leaves open).
 - binary16 rounding: against NumPy's float16 conversion (an independent
   implementation of IEEE round-to-nearest-even);
 - loss gradient: against central finite differences in float64;
-- an all-zero network reduces the proposal to the uniform path index, and the
-  exact expectation with ANY network still equals Eq. (1) (Theorem 1 holds
-  for every child distribution with q_c > 0);
-- the sampled mean with a random network converges to Eq. (1);
+- the child score m s^2 / (r^2 + s^2)^(3/2) behind the features: second
+  moments recomputed from the points, and the score bounds the true residual
+  of a far child (the quadrupole term of the 1/r multipole expansion about
+  the centre of mass, whose dipole term vanishes);
+- the exact expectation with ANY network still equals Eq. (1) (Theorem 1
+  holds for every child distribution with q_c > 0), and the sampled mean
+  with a random network converges to it;
+- the zero network (proposal in proportion to the scores) lowers the
+  estimator's variance on a surface against the uniform path index;
 - training targets: recomputed by brute force with NumPy.
 """
 import math
@@ -37,12 +42,13 @@ def test_f16_round_matches_numpy_float16():
     assert np.array_equal(ours, ref) or np.all((ours == ref) | (np.isnan(ours) & np.isnan(ref)))
 
 
-def test_mlp_zero_network_gives_bias_logits():
+def test_mlp_zero_network_gives_bias_plus_skip_logits():
     prm = np.zeros(oracle.MLP_NPARAM, np.float32)
     prm[-8:] = np.arange(8) * 0.25
     x = np.random.Generator(np.random.PCG64(2)).uniform(-1, 1, (5, 8)).astype(np.float32)
-    for mode in (0, 1):
-        assert np.array_equal(oracle.mlp_forward(prm, x, mode), np.tile(np.arange(8) * 0.25, (5, 1)))
+    b = np.tile(np.arange(8, dtype=np.float32) * np.float32(0.25), (5, 1))
+    assert np.array_equal(oracle.mlp_forward(prm, x, 1), (b + np.float32(16) * x).astype(np.float64))
+    assert np.array_equal(oracle.mlp_forward(prm, x, 0), b.astype(np.float64) + 16.0 * x.astype(np.float64))
 
 
 def test_mlp_gradient_matches_finite_differences():
@@ -74,14 +80,83 @@ def _surface_tree(m=180, seed=21, d=2, leaf=3):
     return pts, nrm, w, oracle.Tree(pts, w, nrm, d=d, leaf_size=leaf)
 
 
-def test_zero_network_is_the_uniform_proposal():
+def test_second_moments_match_numpy():
     pts, nrm, w, t = _surface_tree()
-    q = np.random.Generator(np.random.PCG64(5)).uniform(-1.4, 1.4, (25, 3)).astype(np.float32)
+    P = pts[t.perm].astype(np.float64); Wt = w[t.perm].astype(np.float64)
+    for i in range(t.n_nodes):
+        b, n = t.begin[i], t.count[i]
+        com = (Wt[b:b + n, None] * P[b:b + n]).sum(0) / Wt[b:b + n].sum()
+        s2 = (Wt[b:b + n] * ((P[b:b + n] - com) ** 2).sum(1)).sum() / Wt[b:b + n].sum()
+        assert abs(t.spread2[i] - s2) <= 1e-12 * max(s2, 1e-300) + 1e-300
+
+
+def _scores(t, T, q):
+    """score of each child slot from the exported aggregates (nan for empty slots)"""
+    sc = np.full(8, np.nan)
+    for ch in range(t.first_child[T], t.first_child[T] + t.nchild[T]):
+        r2 = np.sum((t.agg[ch, :3] - q) ** 2)
+        s2 = t.spread2[ch]
+        sc[t.digit[ch]] = t.agg[ch, 3] * s2 / (r2 + s2) ** 1.5
+    return sc
+
+
+def test_score_bounds_the_residual_of_far_children():
+    """|sum_c f - f(LOD_c)| <= m s^2 / r^3 (1 + O(R/r)) for the 1/r kernel: the quadrupole
+    term of the expansion about the centre of mass is at most m s^2 / r^3, and R/r < 1/8 keeps
+    the higher orders under a 1.5 factor.  The bound is also not loose by orders of magnitude."""
+    cl = W.uniform_cube(3000, 0, 17)
+    t = oracle.Tree(cl.sources, cl.weights, d=2, leaf_size=8)
+    P = cl.sources[t.perm].astype(np.float64); Wt = cl.weights[t.perm].astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(18))
+    ratios = []
+    for T in np.nonzero(t.internal)[0][:40]:
+        for _ in range(3):
+            q = t.agg[T, :3] + rng.normal(size=3) * 0 + rng.choice([-1, 1], 3) * rng.uniform(2, 6, 3)
+            sc = _scores(t, T, q)
+            for ch in range(t.first_child[T], t.first_child[T] + t.nchild[T]):
+                b, n = t.begin[ch], t.count[ch]
+                rad = np.sqrt(((P[b:b + n] - t.agg[ch, :3]) ** 2).sum(1)).max()
+                r = np.sqrt(((t.agg[ch, :3] - q) ** 2).sum())
+                if n < 2 or r < 8 * rad:
+                    continue
+                ex = np.sum(Wt[b:b + n] / np.sqrt(((P[b:b + n] - q) ** 2).sum(1) + 1e-6))
+                lod = t.agg[ch, 3] / np.sqrt(r * r + 1e-6)
+                res = abs(ex - lod)
+                assert res <= 1.5 * sc[t.digit[ch]] + 1e-12 * lod
+                ratios.append(res / sc[t.digit[ch]])
+    assert len(ratios) > 100 and np.median(ratios) > 0.05
+
+
+def test_features_are_relative_log_scores():
+    pts, nrm, w, t = _surface_tree()
+    q = np.random.Generator(np.random.PCG64(5)).uniform(-1.4, 1.4, (30, 3)).astype(np.float32)
+    nodes = np.nonzero(t.internal)[0][:30]
+    f = t.mlp_features(nodes, q)
+    for i, T in enumerate(nodes):
+        sc = _scores(t, T, q[i].astype(np.float64))
+        ne = ~np.isnan(sc)
+        want = np.full(8, -1.0)
+        if np.nanmax(sc) > 0:
+            with np.errstate(divide="ignore"):
+                want[ne] = np.maximum(-1.0, np.log(sc[ne] / np.nanmax(sc)) / 16)
+        assert np.allclose(f[i], want, rtol=0, atol=1e-12)
+        assert f[i].max() == 0.0 or np.all(f[i] == -1.0)
+
+
+def test_score_proposal_lowers_the_variance_on_a_surface():
+    """The zero network samples in proportion to the scores: on a surface its per-query
+    spread over seeds is clearly below the uniform path index's."""
+    pts, nrm, w, _ = W.star_surface(4000, 33, level=4)
+    t = oracle.Tree(pts.astype(np.float32), w.astype(np.float32), d=2, leaf_size=8)
+    q = np.random.Generator(np.random.PCG64(34)).uniform(-1.4, 1.4, (60, 3)).astype(np.float32)
+    F = oracle.brute(pts.astype(np.float32), w.astype(np.float32), None, q, POT)
     zero = np.zeros(oracle.MLP_NPARAM, np.float32)
-    for kernel in (POT, WIND):
-        a = t.expect(q, kernel)
-        b = t.expect(q, kernel, params=zero)
-        assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+    K = 300
+    uni = np.array([t.sbh(q, POT, seed=500 + s)["F"] for s in range(K)])
+    sco = np.array([t.sbh(q, POT, seed=500 + s, params=zero)["F"] for s in range(K)])
+    ru = np.median(np.sqrt(np.mean((uni - F) ** 2, 0)) / F)
+    rs = np.median(np.sqrt(np.mean((sco - F) ** 2, 0)) / F)
+    assert rs < 0.85 * ru, (rs, ru)
 
 
 @pytest.mark.parametrize("kernel", [POT, WIND])
@@ -135,7 +210,7 @@ def test_child_targets_match_numpy_brute_force():
 def test_training_pairs_follow_uniform_paths():
     cl = W.c1()
     t = oracle.Tree(cl.sources, cl.weights)
-    nd, na = t.mlp_pairs(20, seed=3)
+    nd = t.mlp_pairs(20, seed=3)
     for j in range(20):
         for a in range(8):
             row = nd[j, a]
@@ -143,7 +218,6 @@ def test_training_pairs_follow_uniform_paths():
             assert len(row) >= 1 and t.level[row[0]] == 1 and t.digit[row[0]] == a
             assert np.all(t.parent[row[1:]] == row[:-1])           # a root-to-leaf chain
             assert np.all(t.internal[row])
-            assert np.all(na[j, a][: len(row)] == t.count[row[0]])
     # different seeds give different paths
-    nd2, _ = t.mlp_pairs(20, seed=4)
+    nd2 = t.mlp_pairs(20, seed=4)
     assert not np.array_equal(nd, nd2)
