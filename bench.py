@@ -313,6 +313,16 @@ def main():
                  alg_bytes_per_launch=wk_o["alg_bytes"], achieved_alg_GBs=wk_o["alg_bytes"] / (ms_o * 1e-3) / 1e9,
                  alg_flops_per_launch=wk_o["alg_flops"])
 
+    # --- the same estimator on the plane's original pixel order: neighbouring queries share a
+    # wavefront (and its random stream); per-query estimates have the same distribution, but
+    # neighbours' errors are correlated, which the paper avoids by shuffling
+    def run_grid():
+        P.sbh_eval(tree, qry_bh, kernel, samples=S, seed=0, group=args.group, out=out)
+
+    grid_order = dict(group=args.group, ms=timed(run_grid, args.steps, args.warmup),
+                      median_rel_err=err_of(run_grid, bh_idx_t))
+    grid_order["queries_per_s"] = N / (grid_order["ms"] * 1e-3)
+
     # --- samples-per-subdomain sweep (error / time curve of the stochastic method)
     sweep = None
     if not args.no_sweep:
@@ -513,6 +523,7 @@ def main():
         "mean_accepted_steps_per_path": mean_steps,
         "attempted_steps_per_path": wk["attempted_steps_per_path"],
         "other_stream_mode": other,
+        "grid_order": grid_order,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

@@ -96,6 +96,8 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
     int level = 1;
     float diamT = tv.diam0 * kInvD;
     float4 aggT = agg_a;
+    float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
+                     (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
     float tT = t_a;
     float prr = 1.0f;
     float acc = 0.0f;
@@ -146,12 +148,11 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
         }
         // roulette first (Eq. (5)); a lane that stops never reads the rest of the block
         float p;
+        float dC = 0.0f;
         if (rr_mode == 0) {
-            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
-            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
-            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
+            dC = fsqrt(cx * cx + cy * cy + cz * cz);
+            p = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
@@ -183,7 +184,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
             }
         }
         prr *= p;
-        acc += (sumc - tT) * __fdividef(fna, (float)nT * prr);
+        acc += (sumc - tT) * (fna * frcp((float)nT * prr));
         ++steps;
         if (!internal) {
             end_b = (int32_t)beginC;
@@ -192,6 +193,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
             break;
         }
         aggT = aggC;
+        dT = dC;
         tT = tC;
         nT = nC;
         beginT = beginC;
@@ -298,6 +300,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     const float fna = (float)n_a;
     // per-lane state
     bool act = valid;
+    float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
+                     (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
@@ -343,12 +347,11 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         }
         // roulette first (Eq. (5)): the swap is only needed by lanes that continue
         float p;
+        float dC = 0.0f;
         if (rr_mode == 0) {
-            const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
-            const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
-            p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), (float)D * dC));
+            dC = fsqrt(cx * cx + cy * cy + cz * cz);
+            p = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
@@ -384,7 +387,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         }
         if (cont) {
             prr *= p;
-            acc += (sumc - tT) * __fdividef(fna, (float)nT * prr);
+            acc += (sumc - tT) * (fna * frcp((float)nT * prr));
             ++steps;
             tT = tC;
         }
@@ -398,6 +401,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         }
         act = cont;
         aggT = aggC;
+        dT = dC;
         nT = nC;
         beginT = beginC;
         blk = blkC;
@@ -524,7 +528,8 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
     {
         const float4 g = tv.nagg[0];
         const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
-        const bool near = valid && !(__fdividef(__builtin_sqrtf(dx * dx + dy * dy + dz * dz), tv.diam0) >= a.beta);
+        const float lim = a.beta * tv.diam0;   // |q - com| / |B| >= beta, squared
+        const bool near = valid && !(dx * dx + dy * dy + dz * dz >= lim * lim);
         if (__ballot(near) == 0ull) {
             acc = term<K>(g, (K == SBH_WINDING) ? tv.ndip[0] : zero4, qx, qy, qz, kp, r0);
         } else if (!tv.root_internal) {
@@ -544,6 +549,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
         __builtin_amdgcn_wave_barrier();
         const float diamC = ldexpf(tv.diam0, -(level + 1) * (D == 2 ? 1 : 2));
+        const float limC = a.beta * diamC;
         const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
         const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
         const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
@@ -555,7 +561,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             const bool internal_c = (int)cnt > tv.leaf_size && level + 1 < tv.max_level;
             const float4 g = ba[c];
             const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
-            const bool near = valid && !(__fdividef(__builtin_sqrtf(dx * dx + dy * dy + dz * dz), diamC) >= a.beta);
+            const bool near = valid && !(dx * dx + dy * dy + dz * dz >= limC * limC);
             if (__ballot(near) == 0ull) {
                 acc += term<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, qx, qy, qz, kp, r0);
             } else if (internal_c) {

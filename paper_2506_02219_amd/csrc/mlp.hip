@@ -144,6 +144,39 @@ __device__ __forceinline__ void score_features(const float4* __restrict__ ba, co
                                             : -1.0f;
 }
 
+// Proposal without the network (z = 16 f): softmax(16 f)_c is
+// max(score_c / max score, e^-16) normalised over the non-empty slots, so no
+// logarithm or exponential is needed.
+__device__ __forceinline__ void score_probs(const float4* __restrict__ ba, const float* __restrict__ bs,
+                                            const uint32_t cnt[8], uint32_t nT, float qx, float qy, float qz,
+                                            float qv[8])
+{
+    float sc[8];
+    float smax = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 a = ba[c];
+        const float s2 = bs[c];
+        const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+        const float x = dx * dx + dy * dy + dz * dz + s2;
+        const float r = x > 0.0f ? __frsqrt_rn(x) : 0.0f;
+        const float v = cnt[c] ? a.w * s2 * (r * r * r) : 0.0f;
+        sc[c] = v;
+        smax = fmaxf(smax, v);
+    }
+    const float inv = smax > 0.0f ? frcp(smax) : 0.0f;
+    float tot = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        // a slot whose score is 0 has feature -1, i.e. the floor e^-16 (all slots when every score is 0)
+        sc[c] = cnt[c] ? (smax > 0.0f ? fmaxf(sc[c] * inv, 1.12535175e-7f) : 1.0f) : 0.0f;
+        tot += sc[c];
+    }
+    const float w = (1.0f - kLambda) * frcp(tot), fn = kLambda * frcp((float)nT);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) qv[c] = cnt[c] ? sc[c] * w + (float)cnt[c] * fn : 0.0f;
+}
+
 // q_c for the eight slots from the logits and the slot counts; empty slots 0.
 __device__ __forceinline__ void learned_probs(const float z[8], const uint32_t cnt[8], uint32_t nT, float qv[8])
 {
@@ -600,6 +633,8 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         int level = 1;
         float diamT = tv.diam0 * 0.5f;
         float4 aggT = agg_a;
+        float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
+                         (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
         float tT = cv, prr = 1.0f, psel = 1.0f, acc = 0.0f;
         int steps = 0, flag = 0;
         int32_t end_b = (int32_t)beginT, end_l = level;
@@ -633,14 +668,11 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                     tv8[c] = cnt[c] ? v : 0.0f;
                     sumc += tv8[c];
                 }
-                score_features(ba, tv.bspr + (int64_t)blk * D3, cnt, qx, qy, qz, f);
+                if constexpr (NET) score_features(ba, tv.bspr + (int64_t)blk * D3, cnt, qx, qy, qz, f);
             }
             float z[8];
             if constexpr (NET) {
                 if (__ballot(internal) != 0ull) mlp_forward_wave(R, f, z, lane);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) z[c] = 16.0f * f[c];
             }
             if (!act) continue;
             float4 aggC;
@@ -650,7 +682,8 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
             float qsel, tC = 0.0f;
             if (internal) {
                 float qv[8];
-                learned_probs(z, cnt, nT, qv);
+                if constexpr (NET) learned_probs(z, cnt, nT, qv);
+                else score_probs(ba, tv.bspr + (int64_t)blk * D3, cnt, nT, qx, qy, qz, qv);
                 const float u_sel = (float)(xsel >> 8) * 5.9604644775390625e-8f;
                 // first slot whose running sum exceeds u; rounding can leave the
                 // total just below u, then the last non-empty slot is taken
@@ -701,13 +734,11 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 csel = (int)r;
                 qsel = 1.0f / (float)nT;
             }
-            float p;
+            float p, dC = 0.0f;
             if (a.rr_mode == 0) {
-                const float ex = aggT.x - qx, ey = aggT.y - qy, ez = aggT.z - qz;
                 const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-                const float dT = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
-                const float dC = __builtin_sqrtf(cx * cx + cy * cy + cz * cz);
-                p = fminf(1.0f, __fdividef(fmaxf(diamT, dT), 2.0f * dC));
+                dC = fsqrt(cx * cx + cy * cy + cz * cz);
+                p = fminf(1.0f, fmaxf(diamT, dT) * frcp(2.0f * dC));
             } else {
                 p = a.rr_mode == 1 ? 1.0f : 0.5f;
             }
@@ -727,7 +758,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 }
             }
             prr *= p;
-            acc += __fdividef(sumc - tT, psel * prr);
+            acc += (sumc - tT) * frcp(psel * prr);
             psel *= qsel;
             ++steps;
             if (!internal) {
@@ -738,6 +769,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 continue;
             }
             aggT = aggC;
+            dT = dC;
             tT = tC;
             nT = nC;
             beginT = beginC;

@@ -108,6 +108,13 @@ struct KParams {
 
 constexpr float kInv4Pi = 0.0795774715459476679f;
 
+// Single-instruction square root and reciprocal (v_sqrt_f32 / v_rcp_f32,
+// about 1 ulp).  Used in the roulette probability, the estimator weights and
+// the far-field tests, where the parity tests' near-tie margins (1e-5)
+// cover a few ulps.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int K>
 __device__ __forceinline__ float term_r2(float4 a, float4 dp, float dx, float dy, float dz, float r2,
                                          const KParams& kp, float r0)
@@ -119,7 +126,7 @@ __device__ __forceinline__ float term_r2(float4 a, float4 dp, float dx, float dy
         const float v = (dp.x * dx + dp.y * dy + dp.z * dz) * (inv * inv * inv) * kInv4Pi;
         return r2 > 0.0f ? v : 0.0f;
     } else {
-        const float r = __builtin_sqrtf(r2);
+        const float r = fsqrt(r2);
         return a.w * kp.wscale * __expf(-kp.alpha * (r - r0));
     }
 }
