@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched evaluation")
+    ap.add_argument("--no-grid", action="store_true", help="skip the estimator on the plane's original order")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -319,9 +320,11 @@ def main():
     def run_grid():
         P.sbh_eval(tree, qry_bh, kernel, samples=S, seed=0, group=args.group, out=out)
 
-    grid_order = dict(group=args.group, ms=timed(run_grid, args.steps, args.warmup),
-                      median_rel_err=err_of(run_grid, bh_idx_t))
-    grid_order["queries_per_s"] = N / (grid_order["ms"] * 1e-3)
+    grid_order = None
+    if not args.no_grid:
+        grid_order = dict(group=args.group, ms=timed(run_grid, args.steps, args.warmup),
+                          median_rel_err=err_of(run_grid, bh_idx_t))
+        grid_order["queries_per_s"] = N / (grid_order["ms"] * 1e-3)
 
     # --- samples-per-subdomain sweep (error / time curve of the stochastic method)
     sweep = None
@@ -366,6 +369,9 @@ def main():
         torch.cuda.synchronize()
         tl = time.perf_counter()
         Xs, Ts, Cs = [], [], []
+        # the last training surface is held out for validation (model selection); the others train
+        val_pts, val_w = train_clouds[-1]
+        train_clouds = train_clouds[:-1]
         for i, (tp, tw) in enumerate(train_clouds):
             tt = P.sbh_build(torch.from_numpy(tp).to(dev), torch.from_numpy(tw).to(dev), None, branching=2,
                              leaf_size=8)
@@ -379,15 +385,33 @@ def main():
         del Xs, Ts, Cs, train_clouds
         torch.cuda.synchronize()
         rows_ms = (time.perf_counter() - tl) * 1e3
+        # validation: median relative error of the learned estimator (S = 1) on 8192 pixels of the
+        # plane over the held-out surface, against float64 brute force
+        vt = P.sbh_build(torch.from_numpy(val_pts).to(dev), torch.from_numpy(val_w).to(dev), None, branching=2,
+                         leaf_size=8)
+        vr = np.random.Generator(np.random.PCG64(7100))
+        vq = torch.from_numpy(cl.queries[np.sort(vr.choice(N, size=8192, replace=False))]).to(dev)
+        vref = P.sbh_brute(torch.from_numpy(val_pts).to(dev), torch.from_numpy(val_w).to(dev), None, vq, kernel,
+                           fp64=True).cpu().numpy()
+        vout = torch.empty(vq.shape[0], dtype=torch.float32, device=dev)
+
+        def validate(params):
+            errs = []
+            for b_ in range(4):
+                P.sbh_eval(vt, vq, kernel, samples=1, seed=77, batch=b_, group=1, out=vout, mlp=params)
+                errs.append(rel_errors(vout.cpu().numpy(), vref, kernel))
+            return float(np.median(np.concatenate(errs)))
+
         prm = L.init_params(1)
         loss0 = L.mean_loss(prm, X, Tg, Cn)
         torch.cuda.synchronize()
         tt0 = time.perf_counter()
-        losses, _ = L.train(prm, X, Tg, Cn, args.train_steps, args.train_batch, args.train_lr, seed=2)
+        prm, val_hist = L.train_selected(prm, X, Tg, Cn, args.train_steps, validate, chunks=8,
+                                         batch_rows=args.train_batch, lr=args.train_lr, seed=2)
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - tt0) * 1e3
         loss1 = L.mean_loss(prm, X, Tg, Cn)
-        lc = losses.cpu().numpy()
+        vt.free()
 
         def proposal_curve(prop, params):
             """(samples, ms, median error) of proposal 1 or 2, and its speed at equal error to the plain method"""
@@ -415,11 +439,11 @@ def main():
                         queries_per_s_at_plain_error=None if t_eq is None else N / (t_eq * 1e-3))
 
         learned = dict(
-            train_seeds=args.train_seeds, train_queries_per_surface=args.train_queries, train_rows=int(X.shape[0]),
+            train_surfaces=args.train_seeds - 1, train_queries_per_surface=args.train_queries, train_rows=int(X.shape[0]),
             train_steps=args.train_steps, train_batch=args.train_batch, lr=args.train_lr,
             surface_generation_s=train_gen_s, rows_ms=rows_ms, train_ms=train_ms,
-            loss_untrained=loss0, loss_trained=loss1, loss_first_steps=float(lc[:50].mean()),
-            loss_last_steps=float(lc[-50:].mean()),
+            loss_untrained=loss0, loss_selected=loss1, validation=[dict(steps=k, median_rel_err=v) for k, v in val_hist],
+            validation_surface_seed=W.c5_training_seeds()[args.train_seeds - 1],
             network=proposal_curve(1, prm), score_only=proposal_curve(2, None))
         del X, Tg, Cn
 

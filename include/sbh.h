@@ -237,8 +237,8 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
 
 /* ------------------------------------------------------------------------
  * Batched persistent evaluation: many trees and query sets (of uneven
- * sizes) evaluated by one persistent launch per branching factor, replayed
- * from a HIP graph.  A work item is a run of tile_waves wavefront-tiles (64
+ * sizes) evaluated by one persistent launch per (branching factor, kernel)
+ * group present, replayed from a HIP graph.  A work item is a run of tile_waves wavefront-tiles (64
  * consecutive queries each) of one cloud; every wavefront takes items from a
  * device counter until none are left.  Each tile runs the same code as
  * sbh_eval with samples >= 1 and opts->group a multiple of 64, so every
@@ -275,7 +275,7 @@ typedef struct sbh_batch_config {
  *   the outputs and synchronises `stream`.
  * The plan keeps pointers to the trees, queries and outputs, which must
  * stay valid (and the trees alive) until sbh_batch_free.  It allocates
- * 2 x 16 bytes of launch state and the descriptors on the current device.
+ * 6 x 16 bytes of launch state and the descriptors on the current device.
  * Errors: SBH_EINVAL, SBH_EUNSUPPORTED (proposal != 0), SBH_ENOMEM, SBH_EHIP.
  */
 sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t samples, const sbh_eval_opts* opts,

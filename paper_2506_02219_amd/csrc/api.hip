@@ -360,10 +360,11 @@ struct sbh_batch {
     sbh_eval_opts opts{};
     std::vector<sbh::BatchItem> clouds;   // as given (item_begin filled per configuration)
     std::vector<double> cost;             // work estimate per cloud
-    sbh::BatchItem* d_items[2] = {nullptr, nullptr};   // d = 2 and d = 4 groups
-    int n_items[2] = {0, 0};
-    uint32_t total[2] = {0u, 0u};
-    sbh::BatchState* d_state = nullptr;   // [2]
+    // groups g = 3 (d == 4) + kernel: one persistent launch each
+    sbh::BatchItem* d_items[sbh::kBatchGroups] = {};
+    int n_items[sbh::kBatchGroups] = {};
+    uint32_t total[sbh::kBatchGroups] = {};
+    sbh::BatchState* d_state = nullptr;   // [kBatchGroups]
     sbh_batch_config cfg{};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -378,25 +379,25 @@ void batch_release(sbh_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < sbh::kBatchGroups; ++g)
         if (b->d_items[g]) (void)hipFree(b->d_items[g]);
     if (b->d_state) (void)hipFree(b->d_state);
 }
 
-// device descriptors for a configuration: clouds split by branching factor,
-// ordered as the configuration asks, with the prefix of their work items
+// device descriptors for a configuration: clouds split by branching factor and
+// kernel, ordered as the configuration asks, with the prefix of their work items
 hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
 {
     std::vector<int> order(b->clouds.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     if (c.heavy_first)
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < sbh::kBatchGroups; ++g) {
         std::vector<sbh::BatchItem> v;
         int64_t next = 0;
         for (int i : order) {
             sbh::BatchItem it = b->clouds[i];
-            if (it.d != (g == 0 ? 2 : 4) || it.nq == 0) continue;
+            if (3 * (it.d == 4 ? 1 : 0) + it.kernel != g || it.nq == 0) continue;
             it.item_begin = next;
             const int64_t tiles = (it.nq + 63) / 64;
             next += (tiles + c.tile_waves - 1) / c.tile_waves;
@@ -417,11 +418,11 @@ hipError_t batch_enqueue(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_
 {
     hipError_t e = sbh::launch_batch_begin(b->d_state, seed, batch, s);
     const int blocks = 256 * b->cfg.waves_per_simd;   // 256 CUs; a block of 4 wavefronts puts one on each SIMD
-    for (int g = 0; g < 2 && e == hipSuccess; ++g)
+    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g)
         if (b->total[g] > 0)
-            e = sbh::launch_sbh_batch(g == 0 ? 2 : 4, b->d_items[g], b->n_items[g], b->total[g], b->cfg.tile_waves,
-                                      blocks, b->d_state + g, b->samples, b->opts.group, b->opts.rr_mode,
-                                      b->opts.eps, b->opts.alpha, s);
+            e = sbh::launch_sbh_batch(g < 3 ? 2 : 4, g % 3, b->d_items[g], b->n_items[g], b->total[g],
+                                      b->cfg.tile_waves, blocks, b->d_state + g, b->samples, b->opts.group,
+                                      b->opts.rr_mode, b->opts.eps, b->opts.alpha, s);
     return e;
 }
 
@@ -483,9 +484,9 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         b->cost.push_back((double)it.nq * (double)(t->depth + 1) * (it.kernel == SBH_WINDING ? 1.5 : 1.0) * samples);
     }
     hipError_t e = hipSuccess;
-    for (int g = 0; g < 2 && e == hipSuccess; ++g)
+    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g)
         e = hipMalloc((void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, 2 * sizeof(sbh::BatchState));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, sbh::kBatchGroups * sizeof(sbh::BatchState));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         batch_release(b);

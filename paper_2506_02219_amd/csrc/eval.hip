@@ -87,6 +87,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
                                              float4 agg_a, float t_a, uint32_t ctr0, uint32_t ctr1, uint32_t ctr3,
                                              uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
@@ -96,8 +97,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
     int level = 1;
     float diamT = tv.diam0 * kInvD;
     float4 aggT = agg_a;
-    float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
-                     (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
+    float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));   // |com_T - q|, carried step to step
     float tT = t_a;
     float prr = 1.0f;
     float acc = 0.0f;
@@ -151,7 +151,7 @@ __device__ __forceinline__ float sample_path(const TreeView& tv, float qx, float
         float dC = 0.0f;
         if (rr_mode == 0) {
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            dC = fsqrt(cx * cx + cy * cy + cz * cz);
+            dC = fsqrt(norm2(cx, cy, cz));
             p = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
@@ -209,6 +209,7 @@ template <int D, int K, bool TRACE>
 __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restrict__ queries, int64_t nq,
                                              SbhArgs a, float* __restrict__ out)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     constexpr int QPW = 64 / D3;
     const int lane = threadIdx.x & 63;
@@ -287,6 +288,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                                            int32_t blk_a, float4 agg_a, float t_a, uint32_t ctr0, uint32_t ctr1,
                                            uint32_t ctr3, uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
@@ -300,21 +302,25 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     const float fna = (float)n_a;
     // per-lane state
     bool act = valid;
-    float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
-                     (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
+    float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));   // |com_T - q|, carried step to step
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    u32x4 rnd = {0u, 0u, 0u, 0u};
+    // The walk's random words do not depend on the query: lane l computes the
+    // Philox block of step pair l once per path (vector ALU), and step k reads
+    // its two words from lane k/2.  This takes the generator off the scalar
+    // unit, which the walk's control already keeps busy.  A walk has at most
+    // 2 max_level + 2 steps, far below 128.
+    const u32x4 vr = philox4x32_10(ctr0, ctr1, (uint32_t)(threadIdx.x & 63), ctr3, key0, key1);
     for (int k = 0;; ++k) {
         if (__ballot(act) == 0ull) break;
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
-        if ((k & 1) == 0) rnd = philox4x32_10(ctr0, ctr1, (uint32_t)(k >> 1), ctr3, key0, key1);
-        const uint32_t xsel = (k & 1) ? rnd.z : rnd.x;
-        const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
+        const int pair = k >> 1;
+        const uint32_t xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, pair);
+        const uint32_t xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, pair);
         const uint32_t r = __umulhi(xsel, nT);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
         const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
@@ -324,23 +330,47 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
         int csel = 0;
+        uint64_t nonempty = 0ull;   // d = 2: slots with points (wavefront-uniform)
         if (internal) {
-            // uniform child selection from the point counts alone
-            uint32_t pre = 0u, preC = 0u;
-            int32_t nint = 0, nintC = 0;
-            for (int c = 0; c < D3; ++c) {
-                const uint32_t cnt = bt[c];
-                const bool hit = (r - pre) < cnt;
-                csel = hit ? c : csel;
-                preC = hit ? pre : preC;
-                nintC = hit ? nint : nintC;
-                nC = hit ? cnt : nC;
-                nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
-                pre += cnt;
+            if constexpr (D == 2) {
+                // child selection across lanes 0..7 (one slot each): an exclusive scan of the
+                // counts by DPP row shifts, then ballots give the slot whose range holds r, the
+                // internal slots before it and the non-empty slots
+                const int ln = threadIdx.x & 63;
+                const uint32_t cl = ln < D3 ? bt[ln] : 0u;
+                uint32_t inc = cl;
+                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
+                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
+                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
+                const uint32_t excl = inc - cl;
+                const uint64_t hm = __ballot(ln < D3 && (r - excl) < cl);
+                const uint64_t im = __ballot(ln < D3 && (int)cl > tv.leaf_size && level + 1 < tv.max_level);
+                nonempty = __ballot(ln < D3 && cl != 0u);
+                csel = __ffsll((unsigned long long)hm) - 1;
+                const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+                nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+                const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
+                aggC = ba[csel];
+                beginC = beginT + preC;
+                blkC = (int32_t)bt[D3] + nintC;
+            } else {
+                // uniform child selection from the point counts alone
+                uint32_t pre = 0u, preC = 0u;
+                int32_t nint = 0, nintC = 0;
+                for (int c = 0; c < D3; ++c) {
+                    const uint32_t cnt = bt[c];
+                    const bool hit = (r - pre) < cnt;
+                    csel = hit ? c : csel;
+                    preC = hit ? pre : preC;
+                    nintC = hit ? nint : nintC;
+                    nC = hit ? cnt : nC;
+                    nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                    pre += cnt;
+                }
+                aggC = ba[csel];
+                beginC = beginT + preC;
+                blkC = (int32_t)bt[D3] + nintC;
             }
-            aggC = ba[csel];
-            beginC = beginT + preC;
-            blkC = (int32_t)bt[D3] + nintC;
         } else {
             aggC = tv.pts[beginT + r];
             beginC = beginT + r;
@@ -350,7 +380,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         float dC = 0.0f;
         if (rr_mode == 0) {
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            dC = fsqrt(cx * cx + cy * cy + cz * cz);
+            dC = fsqrt(norm2(cx, cy, cz));
             p = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
@@ -366,15 +396,26 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         // contribution swap, Eq. (6)
         float sumc = 0.0f, tC = 0.0f;
         if (internal) {
-#pragma unroll
-            for (int c = 0; c < D3; ++c) {
-                const uint32_t cnt = bt[c];
-                const float4 g = ba[c];
-                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                const float vv = cnt ? v : 0.0f;
-                sumc += vv;
-                tC = (c == csel) ? vv : tC;
+            if constexpr (D == 2) {
+                // only the non-empty slots (about half of them on a surface), by a scalar loop
+                // over the ballot's set bits
+                for (uint64_t m = nonempty; m != 0ull; m &= m - 1ull) {
+                    const int c = __ffsll((unsigned long long)m) - 1;
+                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                    const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                    sumc += v;
+                    if (c == csel) tC = v;
+                }
+            } else {
+#pragma unroll 8
+                for (int c = 0; c < D3; ++c) {
+                    const uint32_t cnt = bt[c];
+                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                    const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                    const float vv = cnt ? v : 0.0f;
+                    sumc += vv;
+                    tC = (c == csel) ? vv : tC;
+                }
             }
         } else {
             for (uint32_t i = 0; i < nT; ++i) {
@@ -418,6 +459,7 @@ template <int D, int K, bool TRACE>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     const int lane = threadIdx.x & 63;
     const int64_t j0 = wave * 64;
@@ -501,6 +543,7 @@ template <int D, int K>
 __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict__ queries, int64_t nq, BhArgs a,
                                             float* __restrict__ out)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
     constexpr int MAXS = bh_stack_depth<D>();
@@ -529,7 +572,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         const float4 g = tv.nagg[0];
         const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
         const float lim = a.beta * tv.diam0;   // |q - com| / |B| >= beta, squared
-        const bool near = valid && !(dx * dx + dy * dy + dz * dz >= lim * lim);
+        const bool near = valid && !(norm2(dx, dy, dz) >= lim * lim);
         if (__ballot(near) == 0ull) {
             acc = term<K>(g, (K == SBH_WINDING) ? tv.ndip[0] : zero4, qx, qy, qz, kp, r0);
         } else if (!tv.root_internal) {
@@ -561,7 +604,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             const bool internal_c = (int)cnt > tv.leaf_size && level + 1 < tv.max_level;
             const float4 g = ba[c];
             const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
-            const bool near = valid && !(dx * dx + dy * dy + dz * dz >= limC * limC);
+            const bool near = valid && !(norm2(dx, dy, dz) >= limC * limC);
             if (__ballot(near) == 0ull) {
                 acc += term<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, qx, qy, qz, kp, r0);
             } else if (internal_c) {
@@ -587,6 +630,7 @@ template <int K>
 __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float* __restrict__ queries, int64_t j,
                                                  float eps2, float alpha, float* __restrict__ out)
 {
+#pragma clang fp contract(off)
     const float qx = queries[3 * j], qy = queries[3 * j + 1], qz = queries[3 * j + 2];
     KParams kp{eps2, alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
@@ -619,10 +663,10 @@ __global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __
 // split.  Each tile runs exactly the code of the single-tree kernels, so a
 // cloud's results do not depend on the batch around it.
 // ---------------------------------------------------------------------------
-// key, batch word and a cleared work counter for both branching-factor groups
+// key, batch word and a cleared work counter for every group of the batch
 __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint32_t batch)
 {
-    if (blockIdx.x == 0 && threadIdx.x < 2) {
+    if (blockIdx.x == 0 && threadIdx.x < kBatchGroups) {
         st[threadIdx.x].key0 = key0;
         st[threadIdx.x].key1 = key1;
         st[threadIdx.x].batch = batch;
@@ -630,20 +674,9 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
     }
 }
 
+// One launch per (branching factor, kernel) group present in the batch, so
+// that each instance keeps the registers of the single-tree kernel.
 template <int D, int K>
-__device__ __forceinline__ void batch_tile_k(const BatchItem& it, const SbhArgs& a, int64_t wave)
-{
-    if (it.root_leaf) {
-        const int64_t j = wave * 64 + (threadIdx.x & 63);
-        if (j < it.nq) leaf_exact_query<K>(it.tv, it.queries, j, a.eps2, a.alpha, it.out);
-    } else {
-        sbh_wave_tile<D, K, false>(it.tv, it.queries, it.nq, a, it.out, wave);
-    }
-}
-
-// one launch per branching factor present in the batch (items of the other
-// branching factor are given no work items by the host)
-template <int D>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 k_sbh_batch(const BatchItem* __restrict__ items, int count, uint32_t total_items, int wpi, BatchState* st,
             SbhArgs base)
@@ -660,18 +693,24 @@ k_sbh_batch(const BatchItem* __restrict__ items, int count, uint32_t total_items
             if (items[mid].item_begin <= (int64_t)t) lo = mid;
             else hi = mid - 1;
         }
-        const BatchItem it = items[lo];
+        // the descriptor stays in memory and its fields are read where they are used (scalar
+        // loads), as kernel arguments are: a register copy would not fit beside the walk
+        const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(lo);
         SbhArgs a = base;
         a.key0 = st->key0;
         a.key1 = st->key1;
         a.batch = st->batch;
-        const int64_t w0 = ((int64_t)t - it.item_begin) * wpi;
+        const int64_t nq = it->nq;
+        const int64_t w0 = ((int64_t)t - it->item_begin) * wpi;
         for (int w = 0; w < wpi; ++w) {
             const int64_t wave = w0 + w;
-            if (wave * 64 >= it.nq) break;
-            if (it.kernel == SBH_POTENTIAL) batch_tile_k<D, SBH_POTENTIAL>(it, a, wave);
-            else if (it.kernel == SBH_WINDING) batch_tile_k<D, SBH_WINDING>(it, a, wave);
-            else batch_tile_k<D, SBH_SMOOTHDIST>(it, a, wave);
+            if (wave * 64 >= nq) break;
+            if (it->root_leaf) {
+                const int64_t j = wave * 64 + lane;
+                if (j < nq) leaf_exact_query<K>(it->tv, it->queries, j, a.eps2, a.alpha, it->out);
+            } else {
+                sbh_wave_tile<D, K, false>(it->tv, it->queries, nq, a, it->out, wave);
+            }
         }
     }
 }
@@ -754,12 +793,22 @@ hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hip
     return hipGetLastError();
 }
 
-hipError_t launch_sbh_batch(int d, const BatchItem* items, int count, uint32_t total_items, int wpi, int blocks,
-                            BatchState* st, int samples, int group, int rr_mode, float eps, float alpha, hipStream_t s)
+hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, int count, uint32_t total_items, int wpi,
+                            int blocks, BatchState* st, int samples, int group, int rr_mode, float eps, float alpha,
+                            hipStream_t s)
 {
     SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
-    if (d == 2) k_sbh_batch<2><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a);
-    else k_sbh_batch<4><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a);
+#define SBH_LAUNCH_B(DD, KK) k_sbh_batch<DD, KK><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a)
+    if (d == 2) {
+        if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(2, SBH_POTENTIAL);
+        else if (kernel == SBH_WINDING) SBH_LAUNCH_B(2, SBH_WINDING);
+        else SBH_LAUNCH_B(2, SBH_SMOOTHDIST);
+    } else {
+        if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(4, SBH_POTENTIAL);
+        else if (kernel == SBH_WINDING) SBH_LAUNCH_B(4, SBH_WINDING);
+        else SBH_LAUNCH_B(4, SBH_SMOOTHDIST);
+    }
+#undef SBH_LAUNCH_B
     return hipGetLastError();
 }
 

@@ -123,6 +123,7 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpRegs& R, const float f
 __device__ __forceinline__ void score_features(const float4* __restrict__ ba, const float* __restrict__ bs,
                                                const uint32_t cnt[8], float qx, float qy, float qz, float f[8])
 {
+#pragma clang fp contract(off)
     float sc[8];
     float smax = 0.0f;
 #pragma unroll
@@ -130,7 +131,7 @@ __device__ __forceinline__ void score_features(const float4* __restrict__ ba, co
         const float4 a = ba[c];
         const float s2 = bs[c];
         const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
-        const float x = dx * dx + dy * dy + dz * dz + s2;
+        const float x = norm2(dx, dy, dz) + s2;
         const float r = x > 0.0f ? __frsqrt_rn(x) : 0.0f;
         const float v = cnt[c] ? a.w * s2 * (r * r * r) : 0.0f;
         sc[c] = v;
@@ -151,6 +152,7 @@ __device__ __forceinline__ void score_probs(const float4* __restrict__ ba, const
                                             const uint32_t cnt[8], uint32_t nT, float qx, float qy, float qz,
                                             float qv[8])
 {
+#pragma clang fp contract(off)
     float sc[8];
     float smax = 0.0f;
 #pragma unroll
@@ -158,7 +160,7 @@ __device__ __forceinline__ void score_probs(const float4* __restrict__ ba, const
         const float4 a = ba[c];
         const float s2 = bs[c];
         const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
-        const float x = dx * dx + dy * dy + dz * dz + s2;
+        const float x = norm2(dx, dy, dz) + s2;
         const float r = x > 0.0f ? __frsqrt_rn(x) : 0.0f;
         const float v = cnt[c] ? a.w * s2 * (r * r * r) : 0.0f;
         sc[c] = v;
@@ -585,6 +587,7 @@ template <int K, bool TRACE, bool NET>
 __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* __restrict__ queries, int64_t nq,
                                                      LearnArgs a, float* __restrict__ out)
 {
+#pragma clang fp contract(off)
     constexpr int D3 = 8;
     constexpr int TS = topo_stride(D3);
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -633,8 +636,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         int level = 1;
         float diamT = tv.diam0 * 0.5f;
         float4 aggT = agg_a;
-        float dT = fsqrt((agg_a.x - qx) * (agg_a.x - qx) + (agg_a.y - qy) * (agg_a.y - qy) +
-                         (agg_a.z - qz) * (agg_a.z - qz));   // |com_T - q|, carried from step to step
+        float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));   // |com_T - q|, carried step to step
         float tT = cv, prr = 1.0f, psel = 1.0f, acc = 0.0f;
         int steps = 0, flag = 0;
         int32_t end_b = (int32_t)beginT, end_l = level;
@@ -737,7 +739,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
             float p, dC = 0.0f;
             if (a.rr_mode == 0) {
                 const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-                dC = fsqrt(cx * cx + cy * cy + cz * cz);
+                dC = fsqrt(norm2(cx, cy, cz));
                 p = fminf(1.0f, fmaxf(diamT, dT) * frcp(2.0f * dC));
             } else {
                 p = a.rr_mode == 1 ? 1.0f : 0.5f;

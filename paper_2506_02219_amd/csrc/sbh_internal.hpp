@@ -115,15 +115,22 @@ constexpr float kInv4Pi = 0.0795774715459476679f;
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// The evaluation code is compiled with floating-point contraction off and
+// explicit fmaf where a fused multiply-add is wanted, so that a value is the
+// same in every kernel that inlines it (single-tree and batched launches
+// give bit-identical results).
+__device__ __forceinline__ float norm2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dx, dx, dy * dy)); }
+
 template <int K>
 __device__ __forceinline__ float term_r2(float4 a, float4 dp, float dx, float dy, float dz, float r2,
                                          const KParams& kp, float r0)
 {
+#pragma clang fp contract(off)
     if constexpr (K == SBH_POTENTIAL) {
         return a.w * __builtin_amdgcn_rsqf(r2 + kp.eps2);
     } else if constexpr (K == SBH_WINDING) {
         const float inv = __builtin_amdgcn_rsqf(r2);
-        const float v = (dp.x * dx + dp.y * dy + dp.z * dz) * (inv * inv * inv) * kInv4Pi;
+        const float v = fmaf(dp.z, dz, fmaf(dp.x, dx, dp.y * dy)) * (inv * inv * inv) * kInv4Pi;
         return r2 > 0.0f ? v : 0.0f;
     } else {
         const float r = fsqrt(r2);
@@ -135,9 +142,9 @@ template <int K>
 __device__ __forceinline__ float term(float4 a, float4 dp, float qx, float qy, float qz, const KParams& kp,
                                       float r0)
 {
+#pragma clang fp contract(off)
     const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    return term_r2<K>(a, dp, dx, dy, dz, r2, kp, r0);
+    return term_r2<K>(a, dp, dx, dy, dz, norm2(dx, dy, dz), kp, r0);
 }
 
 // Lower bound on the distance from q to any source (distance to the root
@@ -149,7 +156,7 @@ __device__ __forceinline__ float cube_distance(const TreeView& tv, float qx, flo
     const float ex = fmaxf(fmaxf(tv.lo[0] - qx, qx - (tv.lo[0] + tv.side)), 0.0f);
     const float ey = fmaxf(fmaxf(tv.lo[1] - qy, qy - (tv.lo[1] + tv.side)), 0.0f);
     const float ez = fmaxf(fmaxf(tv.lo[2] - qz, qz - (tv.lo[2] + tv.side)), 0.0f);
-    return __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+    return __builtin_sqrtf(norm2(ex, ey, ez));
 }
 
 // ---------------------------------------------------------------------------
@@ -200,12 +207,14 @@ struct BatchItem {          // one cloud of a batch (device copy)
     int64_t item_begin;     // index of the cloud's first work item
     int32_t kernel, d, root_leaf, pad;
 };
-struct BatchState {         // per-launch key and batch word, and the work counter (one per branching group)
+struct BatchState {         // per-launch key and batch word, and the work counter of one group
     uint32_t key0, key1, batch, counter;
 };
+constexpr int kBatchGroups = 6;   // (branching factor 2 or 4) x (kernel)
 hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hipStream_t s);
-hipError_t launch_sbh_batch(int d, const BatchItem* items, int count, uint32_t total_items, int wpi, int blocks,
-                            BatchState* st, int samples, int group, int rr_mode, float eps, float alpha, hipStream_t s);
+hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, int count, uint32_t total_items, int wpi,
+                            int blocks, BatchState* st, int samples, int group, int rr_mode, float eps, float alpha,
+                            hipStream_t s);
 void* batch_begin_kernel();
 
 // learned proposal (mlp.hip)

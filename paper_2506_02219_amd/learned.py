@@ -64,5 +64,32 @@ def train(params: torch.Tensor, X: torch.Tensor, Tg: torch.Tensor, Cn: torch.Ten
     return losses[:steps], state
 
 
+def train_selected(params: torch.Tensor, X, Tg, Cn, steps: int, validate, chunks: int = 8, batch_rows: int = 8192,
+                   lr: float = 2e-3, seed: int = 0):
+    """Train in `chunks` equal parts and keep the parameters with the lowest `validate(params)` (a
+    validation error of the estimator), the untrained parameters included.  Returns (best params,
+    history of (steps done, validation value))."""
+    best = params.clone()
+    best_v = validate(params)
+    hist = [(0, best_v)]
+    state = torch.zeros(2 * MLP_NPARAM, dtype=torch.float32, device=params.device)
+    n = X.shape[0]
+    gen = torch.Generator().manual_seed(seed)
+    per = max(1, steps // max(chunks, 1))
+    done = 0
+    while done < steps:
+        perm = torch.randperm(n, generator=gen).to(params.device)
+        Xs, Ts, Cs = X[perm].contiguous(), Tg[perm].contiguous(), Cn[perm].contiguous()
+        k = min(per, steps - done)
+        sbh_mlp_train(params, state, Xs, Ts, Cs, steps=k, batch_rows=batch_rows, lr=lr, step0=done)
+        done += k
+        v = validate(params)
+        hist.append((done, v))
+        if v < best_v:
+            best_v = v
+            best = params.clone()
+    return best, hist
+
+
 def mean_loss(params, X, Tg, Cn) -> float:
     return float(sbh_mlp_loss_grad(params, X, Tg, Cn)[MLP_NPARAM].item())
