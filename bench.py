@@ -269,7 +269,6 @@ def main():
         end_count = np.where(found, exp["count"][order][pos], 1).astype(np.int64)
         end_internal = found & (end_count > 8) & (rec[:, 1] < tree.max_level)
         wind = kernel == 1
-        blk_bytes = d3 * 16 * (2 if wind else 1) + d3 * 4 + 4
         pt_bytes = 16 * (2 if wind else 1)
         # accepted steps read child blocks, except the last one of a path that moved onto a virtual point
         # (flag 2), which read its leaf's points; a roulette stop (flag 0) read the block or the leaf
@@ -283,13 +282,30 @@ def main():
         leaf_pts = rr_leaf_pts.sum() + vp_pts.sum()
         leaf_att = int((rr_leaf_pts > 0).sum() + vp.sum())
         n_int_att = int(internal_att.sum())
-        bytes_q = 12 + 4 + d3 * (16 * (2 if wind else 1) + 4)
-        alg_bytes = float(n_int_att * blk_bytes + leaf_pts * pt_bytes + N * bytes_q)
+        # only non-empty children are work: the number of children of every internal node a path
+        # scanned, from the per-node running sum of child counts along the ancestor chain
+        parent = exp["parent"].astype(np.int64)
+        nch = exp["nchild"].astype(np.int64)
+        lev = exp["level"].astype(np.int64)
+        cumc = np.zeros(len(nch), np.int64)
+        for L in range(1, int(lev.max()) + 1):   # breadth-first: parents come first
+            m = lev == L
+            cumc[m] = nch[m] + cumc[parent[m]]
+        end_node = order[pos]
+        last = np.where((flags == 0) & end_internal, end_node, parent[end_node])   # last internal node scanned
+        if vp.any():
+            last[vp] = parent[order[lpos]]
+        last = np.where(found | vp, last, 0)
+        n_terms_int = int(np.where(lev[last] >= 1, cumc[last], 0).sum())
+        bytes_q = 12 + 4 + int(nch[0]) * 16 * (2 if wind else 1) + d3 * 4
+        alg_bytes = float(n_terms_int * 16 * (2 if wind else 1) + n_int_att * (d3 * 4 + 4) + leaf_pts * pt_bytes
+                          + N * bytes_q)
         tf = TERM_FLOPS[kernel]
-        alg_flops = float(n_int_att * (d3 * (tf + 1) + 25) + leaf_pts * (tf + 1) + leaf_att * 25
-                          + len(rec) * tf + N * (d3 + 4))
+        alg_flops = float(n_terms_int * (tf + 1) + n_int_att * 25 + leaf_pts * (tf + 1) + leaf_att * 25
+                          + len(rec) * tf + N * (int(nch[0]) + 4))
         return dict(alg_bytes=alg_bytes, alg_flops=alg_flops, mean_steps=float(steps_acc.mean()),
-                    attempted_steps_per_path=float((n_int_att + leaf_att) / len(rec)))
+                    attempted_steps_per_path=float((n_int_att + leaf_att) / len(rec)),
+                    children_per_internal_step=n_terms_int / max(n_int_att, 1))
 
     wk = work_of(args.group)
     mean_steps = wk["mean_steps"]
@@ -326,6 +342,18 @@ def main():
                           median_rel_err=err_of(run_grid, bh_idx_t))
         grid_order["queries_per_s"] = N / (grid_order["ms"] * 1e-3)
 
+    # --- the tile-shared score proposal on the plane's own order (tiles of 64 neighbouring pixels)
+    tile_grid = None
+    if not args.no_grid and args.branching == 2:
+        def run_tile(samples):
+            P.sbh_eval(tree, qry_bh, kernel, samples=samples, seed=0, group=args.group, out=out, proposal=3)
+
+        tile_grid = dict(group=args.group, sweep=[])
+        for sv in (1, 2, 4):
+            ms_t = timed(lambda: run_tile(sv), args.steps if sv == 1 else 3, args.warmup if sv == 1 else 1)
+            tile_grid["sweep"].append(dict(samples=sv, ms=ms_t, median_rel_err=err_of(lambda: run_tile(sv), bh_idx_t)))
+        tile_grid["queries_per_s"] = N / (tile_grid["sweep"][0]["ms"] * 1e-3)
+
     # --- samples-per-subdomain sweep (error / time curve of the stochastic method)
     sweep = None
     if not args.no_sweep:
@@ -357,6 +385,12 @@ def main():
                 t_eq, kind = pts[0][1], "upper_bound_at_smallest_beta"
             else:
                 kind = "not_reached"
+        if tile_grid is not None:
+            # Barnes-Hut's time at the tile-proposal estimator's (lower) error
+            e1 = tile_grid["sweep"][0]["median_rel_err"]
+            tb = log_interp([p_[2] for p_ in pts], [p_[1] for p_ in pts], e1)
+            tile_grid["bh_ms_at_this_error"] = tb
+            tile_grid["speedup_vs_bh_at_this_error"] = None if tb is None else tb / tile_grid["sweep"][0]["ms"]
         bh = dict(branching=args.bh_branching, sweep=[dict(beta=b, ms=round(m, 4), median_rel_err=e) for b, m, e in pts],
                   ms_at_equal_error=None if t_eq is None else round(t_eq, 4),
                   queries_per_s_at_equal_error=None if t_eq is None else N / (t_eq * 1e-3),
@@ -548,6 +582,7 @@ def main():
         "attempted_steps_per_path": wk["attempted_steps_per_path"],
         "other_stream_mode": other,
         "grid_order": grid_order,
+        "tile_score_grid_order": tile_grid,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

@@ -70,7 +70,8 @@ typedef struct sbh_eval_opts {
                             (the paper's, default); 1 = the learned proposal with
                             network parameters opts->mlp; 2 = the score proposal
                             (the learned one with an all-zero network, evaluated
-                            without it).  1 and 2: branching 2 only. */
+                            without it); 3 = the tile-shared score proposal
+                            (group a multiple of 64).  1, 2 and 3: branching 2 only. */
     uint32_t batch;      /* fourth Philox counter word, for independent batches; default 0 */
     int32_t* paths;      /* optional DEVICE [nq][d^3][samples][4] int32 records of every
                             sampled path: {end begin, end level, accepted steps, stop
@@ -138,8 +139,9 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   nq = 0 is a no-op.  Errors: SBH_EINVAL (null pointers, nq < 0, bad
  *   kernel, samples < 0, beta <= 0 or NaN with samples == 0, group < 1,
  *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals, proposal
- *   not 0, 1 or 2, proposal 1 without opts->mlp), SBH_EUNSUPPORTED
- *   (proposal 1 or 2 on a tree with branching 4), SBH_EHIP.
+ *   not 0..3, proposal 1 without opts->mlp, proposal 3 with a group that is
+ *   not a multiple of 64), SBH_EUNSUPPORTED (proposals 1-3 on a tree with
+ *   branching 4), SBH_EHIP.
  *
  *   Learned and score proposals (opts->proposal = 1, 2).  Section 3.3 draws
  *   the path index uniformly and leaves importance sampling open; Theorem 1
@@ -157,6 +159,16 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   running sum of q exceeds u = (x >> 8) 2^-24 of the selection word x (the
  *   last non-empty slot if rounding leaves the total below u).  Leaves choose
  *   a point uniformly.
+ *
+ *   Tile-shared score proposal (opts->proposal = 3).  Queries are taken in
+ *   tiles of 64 consecutive indices (the wavefronts of the shared-stream
+ *   walk); at each internal node every query of a tile uses the same
+ *     q_c = (7/8) mean over the tile's queries of pi_c(q) + (1/8) n_c / n_T,
+ *   pi_c(q) = max(score_c(q) / max score(q), e^-16) normalised over the
+ *   non-empty slots (proposal 2's softmax), so that the tile keeps one
+ *   shared path; q depends only on the node and the tile's queries, and the
+ *   estimator stays unbiased for every query.  It pays when a tile's queries
+ *   are close to one another (e.g. a grid in its own order).
  */
 sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_kernel kernel,
                     float beta, int32_t samples, uint64_t seed, const sbh_eval_opts* opts,

@@ -39,8 +39,8 @@ def lib():
         L.orc_tree_meta.argtypes = [P, P]
         L.orc_tree_export.argtypes = [P] + [P] * 11
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
-        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, P, P, P, P, i32]
-        L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, P, i32]
+        L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, i64, P, P, P, P, P, i32]
+        L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32, P, i32]
         L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
         L.orc_mlp_nparam.restype = i32
         L.orc_f16_round.argtypes = [C.c_float]
@@ -136,27 +136,32 @@ class Tree:
         return out, mg, vis
 
     def sbh(self, queries, kernel, samples=1, seed=0, group=1, batch=0, rr_mode=0, eps=1e-3, alpha=100.0,
-            paths=False, index=None, params=None, threads=0):
+            paths=False, index=None, params=None, tile_queries=None, threads=0):
         """Algorithm 2 driven by Philox; returns dict(F, margin, absum, sens[, paths]).
-        index: optional original query indices (random stream ids) of a query subset."""
+        index: optional original query indices (random stream ids) of a query subset;
+        params: learned proposal; tile_queries: the full query set, selecting the tile-shared
+        score proposal (tiles of 64 consecutive indices of it)."""
         q = _f32(queries, (-1, 3)); n = q.shape[0]
         idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
         prm = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
         out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n); sn = np.zeros(n)
         d3 = self.d ** 3
         pth = np.zeros((n, d3, samples, 4), np.int32) if paths else None
+        tq = None if tile_queries is None else _f32(tile_queries, (-1, 3))
         lib().orc_sbh(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, rr_mode, _p(idx), _p(prm),
-                      _p(out), _p(mg), _p(ab), _p(sn), _p(pth), threads)
+                      _p(tq), 0 if tq is None else tq.shape[0], _p(out), _p(mg), _p(ab), _p(sn), _p(pth), threads)
         r = dict(F=out, margin=mg, absum=ab, sens=sn)
         if paths:
             r["paths"] = pth
         return r
 
-    def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, params=None, threads=0):
-        """Exact expectation of the one-sample estimator (Theorem 1), optionally with the learned proposal."""
+    def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, params=None, tiles=False, threads=0):
+        """Exact expectation of the one-sample estimator (Theorem 1), optionally with the learned
+        proposal or the tile-shared score proposal (tiles of 64 consecutive queries)."""
         q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
         prm = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
-        lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(prm), _p(out), threads)
+        lib().orc_sbh_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, rr_mode, _p(prm), int(bool(tiles)),
+                             _p(out), threads)
         return out
 
     def mlp_features(self, nodes, queries):

@@ -676,6 +676,70 @@ static void learned_q(const orc_tree* t, const float* prm, int64_t T, const doub
     }
 }
 
+/* Score proposal of one query: pi_c = max(score_c / max score, e^-16)
+ * normalised over the non-empty slots (uniform over them when every score is
+ * 0), i.e. the softmax of 16 f with the features above; by slot. */
+static void score_pi(const orc_tree* t, int64_t T, const double q[3], double pi[8])
+{
+    double sc[8], smax = 0.0, tot = 0.0;
+    int ne[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) { sc[k] = 0.0; pi[k] = 0.0; }
+    for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+        double r2 = dist2(&t->com[3 * ch], q), s2 = t->spr[ch];
+        double v = (r2 + s2 > 0.0) ? t->mass[ch] * s2 / pow(r2 + s2, 1.5) : 0.0;
+        sc[t->digit[ch]] = v;
+        ne[t->digit[ch]] = 1;
+        if (v > smax) smax = v;
+    }
+    for (int k = 0; k < 8; ++k) {
+        if (!ne[k]) continue;
+        double r = smax > 0.0 ? sc[k] / smax : 1.0;
+        pi[k] = r > exp(-16.0) ? r : exp(-16.0);
+        tot += pi[k];
+    }
+    for (int k = 0; k < 8; ++k) pi[k] /= tot;
+}
+
+/* Which child distribution the estimator uses at internal nodes:
+ *   prm != NULL: the learned proposal of each query (learned_q);
+ *   tile != NULL: the tile-shared score proposal: queries are grouped in tiles
+ *     of 64 consecutive indices, and every query of a tile uses
+ *     q_c = (1 - LAMBDA) mean over the tile of score_pi_c + LAMBDA n_c / n_T
+ *     (tile = the tile's query positions, ntile of them);
+ *   neither: the uniform path index. */
+typedef struct {
+    const float* prm;
+    const float* tile;
+    int64_t ntile;
+} proposal;
+
+/* q_c per child of internal node T (children order); returns 0 for the uniform path index */
+static int proposal_q(const orc_tree* t, const proposal* pr, int64_t T, const double q[3], double qc[8],
+                      int slots[8], int* nk)
+{
+    if (pr && pr->prm) {
+        learned_q(t, pr->prm, T, q, qc, slots, nk);
+        return 1;
+    }
+    if (pr && pr->tile) {
+        double mean[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pi[8];
+        for (int64_t i = 0; i < pr->ntile; ++i) {
+            double qi[3] = {pr->tile[3 * i], pr->tile[3 * i + 1], pr->tile[3 * i + 2]};
+            score_pi(t, T, qi, pi);
+            for (int k = 0; k < 8; ++k) mean[k] += pi[k];
+        }
+        *nk = t->nchild[T];
+        for (int i = 0; i < t->nchild[T]; ++i) {
+            int64_t ch = t->first_child[T] + i;
+            slots[i] = t->digit[ch];
+            qc[i] = (1.0 - MLP_LAMBDA) * mean[slots[i]] / (double)pr->ntile +
+                    MLP_LAMBDA * (double)t->count[ch] / (double)t->count[T];
+        }
+        return 1;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Stochastic path estimator: Eqs. (5)-(7), Section 3.3.1, Algorithm 2.       */
 /* ------------------------------------------------------------------------ */
@@ -704,7 +768,7 @@ typedef struct {
  * counter = (sigma, a_slot*S + s, step/2, batch), key = (seed lo, seed hi). */
 static path_out sample_path(const orc_tree* t, const kparams* kp, const double q[3], int64_t a,
                             uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode,
-                            const float* prm)
+                            const proposal* prop)
 {
     path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
@@ -739,11 +803,10 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
             }
             q_c = (double)t->count[c] / (double)nT;
-            if (prm) {
-                /* learned proposal: inverse-CDF selection over the slots with a 24-bit uniform */
-                double qv[8];
-                int slots[8], nk;
-                learned_q(t, prm, T, q, qv, slots, &nk);
+            double qv[8];
+            int slots[8], nk;
+            if (proposal_q(t, prop, T, q, qv, slots, &nk)) {
+                /* learned or score proposal: inverse-CDF selection over the slots with a 24-bit uniform */
                 double u_sel = (double)(x_sel >> 8) * (1.0 / 16777216.0), cum = 0.0;
                 int ci = nk - 1;
                 for (int i = 0; i < nk; ++i) {
@@ -801,7 +864,8 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
  * [n][d^3][S] x int32{begin, level, steps, flags} (absent slots: begin -1). */
 void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
              int S, uint64_t seed, int G, uint32_t batch, int rr_mode, const int64_t* qindex, const float* prm,
-             double* out, double* min_margin, double* absum, double* sens, int32_t* paths, int nthreads)
+             const float* tile_all, int64_t n_all, double* out, double* min_margin, double* absum, double* sens,
+             int32_t* paths, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
     int d3 = t->d * t->d * t->d;
@@ -814,6 +878,12 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
         double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
         int64_t jj = qindex ? qindex[j] : j;   /* the query's index in the full query set */
         uint32_t sigma = (uint32_t)(G == 1 ? jj : jj / G);
+        proposal prop = {prm, NULL, 0};
+        if (tile_all) {   /* the tile of 64 consecutive indices holding jj, within the full query set */
+            int64_t t0 = (jj / 64) * 64, t1 = t0 + 64 < n_all ? t0 + 64 : n_all;
+            prop.tile = &tile_all[3 * t0];
+            prop.ntile = t1 - t0;
+        }
         double F = 0.0, A = 0.0, SN = 0.0, mg = INFINITY;
         if (paths)
             for (int k = 0; k < d3 * S; ++k) {
@@ -831,7 +901,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
                 double Fa = 0.0, Aa = 0.0, Sa = 0.0;
                 for (int s = 0; s < S; ++s) {
                     path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode,
-                                              prm);
+                                              &prop);
                     Fa += po.value;
                     Aa += po.absum;
                     Sa += po.sens;
@@ -862,7 +932,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
 /* V(a).  Exponential in nothing: one visit per node per query.             */
 /* ------------------------------------------------------------------------ */
 static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3], int64_t T, double tT,
-                         double ps, double pr, int rr_mode, const float* prm)
+                         double ps, double pr, int rr_mode, const proposal* prop)
 {
     int64_t nT = t->count[T];
     if (nT == 1) return 0.0;
@@ -876,12 +946,12 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         double delta = sum - tT;
         double qv[8];
         int slots[8], nk;
-        if (prm) learned_q(t, prm, T, q, qv, slots, &nk);
+        int nonuni = proposal_q(t, prop, T, q, qv, slots, &nk);
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
-            double qc = prm ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
+            double qc = nonuni ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
             double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / diam_c);
             double tc = node_term(t, kp, ch, q);
-            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prm));
+            total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prop));
         }
     } else {
         double sum = 0.0;
@@ -897,7 +967,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
 }
 
 void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
-                    int rr_mode, const float* prm, double* out, int nthreads)
+                    int rr_mode, const float* prm, int tiles, double* out, int nthreads)
 {
     kparams kp = {kernel, eps, alpha};
 #ifdef _OPENMP
@@ -907,11 +977,17 @@ void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, 
     for (int64_t j = 0; j < n; ++j) {
         double q[3] = {qry[3 * j], qry[3 * j + 1], qry[3 * j + 2]};
         if (!is_internal(t, 0)) { out[j] = leaf_exact(t, &kp, 0, q); continue; }
+        proposal prop = {prm, NULL, 0};
+        if (tiles) {   /* tile-shared score proposal over the tiles of 64 consecutive queries */
+            int64_t t0 = (j / 64) * 64, t1 = t0 + 64 < n ? t0 + 64 : n;
+            prop.tile = &qry[3 * t0];
+            prop.ntile = t1 - t0;
+        }
         double F = 0.0;
         for (int ci = 0; ci < t->nchild[0]; ++ci) {
             int64_t a = t->first_child[0] + ci;
             double cv = node_term(t, &kp, a, q);
-            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode, prm);
+            F += cv + expect_rec(t, &kp, q, a, cv, 1.0, 1.0, rr_mode, &prop);
         }
         out[j] = F;
     }

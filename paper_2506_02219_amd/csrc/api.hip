@@ -60,7 +60,9 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (!(o.alpha > 0.0f) || !std::isfinite(o.alpha)) return fail(SBH_EINVAL, "alpha must be finite and > 0");
     if (o.group < 1) return fail(SBH_EINVAL, "group must be >= 1");
     if (o.rr_mode < 0 || o.rr_mode > 2) return fail(SBH_EINVAL, "rr_mode must be 0, 1 or 2");
-    if (o.proposal < 0 || o.proposal > 2) return fail(SBH_EINVAL, "proposal must be 0, 1 or 2");
+    if (o.proposal < 0 || o.proposal > 3) return fail(SBH_EINVAL, "proposal must be 0, 1, 2 or 3");
+    if (o.proposal == 3 && o.group % 64 != 0)
+        return fail(SBH_EINVAL, "the tile-shared score proposal needs group a multiple of 64");
     if (o.proposal == 1 && !o.mlp) return fail(SBH_EINVAL, "the learned proposal needs opts->mlp");
     return SBH_OK;
 }
@@ -169,8 +171,10 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     e.eps = o.eps;
     e.alpha = o.alpha;
     e.paths = samples > 0 ? o.paths : nullptr;
-    const bool learned = samples > 0 && o.proposal != 0;
-    if (learned && t->d != 2) return fail(SBH_EUNSUPPORTED, "sbh_eval: proposals 1 and 2 need branching 2");
+    const bool learned = samples > 0 && (o.proposal == 1 || o.proposal == 2);
+    if (samples > 0 && o.proposal != 0 && t->d != 2)
+        return fail(SBH_EUNSUPPORTED, "sbh_eval: proposals 1, 2 and 3 need branching 2");
+    e.tile_score = (samples > 0 && o.proposal == 3) ? 1 : 0;
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;
     if (samples == 0) err = sbh::launch_bh_eval(t, queries, nq, e, out, stream);

@@ -397,12 +397,16 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         float sumc = 0.0f, tC = 0.0f;
         if (internal) {
             if constexpr (D == 2) {
-                // only the non-empty slots (about half of them on a surface), by a scalar loop
-                // over the ballot's set bits
-                for (uint64_t m = nonempty; m != 0ull; m &= m - 1ull) {
-                    const int c = __ffsll((unsigned long long)m) - 1;
+                // the block in one batch of scalar loads; only the non-empty slots (about half
+                // of them on a surface) are evaluated, behind wavefront-uniform branches
+                float4 g8[D3];
+#pragma unroll
+                for (int c = 0; c < D3; ++c) g8[c] = ba[c];
+#pragma unroll
+                for (int c = 0; c < D3; ++c) {
+                    if (!((nonempty >> c) & 1ull)) continue;
                     const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                    const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                    const float v = term<K>(g8[c], gd, qx, qy, qz, kp, r0);
                     sumc += v;
                     if (c == csel) tC = v;
                 }
@@ -453,9 +457,232 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     return acc;
 }
 
+// Sum over the 64 lanes of eight values per lane, in a fixed order: three
+// halving exchanges leave lane l with one partial sum of value l >> 3, three
+// more complete it; value c is then in lanes 8c .. 8c + 7.
+__device__ __forceinline__ float wave_sum8(const float v[8])
+{
+    const int l = threadIdx.x & 63;
+    const bool b5 = (l >> 5) & 1, b4 = (l >> 4) & 1, b3 = (l >> 3) & 1;
+    float w4[4], w2[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float send = b5 ? v[i] : v[4 + i];
+        const float keep = b5 ? v[4 + i] : v[i];
+        w4[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float send = b4 ? w4[i] : w4[2 + i];
+        const float keep = b4 ? w4[2 + i] : w4[i];
+        w2[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    float w = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8, 64);
+    w += __shfl_xor(w, 4, 64);
+    w += __shfl_xor(w, 2, 64);
+    w += __shfl_xor(w, 1, 64);
+    return w;
+}
+
+// The coherent walk with the tile-shared score proposal (d = 2): at an
+// internal node every lane computes its own score proposal pi_c (the
+// relative quadrupole scores of the children, floored at e^-16), the
+// wavefront averages them over its valid lanes (the tile of 64 consecutive
+// queries), and the shared path draws the child from
+//   q_c = (1 - 1/8) mean pi_c + (1/8) n_c / n_T,
+// so that the walk stays shared; each lane's swap is divided by the product
+// of the q's drawn (Eq. (7) with p(I in T) = prod q).  The child block is
+// scanned before the selection (its distances feed the scores).
+template <int K, bool TRACE>
+__device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, float qy, float qz, float r0,
+                                                const KParams& kp, bool valid, float inv_valid, uint32_t n_a,
+                                                uint32_t begin_a, int32_t blk_a, float4 agg_a, float t_a,
+                                                uint32_t ctr0, uint32_t ctr1, uint32_t ctr3, uint32_t key0,
+                                                uint32_t key1, int rr_mode, int4* rec)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kLam = 0.125f;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ln = threadIdx.x & 63;
+    uint32_t nT = n_a, beginT = begin_a;
+    int32_t blk = blk_a;
+    int level = 1;
+    float diamT = tv.diam0 * 0.5f;
+    bool act = valid;
+    float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
+    float tT = t_a, prr = 1.0f, psel = 1.0f, acc = 0.0f;
+    int steps = 0, flag = 0;
+    int32_t end_b = (int32_t)beginT, end_l = level;
+    const u32x4 vr = philox4x32_10(ctr0, ctr1, (uint32_t)ln, ctr3, key0, key1);
+    for (int k = 0;; ++k) {
+        if (__ballot(act) == 0ull) break;
+        if (nT == 1u) {
+            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+            break;
+        }
+        const int pair = k >> 1;
+        const uint32_t xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, pair);
+        const uint32_t xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, pair);
+        const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
+        float4 aggC;
+        uint32_t nC = 1u, beginC;
+        int32_t blkC = 0;
+        float sumc = 0.0f, tC = 0.0f, qsel;
+        uint32_t rleaf = 0u;
+        uint64_t nonempty_step = 0ull;
+        int csel_step = 0;
+        int32_t blk_step = 0;
+        if (internal) {
+            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+            const float* __restrict__ bs = tv.bspr + (int64_t)blk * D3;
+            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+            const uint32_t cl = ln < D3 ? bt[ln] : 0u;
+            uint32_t inc = cl;
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);
+            const uint32_t excl = inc - cl;
+            const uint64_t im = __ballot(ln < D3 && (int)cl > tv.leaf_size && level + 1 < tv.max_level);
+            const uint64_t nonempty = __ballot(ln < D3 && cl != 0u);
+            // this lane's scores from the block (one batch of scalar loads); the terms of the
+            // swap wait until the roulette has kept some lane
+            float4 g8[D3];
+            float s8[D3], pi[D3];
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                g8[c] = ba[c];
+                s8[c] = bs[c];
+            }
+            float smax = 0.0f;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                pi[c] = 0.0f;
+                if (!((nonempty >> c) & 1ull)) continue;
+                const float x = norm2(g8[c].x - qx, g8[c].y - qy, g8[c].z - qz) + s8[c];
+                const float rs = x > 0.0f ? __builtin_amdgcn_rsqf(x) : 0.0f;
+                pi[c] = g8[c].w * s8[c] * (rs * rs * rs);
+                smax = fmaxf(smax, pi[c]);
+            }
+            const float inv = smax > 0.0f ? frcp(smax) : 0.0f;
+            float tot = 0.0f;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                const float r = smax > 0.0f ? fmaxf(pi[c] * inv, 1.12535175e-7f) : 1.0f;
+                pi[c] = ((nonempty >> c) & 1ull) ? r : 0.0f;
+                tot += pi[c];
+            }
+            const float invt = valid ? frcp(tot) : 0.0f;   // lanes past the end of the query set add nothing
+#pragma unroll
+            for (int c = 0; c < D3; ++c) pi[c] *= invt;
+            const float msum = wave_sum8(pi);                 // lane 8c holds the sum of pi_c
+            // q and the inverse-CDF selection, the same in every lane (uniform values)
+            const float u_sel = (float)(xsel >> 8) * 5.9604644775390625e-8f;
+            const float fnT = frcp((float)nT);
+            float cum = 0.0f;
+            int csel = -1, last = 0;
+            float qL = 0.0f;
+            qsel = 0.0f;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                if (!((nonempty >> c) & 1ull)) continue;
+                const float mc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(msum), 8 * c));
+                const uint32_t nc = (uint32_t)__builtin_amdgcn_readlane((int)cl, c);
+                const float qc = (1.0f - kLam) * (mc * inv_valid) + kLam * ((float)nc * fnT);
+                cum += qc;
+                last = c;
+                qL = qc;
+                if (csel < 0 && u_sel < cum) {
+                    csel = c;
+                    qsel = qc;
+                }
+            }
+            if (csel < 0) {   // rounding left the total just below u: the last non-empty slot
+                csel = last;
+                qsel = qL;
+            }
+            csel = __builtin_amdgcn_readfirstlane(csel);
+            qsel = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(qsel)));
+            const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+            nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+            aggC = ba[csel];
+            nonempty_step = nonempty;
+            csel_step = csel;
+            blk_step = blk;
+            beginC = beginT + preC;
+            blkC = (int32_t)bt[D3] + __popcll(im & ((1ull << csel) - 1ull));
+        } else {
+            rleaf = __umulhi(xsel, nT);
+            aggC = tv.pts[beginT + rleaf];
+            beginC = beginT + rleaf;
+            qsel = frcp((float)nT);
+        }
+        float p, dC = 0.0f;
+        if (rr_mode == 0) {
+            dC = fsqrt(norm2(aggC.x - qx, aggC.y - qy, aggC.z - qz));
+            p = fminf(1.0f, fmaxf(diamT, dT) * frcp(2.0f * dC));
+        } else {
+            p = rr_mode == 1 ? 1.0f : 0.5f;
+        }
+        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+        const bool cont = act && (u < p);
+        if (act && !cont) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        if (__ballot(cont) == 0ull) break;
+        if (internal) {   // contribution swap over the non-empty children, Eq. (6)
+            const float4* __restrict__ ba = tv.bagg + (int64_t)blk_step * D3;
+            const float4* __restrict__ bd = tv.bdip + (int64_t)blk_step * D3;
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                if (!((nonempty_step >> c) & 1ull)) continue;
+                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                sumc += v;
+                if (c == csel_step) tC = v;
+            }
+        } else {   // leaf: its points are the virtual children
+            for (uint32_t i = 0; i < nT; ++i) {
+                const float4 g = tv.pts[beginT + i];
+                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+            }
+        }
+        if (cont) {
+            prr *= p;
+            acc += (sumc - tT) * frcp(psel * prr);
+            ++steps;
+            tT = tC;
+        }
+        psel *= qsel;
+        if (!internal) {
+            if (cont) {
+                flag = 2;
+                end_b = (int32_t)beginC;
+                end_l = level + 1;
+            }
+            break;
+        }
+        act = cont;
+        dT = dC;
+        nT = nC;
+        beginT = beginC;
+        blk = blkC;
+        ++level;
+        diamT *= 0.5f;
+    }
+    if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
+    return acc;
+}
+
 // One wavefront-tile of 64 consecutive queries (j = 64 wave + lane) with the
 // shared walk; used by the single-tree kernel and by the batched kernel.
-template <int D, int K, bool TRACE>
+// TILE: the tile-shared score proposal (d = 2) instead of the uniform path index.
+template <int D, int K, bool TRACE, bool TILE = false>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave)
 {
@@ -479,6 +706,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
         r0 = cube_distance(tv, qx, qy, qz);
     }
     const uint32_t stream = (uint32_t)(j0 / a.group);   // a.group is a multiple of 64
+    const float inv_valid = 1.0f / (float)__popcll(__ballot(valid));
+    (void)inv_valid;
     const uint32_t* __restrict__ rt = tv.btopo;
     const int32_t base_root = (int32_t)rt[D3];
     uint32_t begin_a = 0u;
@@ -501,8 +730,14 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
         float fa = 0.0f;
         for (int s = 0; s < a.samples; ++s) {
             int4 rec;
-            fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, stream,
-                                         (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1, a.rr_mode, &rec);
+            if constexpr (TILE && D == 2)
+                fa += wave_path_tile<K, TRACE>(tv, qx, qy, qz, r0, kp, valid, inv_valid, n_a, begin_a, blk_a, agg_a,
+                                               cv, stream, (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1,
+                                               a.rr_mode, &rec);
+            else
+                fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, stream,
+                                             (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1, a.rr_mode,
+                                             &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
             }
@@ -523,6 +758,15 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
 {
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     sbh_wave_tile<D, K, TRACE>(tv, queries, nq, a, out, wave);
+}
+
+// the coherent walk with the tile-shared score proposal (d = 2)
+template <int K, bool TRACE>
+__global__ void __launch_bounds__(256)
+k_sbh_wave_tile(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
+{
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    sbh_wave_tile<2, K, TRACE, true>(tv, queries, nq, a, out, wave);
 }
 
 // ---------------------------------------------------------------------------
@@ -677,7 +921,7 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
 // One launch per (branching factor, kernel) group present in the batch, so
 // that each instance keeps the registers of the single-tree kernel.
 template <int D, int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_sbh_batch(const BatchItem* __restrict__ items, int count, uint32_t total_items, int wpi, BatchState* st,
             SbhArgs base)
 {
@@ -735,6 +979,14 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
               e.eps * e.eps, e.alpha, e.paths};
     if (e.group % 64 == 0) {
         const unsigned blocks = (unsigned)((nq + 255) / 256);
+        if (e.tile_score) {
+            if constexpr (D == 2) {
+                if (e.paths) k_sbh_wave_tile<K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+                else k_sbh_wave_tile<K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
         if (e.paths) k_sbh_wave<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
         else k_sbh_wave<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
         return hipGetLastError();

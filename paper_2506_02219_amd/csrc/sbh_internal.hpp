@@ -185,6 +185,7 @@ struct EvalLaunch {
     float beta;
     float eps, alpha;
     int32_t* paths;
+    int tile_score;     // coherent walk with the tile-shared score proposal (d = 2, group % 64 == 0)
 };
 
 hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,

@@ -112,12 +112,13 @@ def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
 
 def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, eps=1e-3, alpha=100.0,
               index=None, gpu_out=None, gpu_paths=None, batch=0, mlp=None, near_tie=NEAR_TIE,
-              max_divergent=1e-5, proposal=None):
+              max_divergent=1e-5, proposal=None, tile_all=None):
     """Run (or take) the GPU estimator and compare with the oracle, query by query.
     With `index`, `queries` are a subset of a larger set evaluated on the GPU
     (gpu_out/gpu_paths are the full-set outputs).  mlp: float32 network
     parameters (numpy) for the learned proposal on both sides; proposal=2 runs the
-    score proposal on the GPU against the oracle's all-zero network."""
+    score proposal on the GPU against the oracle's all-zero network; proposal=3 the tile-shared
+    score proposal (tile_all: the full query set when `queries` is a subset)."""
     d3 = gt.branching ** 3
     if gpu_out is None:
         q = T(queries)
@@ -132,7 +133,8 @@ def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, ep
         gp = gpu_paths[index]
     r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps, alpha=alpha,
                paths=True, index=index, batch=batch,
-               params=np.zeros(oracle.MLP_NPARAM, np.float32) if proposal == 2 else mlp)
+               params=np.zeros(oracle.MLP_NPARAM, np.float32) if proposal == 2 else mlp,
+               tile_queries=(queries if tile_all is None else tile_all) if proposal == 3 else None)
     near = r["margin"] < near_tie
     path_bad = np.any(gp != r["paths"], axis=(1, 2, 3))
     ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha, r["sens"])

@@ -18,17 +18,23 @@ pytestmark = pytest.mark.gpu
 NSAMPLE = 1500
 
 
-def run_full(cl, group, samples, alpha=100.0, d=2):
-    gt = P.sbh_build(T(cl.sources), T(cl.weights), None if cl.normals is None else T(cl.normals), branching=d)
-    ot = oracle.Tree(cl.sources, cl.weights, cl.normals, d=d, leaf_size=8)
-    compare_trees(gt, ot)
+def run_full(cl, group, samples, alpha=100.0, d=2, proposal=None, trees=None):
+    if trees is None:
+        gt = P.sbh_build(T(cl.sources), T(cl.weights), None if cl.normals is None else T(cl.normals), branching=d)
+        ot = oracle.Tree(cl.sources, cl.weights, cl.normals, d=d, leaf_size=8)
+        compare_trees(gt, ot)
+    else:
+        gt, ot = trees
     q = T(cl.queries)
     paths = torch.empty((cl.n, d ** 3, samples, 4), dtype=torch.int32, device=DEV)
-    out = host(P.sbh_eval(gt, q, cl.kernel, samples=samples, seed=0, group=group, alpha=alpha, paths=paths))
+    out = host(P.sbh_eval(gt, q, cl.kernel, samples=samples, seed=0, group=group, alpha=alpha, paths=paths,
+                          proposal=proposal))
     pth = host(paths)
     idx = np.sort(np.random.Generator(np.random.PCG64(17)).choice(cl.n, NSAMPLE, replace=False))
     st = check_sbh(gt, ot, cl.queries[idx], cl.kernel, samples=samples, seed=0, group=group, alpha=alpha,
-                   index=idx, gpu_out=out, gpu_paths=pth)
+                   index=idx, gpu_out=out, gpu_paths=pth, proposal=proposal,
+                   tile_all=cl.queries if proposal == 3 else None,
+                   max_divergent=3e-3 if proposal else 1e-5)
     return gt, ot, st
 
 
@@ -70,6 +76,9 @@ def test_c5_potential_fullsize(c5):
     gt, ot, st = run_full(cl, 64, 1)
     print(st)
     print(bh_sampled(gt, ot, cl))
+    # the plane in its own order with the tile-shared score proposal (same trees)
+    grid = W.Cloud(c5.sources, c5.weights, None, c5.queries, c5.kernel)
+    print(run_full(grid, 64, 1, proposal=3, trees=(gt, ot))[2])
 
 
 @pytest.mark.parametrize("samples", [1, 4])

@@ -294,3 +294,39 @@ def test_learned_root_leaf_is_exact_and_branching_four_is_refused():
     with pytest.raises(P.SbhError) as e:
         P.sbh_eval(g4, T(q), P.POTENTIAL, samples=1, mlp=T(random_params(46)))
     assert "SBH_EUNSUPPORTED" in str(e.value)
+
+
+# ----------------------------------------------------------------------------- tile-shared score proposal
+def grid_rows(n, y0=-0.9, dy=0.2):
+    """rows of 64 neighbouring pixels (a grid in its own order), n queries"""
+    xs = (np.arange(64) + 0.5) * (3.0 / 1000) - 0.4
+    rows = [np.stack([xs, np.full(64, y0 + dy * i), np.zeros(64)], 1) for i in range((n + 63) // 64)]
+    return np.concatenate(rows)[:n].astype(np.float32)
+
+
+@pytest.mark.parametrize("kernel", [P.POTENTIAL, P.WINDING, P.SMOOTHDIST])
+@pytest.mark.parametrize("samples,group", [(1, 64), (2, 128)])
+def test_tile_proposal_parity(kernel, samples, group):
+    pts, nrm, w, _ = surface_cloud()
+    q = grid_rows(1000)   # 15 full tiles and a ragged one
+    gt, ot = build_both(pts, w, nrm)
+    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=11, group=group, alpha=20.0, proposal=3,
+                    max_divergent=3e-3))
+
+
+def test_tile_proposal_random_queries_and_roulette_modes():
+    cl = W.c1()
+    gt, ot = build_both(cl.sources, cl.weights)
+    for rr in (0, 1, 2):
+        check_sbh(gt, ot, cl.queries[:1300], P.POTENTIAL, samples=1, seed=12, group=64, rr_mode=rr, proposal=3,
+                  max_divergent=3e-3)
+
+
+def test_tile_proposal_argument_errors():
+    cl = W.c1()
+    gt = P.sbh_build(T(cl.sources), T(cl.weights))
+    with pytest.raises(P.SbhError):
+        P.sbh_eval(gt, T(cl.queries[:100]), P.POTENTIAL, samples=1, group=1, proposal=3)
+    g4 = P.sbh_build(T(cl.sources), T(cl.weights), branching=4)
+    with pytest.raises(P.SbhError):
+        P.sbh_eval(g4, T(cl.queries[:100]), P.POTENTIAL, samples=1, group=64, proposal=3)

@@ -221,3 +221,50 @@ def test_training_pairs_follow_uniform_paths():
     # different seeds give different paths
     nd2 = t.mlp_pairs(20, seed=4)
     assert not np.array_equal(nd, nd2)
+
+
+# ----------------------------------------------------------------------------- tile-shared score proposal
+def _tile_case():
+    pts, nrm, w, _ = W.star_surface(3000, 41, level=3)
+    pts, w = pts.astype(np.float32), w.astype(np.float32)
+    t = oracle.Tree(pts, w, d=2, leaf_size=6)
+    # rows of 64 neighbouring pixels (as consecutive queries of a grid) and a partial last tile
+    xs = (np.arange(64) + 0.5) * (3.0 / 1000) - 0.6
+    q = np.concatenate([np.stack([xs, np.full(64, y), np.zeros(64)], 1) for y in (-0.9, 0.1, 1.25)])[:170]
+    return pts, w, t, q.astype(np.float32)
+
+
+@pytest.mark.parametrize("rr_mode", [0, 2])
+def test_tile_proposal_expectation_equals_brute_force(rr_mode):
+    """Theorem 1 with the tile-shared proposal: q depends on the node and the tile only."""
+    pts, w, t, q = _tile_case()
+    F = oracle.brute(pts, w, None, q, POT)
+    E = t.expect(q, POT, rr_mode=rr_mode, tiles=True)
+    assert np.all(np.abs(E - F) / np.abs(F) < 1e-11)
+
+
+def test_tile_of_one_query_is_that_querys_score_proposal():
+    """A tile holding a single query proposes exactly that query's score proposal (the zero
+    network), computed by another route (float32 features and the network's softmax)."""
+    pts, w, t, q = _tile_case()
+    zero = np.zeros(oracle.MLP_NPARAM, np.float32)
+    for j in (0, 77, 169):
+        a = t.sbh(q[j:j + 1], POT, samples=3, seed=5, paths=True, tile_queries=q[j:j + 1])
+        b = t.sbh(q[j:j + 1], POT, samples=3, seed=5, paths=True, params=zero)
+        assert np.array_equal(a["paths"], b["paths"]) or min(a["margin"][0], b["margin"][0]) < 1e-6
+        assert abs(a["F"][0] - b["F"][0]) <= 1e-6 * abs(b["F"][0])
+
+
+def test_tile_sampler_mean_converges_and_lowers_the_spread():
+    pts, w, t, q = _tile_case()
+    F = oracle.brute(pts, w, None, q, POT)
+    K = 1500
+    tile = np.array([t.sbh(q, POT, seed=900 + s, group=64, tile_queries=q)["F"] for s in range(K)])
+    uni = np.array([t.sbh(q, POT, seed=900 + s, group=64)["F"] for s in range(K)])
+    from scipy.stats import norm
+    z = norm.isf(1e-3 / (2 * len(F)))
+    se = tile.std(0, ddof=1) / math.sqrt(K)
+    assert np.all(np.abs(tile.mean(0) - F) <= z * se)
+    rt = np.median(np.sqrt(np.mean((tile - F) ** 2, 0)) / F)
+    ru = np.median(np.sqrt(np.mean((uni - F) ** 2, 0)) / F)
+    assert rt < 0.85 * ru, (rt, ru)
