@@ -53,6 +53,14 @@ typedef enum sbh_kernel {
     SBH_SMOOTHDIST = 2
 } sbh_kernel;
 
+/* Child-selection distributions of the estimator (sbh_eval_opts.proposal). */
+typedef enum sbh_proposal {
+    SBH_PROPOSAL_UNIFORM = 0,     /* the uniform path index (Section 3.3) */
+    SBH_PROPOSAL_LEARNED = 1,     /* the learned proposal (network parameters in opts->mlp) */
+    SBH_PROPOSAL_SCORE = 2,       /* per-query quadrupole-score proposal (the learned one with a zero network) */
+    SBH_PROPOSAL_TILE_SCORE = 3   /* the score proposal averaged over tiles of 64 consecutive queries */
+} sbh_proposal;
+
 typedef struct sbh_build_opts {
     int32_t branching;   /* per-dimension branching d: 2 (octree) or 4 (64-way); default 2 */
     int32_t leaf_size;   /* a node is split iff it holds more points than this; 1..64, default 8 */
@@ -77,7 +85,9 @@ typedef struct sbh_eval_opts {
                             sampled path: {end begin, end level, accepted steps, stop
                             reason (0 roulette, 1 one-point node, 2 virtual point)};
                             subdomain slots that are empty hold begin = -1.  NULL = off. */
-    const float* mlp;    /* DEVICE [SBH_MLP_NPARAM] network parameters for proposal 1; default NULL */
+    const float* mlp;    /* DEVICE [SBH_MLP_NPARAM] network parameters for proposal 1; default NULL.
+                            Parameters that are not all finite are ignored: the kernel then
+                            uses the score proposal (the zero network). */
 } sbh_eval_opts;
 
 typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */

@@ -198,7 +198,9 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
     paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records;
     mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal (1);
-    proposal: 0 uniform path index, 1 learned (needs mlp), 2 score proposal (default: 1 with mlp, else 0)."""
+    proposal: 0 uniform path index, 1 learned (needs mlp; parameters that are not all finite fall back
+    to the score proposal), 2 score proposal, 3 tile-shared score proposal (group a multiple of 64)
+    (default: 1 with mlp, else 0)."""
     import torch
     _dev(queries, "queries", (3,))
     nq = queries.shape[0]

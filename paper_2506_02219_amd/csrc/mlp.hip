@@ -604,7 +604,14 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         qz = queries[3 * j + 2];
     }
     MlpRegs R;
-    if constexpr (NET) mlp_load_regs(R, a.prm, lane);
+    bool net = NET;
+    if constexpr (NET) {
+        // parameters that are not all finite are ignored (the zero network: the score proposal)
+        bool bad = false;
+        for (int i = lane; i < kMlpParams; i += 64) bad |= !__builtin_isfinite(a.prm[i]);
+        net = __ballot(bad) == 0ull;
+        mlp_load_regs(R, a.prm, lane);
+    }
     KParams kp{a.eps2, a.alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
@@ -674,7 +681,12 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
             }
             float z[8];
             if constexpr (NET) {
-                if (__ballot(internal) != 0ull) mlp_forward_wave(R, f, z, lane);
+                if (net) {
+                    if (__ballot(internal) != 0ull) mlp_forward_wave(R, f, z, lane);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) z[c] = 16.0f * f[c];
+                }
             }
             if (!act) continue;
             float4 aggC;

@@ -330,3 +330,16 @@ def test_tile_proposal_argument_errors():
     g4 = P.sbh_build(T(cl.sources), T(cl.weights), branching=4)
     with pytest.raises(P.SbhError):
         P.sbh_eval(g4, T(cl.queries[:100]), P.POTENTIAL, samples=1, group=64, proposal=3)
+
+
+def test_non_finite_network_falls_back_to_the_score_proposal():
+    cl = W.c1()
+    gt = P.sbh_build(T(cl.sources), T(cl.weights))
+    q = T(cl.queries[:700])
+    bad = random_params(50, 1.0)
+    bad[123] = np.nan
+    bad[1500] = np.inf
+    a = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=2, seed=3, mlp=T(bad)))
+    zero = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=2, seed=3, mlp=T(np.zeros(P.MLP_NPARAM, np.float32))))
+    assert np.all(np.isfinite(a))
+    assert np.array_equal(a, zero)
