@@ -282,11 +282,55 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 // implementation section on 64-wide wavefronts.  Per query the subdomain
 // totals CV_a + F_a / S are added in slot order.
 // ---------------------------------------------------------------------------
+// max(a, b) of two non-negative finite floats as one instruction (fmaxf quiets
+// NaN inputs first, two more instructions that the walk does not need)
+__device__ __forceinline__ float vmax(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Random words of the coherent walk.  They do not depend on the query, so one
+// vector Philox evaluation serves eight paths of a wavefront: lane l holds the
+// block (counter word 2 = step pair) of step pair l & 7 of path 8m + (l >> 3).
+// Step k of path p reads its two words from lane 8 (p & 7) + k / 2.  Steps
+// past the sixteenth (rare: the roulette ends most paths within a few steps,
+// and trees are seldom that deep) compute their block again on the vector
+// unit (lane 0 holds it).  Counters are those of the per-query walk.
+struct PathWords {
+    u32x4 vr;
+    int chunk = -1;   // m of the eight paths held, -1 before the first
+    __device__ __forceinline__ void need(uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0, uint32_t key1)
+    {
+        if ((int)(path >> 3) != chunk) {
+            chunk = (int)(path >> 3);
+            const uint32_t l = threadIdx.x & 63;
+            vr = philox4x32_10(ctr0, (path & ~7u) + (l >> 3), l & 7u, ctr3, key0, key1);
+        }
+    }
+    // the two words (child selection, roulette) of step k of `path`
+    __device__ __forceinline__ void step(int k, uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0,
+                                         uint32_t key1, uint32_t& xsel, uint32_t& xrr) const
+    {
+        if (k < 16) {
+            const int src = (int)((path & 7u) << 3) + (k >> 1);
+            xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, src);
+            xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, src);
+        } else {
+            const u32x4 e = philox4x32_10(ctr0, path, (uint32_t)(k >> 1) + (threadIdx.x & 7u), ctr3, key0, key1);
+            xsel = __builtin_amdgcn_readlane((k & 1) ? e.z : e.x, 0);
+            xrr = __builtin_amdgcn_readlane((k & 1) ? e.w : e.y, 0);
+        }
+    }
+};
+
 template <int D, int K, bool TRACE>
 __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
                                            const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
-                                           int32_t blk_a, float4 agg_a, float t_a, uint32_t ctr0, uint32_t ctr1,
-                                           uint32_t ctr3, uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
+                                           int32_t blk_a, float4 agg_a, float t_a, const PathWords& pw,
+                                           uint32_t ctr0, uint32_t ctr1, uint32_t ctr3, uint32_t key0,
+                                           uint32_t key1, int rr_mode, int4* rec)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
@@ -298,29 +342,22 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     int32_t blk = blk_a;
     int level = 1;
     float diamT = tv.diam0 * kInvD;
-    float4 aggT = agg_a;
     const float fna = (float)n_a;
-    // per-lane state
+    // per-lane state; actm holds the lanes still walking (wavefront-uniform), kept as a mask
+    // so that the votes below are single compares
     bool act = valid;
+    uint64_t actm = __ballot(valid);
     float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));   // |com_T - q|, carried step to step
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    // The walk's random words do not depend on the query: lane l computes the
-    // Philox block of step pair l once per path (vector ALU), and step k reads
-    // its two words from lane k/2.  This takes the generator off the scalar
-    // unit, which the walk's control already keeps busy.  A walk has at most
-    // 2 max_level + 2 steps, far below 128.
-    const u32x4 vr = philox4x32_10(ctr0, ctr1, (uint32_t)(threadIdx.x & 63), ctr3, key0, key1);
-    for (int k = 0;; ++k) {
-        if (__ballot(act) == 0ull) break;
+    for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
-        const int pair = k >> 1;
-        const uint32_t xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, pair);
-        const uint32_t xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, pair);
+        uint32_t xsel, xrr;
+        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, xrr);
         const uint32_t r = __umulhi(xsel, nT);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
         const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
@@ -343,9 +380,10 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
                 const uint32_t excl = inc - cl;
-                const uint64_t hm = __ballot(ln < D3 && (r - excl) < cl);
-                const uint64_t im = __ballot(ln < D3 && (int)cl > tv.leaf_size && level + 1 < tv.max_level);
-                nonempty = __ballot(ln < D3 && cl != 0u);
+                // (lanes 8..63 hold a zero count: none of them votes)
+                const uint64_t hm = __ballot((r - excl) < cl);
+                const uint64_t im = level + 1 < tv.max_level ? __ballot((int)cl > tv.leaf_size) : 0ull;
+                nonempty = __ballot(cl != 0u);
                 csel = __ffsll((unsigned long long)hm) - 1;
                 const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
                 nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
@@ -381,18 +419,20 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         if (rr_mode == 0) {
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
             dC = fsqrt(norm2(cx, cy, cz));
-            p = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
+            p = fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
         const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
-        const bool cont = act && (u < p);
+        const bool lt = u < p;
+        const uint64_t contm = __ballot(lt) & actm;
+        const bool cont = act && lt;
         if (act && !cont) {
             flag = 0;
             end_b = (int32_t)beginT;
             end_l = level;
         }
-        if (__ballot(cont) == 0ull) break;
+        if (contm == 0ull) break;
         // contribution swap, Eq. (6)
         float sumc = 0.0f, tC = 0.0f;
         if (internal) {
@@ -404,7 +444,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 for (int c = 0; c < D3; ++c) g8[c] = ba[c];
 #pragma unroll
                 for (int c = 0; c < D3; ++c) {
-                    if (!((nonempty >> c) & 1ull)) continue;
+                    if (!(((uint32_t)nonempty >> c) & 1u)) continue;
                     const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
                     const float v = term<K>(g8[c], gd, qx, qy, qz, kp, r0);
                     sumc += v;
@@ -445,7 +485,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             break;
         }
         act = cont;
-        aggT = aggC;
+        actm = contm;
         dT = dC;
         nT = nC;
         beginT = beginC;
@@ -497,8 +537,8 @@ template <int K, bool TRACE>
 __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, float qy, float qz, float r0,
                                                 const KParams& kp, bool valid, float inv_valid, uint32_t n_a,
                                                 uint32_t begin_a, int32_t blk_a, float4 agg_a, float t_a,
-                                                uint32_t ctr0, uint32_t ctr1, uint32_t ctr3, uint32_t key0,
-                                                uint32_t key1, int rr_mode, int4* rec)
+                                                const PathWords& pw, uint32_t ctr0, uint32_t ctr1, uint32_t ctr3,
+                                                uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = 8;
@@ -515,16 +555,14 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
     float tT = t_a, prr = 1.0f, psel = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    const u32x4 vr = philox4x32_10(ctr0, ctr1, (uint32_t)ln, ctr3, key0, key1);
     for (int k = 0;; ++k) {
         if (__ballot(act) == 0ull) break;
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
-        const int pair = k >> 1;
-        const uint32_t xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, pair);
-        const uint32_t xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, pair);
+        uint32_t xsel, xrr;
+        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, xrr);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
         float4 aggC;
         uint32_t nC = 1u, beginC;
@@ -713,6 +751,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     uint32_t begin_a = 0u;
     int32_t nint = 0;
     float F = 0.0f;
+    PathWords pw;
     for (int slot = 0; slot < D3; ++slot) {
         const uint32_t n_a = rt[slot];
         if (n_a == 0u) {
@@ -730,14 +769,14 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
         float fa = 0.0f;
         for (int s = 0; s < a.samples; ++s) {
             int4 rec;
+            const uint32_t path = (uint32_t)(slot * a.samples + s);
+            pw.need(path, stream, a.batch, a.key0, a.key1);
             if constexpr (TILE && D == 2)
                 fa += wave_path_tile<K, TRACE>(tv, qx, qy, qz, r0, kp, valid, inv_valid, n_a, begin_a, blk_a, agg_a,
-                                               cv, stream, (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1,
-                                               a.rr_mode, &rec);
+                                               cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             else
-                fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, stream,
-                                             (uint32_t)(slot * a.samples + s), a.batch, a.key0, a.key1, a.rr_mode,
-                                             &rec);
+                fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw,
+                                             stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
             }
