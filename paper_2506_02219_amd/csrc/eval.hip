@@ -363,7 +363,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
         const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
         const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
-        float4 aggC;
+        float4 aggC, dpC = zero4;   // the selected child's aggregate (and dipole)
         uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
         int csel = 0;
@@ -373,22 +373,25 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 // child selection across lanes 0..7 (one slot each): an exclusive scan of the
                 // counts by DPP row shifts, then ballots give the slot whose range holds r, the
                 // internal slots before it and the non-empty slots
+                // (every lane loads one of the block's 16 words; lanes 8..63 then hold a zero count
+                // and none of them votes)
                 const int ln = threadIdx.x & 63;
-                const uint32_t cl = ln < D3 ? bt[ln] : 0u;
+                const uint32_t bw = bt[ln & 15];
+                const uint32_t cl = ln < D3 ? bw : 0u;
                 uint32_t inc = cl;
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
                 const uint32_t excl = inc - cl;
-                // (lanes 8..63 hold a zero count: none of them votes)
                 const uint64_t hm = __ballot((r - excl) < cl);
-                const uint64_t im = level + 1 < tv.max_level ? __ballot((int)cl > tv.leaf_size) : 0ull;
+                const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
                 nonempty = __ballot(cl != 0u);
                 csel = __ffsll((unsigned long long)hm) - 1;
                 const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
                 nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
                 const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
                 aggC = ba[csel];
+                if constexpr (K == SBH_WINDING) dpC = bd[csel];
                 beginC = beginT + preC;
                 blkC = (int32_t)bt[D3] + nintC;
             } else {
@@ -406,19 +409,24 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     pre += cnt;
                 }
                 aggC = ba[csel];
+                if constexpr (K == SBH_WINDING) dpC = bd[csel];
                 beginC = beginT + preC;
                 blkC = (int32_t)bt[D3] + nintC;
             }
         } else {
             aggC = tv.pts[beginT + r];
+            if constexpr (K == SBH_WINDING) dpC = tv.pdip[beginT + r];
             beginC = beginT + r;
         }
         // roulette first (Eq. (5)): the swap is only needed by lanes that continue
+        // (the offset and squared distance also give the selected child's own term below,
+        // bit for bit the value the swap's sum takes for it)
         float p;
         float dC = 0.0f;
+        const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+        const float r2C = norm2(cx, cy, cz);
         if (rr_mode == 0) {
-            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
-            dC = fsqrt(norm2(cx, cy, cz));
+            dC = fsqrt(r2C);
             p = fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
@@ -434,7 +442,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         }
         if (contm == 0ull) break;
         // contribution swap, Eq. (6)
-        float sumc = 0.0f, tC = 0.0f;
+        float sumc = 0.0f;
+        const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
         if (internal) {
             if constexpr (D == 2) {
                 // the block in one batch of scalar loads; only the non-empty slots (about half
@@ -446,9 +455,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 for (int c = 0; c < D3; ++c) {
                     if (!(((uint32_t)nonempty >> c) & 1u)) continue;
                     const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                    const float v = term<K>(g8[c], gd, qx, qy, qz, kp, r0);
-                    sumc += v;
-                    if (c == csel) tC = v;
+                    sumc += term<K>(g8[c], gd, qx, qy, qz, kp, r0);
                 }
             } else {
 #pragma unroll 8
@@ -456,18 +463,14 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     const uint32_t cnt = bt[c];
                     const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
                     const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
-                    const float vv = cnt ? v : 0.0f;
-                    sumc += vv;
-                    tC = (c == csel) ? vv : tC;
+                    sumc += cnt ? v : 0.0f;
                 }
             }
         } else {
             for (uint32_t i = 0; i < nT; ++i) {
                 const float4 g = tv.pts[beginT + i];
                 const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
-                const float v = term<K>(g, gd, qx, qy, qz, kp, r0);
-                sumc += v;
-                tC = (i == r) ? v : tC;
+                sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
             }
         }
         if (cont) {
