@@ -481,7 +481,7 @@ def main():
             network=proposal_curve(1, prm), score_only=proposal_curve(2, None))
         del X, Tg, Cn
 
-    # --- batched evaluation of 64 clouds of uneven size (one persistent launch, graph replay)
+    # --- batched evaluation of 64 clouds of uneven size (one launch per kernel group, graph replay)
     batched = None
     if c4 is not None:
         trees_b, qs_b, ks_b = [], [], []

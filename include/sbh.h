@@ -258,12 +258,13 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
                          hipStream_t stream, float* losses);
 
 /* ------------------------------------------------------------------------
- * Batched persistent evaluation: many trees and query sets (of uneven
- * sizes) evaluated by one persistent launch per (branching factor, kernel)
- * group present, replayed from a HIP graph.  A work item is a run of tile_waves wavefront-tiles (64
- * consecutive queries each) of one cloud; every wavefront takes items from a
- * device counter until none are left.  Each tile runs the same code as
- * sbh_eval with samples >= 1 and opts->group a multiple of 64, so every
+ * Batched evaluation: many trees and query sets (of uneven sizes) evaluated
+ * by one launch per (branching factor, kernel) group present, replayed from
+ * a HIP graph.  A work item is one workgroup of tile_waves wavefronts, each
+ * taking one tile (64 consecutive queries) of the same cloud; the hardware
+ * dispatcher starts workgroups as earlier ones finish, so clouds of uneven
+ * cost balance without a shared work counter.  Each tile runs the same code
+ * as sbh_eval with samples >= 1 and opts->group a multiple of 64, so every
  * cloud's output is bit-identical to its own sbh_eval call with the same
  * seed, batch word and options.
  * ------------------------------------------------------------------------ */
@@ -279,9 +280,10 @@ typedef struct sbh_batch_item {
 } sbh_batch_item;
 
 typedef struct sbh_batch_config {
-    int32_t tile_waves;      /* wavefront-tiles per work item, 1..1024 */
-    int32_t waves_per_simd;  /* persistent grid: 256 workgroups of 4 wavefronts per unit, 1..8 */
-    int32_t heavy_first;     /* 1: work items of the costliest clouds (queries x depth) first */
+    int32_t tile_waves;      /* wavefronts (64-query tiles) per workgroup: 1, 2 or 4 */
+    int32_t waves_per_simd;  /* 1..8: at most this many resident wavefronts per SIMD (8 = the hardware's
+                                own limit; below it, LDS is reserved per workgroup to cap residency) */
+    int32_t heavy_first;     /* 1: workgroups of the costliest clouds (queries x depth) first */
     float ms;                /* autotuned plans: measured time of one batch; else 0 */
 } sbh_batch_config;
 
@@ -292,12 +294,13 @@ typedef struct sbh_batch_config {
  *   sbh_eval with group a multiple of 64, proposal 0 and no path records
  *   (NULL: the defaults with group 64).
  *   config (host): the launch configuration, or NULL to autotune: every
- *   candidate (tile_waves 1, 2, 4, 8; waves_per_simd 4, 8; heavy_first 0, 1)
+ *   candidate (tile_waves 1, 2, 4; waves_per_simd 4, 8; heavy_first 0, 1)
  *   is timed on the batch itself (seed 0) and the fastest kept; this writes
  *   the outputs and synchronises `stream`.
  * The plan keeps pointers to the trees, queries and outputs, which must
  * stay valid (and the trees alive) until sbh_batch_free.  It allocates
- * 6 x 16 bytes of launch state and the descriptors on the current device.
+ * 6 x 16 bytes of launch state, the descriptors and the workgroup tables
+ * (8 bytes per tile) on the current device.
  * Errors: SBH_EINVAL, SBH_EUNSUPPORTED (proposal != 0), SBH_ENOMEM, SBH_EHIP.
  */
 sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t samples, const sbh_eval_opts* opts,

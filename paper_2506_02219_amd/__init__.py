@@ -321,7 +321,7 @@ def sbh_mlp_train(params, adam_state, features, targets, counts, steps, batch_ro
 
 class Batch:
     """A batch plan (sbh_batch*): trees, query sets and outputs of many clouds evaluated by one
-    persistent launch replayed from a HIP graph.  Keeps references to its trees and tensors."""
+    launch per group, replayed from a HIP graph.  Keeps references to its trees and tensors."""
 
     def __init__(self, trees, queries, kernels, samples=1, group=64, eps=1e-3, alpha=100.0, rr_mode=0,
                  config=None, outs=None, stream=None):

@@ -356,20 +356,23 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batched persistent evaluation
+// Batched evaluation
 // ---------------------------------------------------------------------------
 struct sbh_batch {
     int device = 0;
     int samples = 1;
     sbh_eval_opts opts{};
-    std::vector<sbh::BatchItem> clouds;   // as given (item_begin filled per configuration)
+    std::vector<sbh::BatchItem> clouds;   // as given
     std::vector<double> cost;             // work estimate per cloud
-    // groups g = 3 (d == 4) + kernel: one persistent launch each
-    sbh::BatchItem* d_items[sbh::kBatchGroups] = {};
-    int n_items[sbh::kBatchGroups] = {};
-    uint32_t total[sbh::kBatchGroups] = {};
+    // groups g = 3 (d == 4) + kernel: one launch each
+    sbh::BatchItem* d_items[sbh::kBatchGroups] = {};   // the group's clouds, in launch order
+    int2* d_wg[sbh::kBatchGroups] = {};                 // workgroup table: (cloud in d_items, first tile)
+    int64_t tiles[sbh::kBatchGroups] = {};              // 64-query tiles of the group (table capacity)
+    int n_wg[sbh::kBatchGroups] = {};
     sbh::BatchState* d_state = nullptr;   // [kBatchGroups]
     sbh_batch_config cfg{};
+    size_t lds_bytes = 0;                 // per workgroup, for the occupancy cap
+    int lds_per_cu = 0, lds_per_wg_max = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -383,35 +386,45 @@ void batch_release(sbh_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    for (int g = 0; g < sbh::kBatchGroups; ++g)
+    for (int g = 0; g < sbh::kBatchGroups; ++g) {
         if (b->d_items[g]) (void)hipFree(b->d_items[g]);
+        if (b->d_wg[g]) (void)hipFree(b->d_wg[g]);
+    }
     if (b->d_state) (void)hipFree(b->d_state);
 }
 
-// device descriptors for a configuration: clouds split by branching factor and
-// kernel, ordered as the configuration asks, with the prefix of their work items
+// Device descriptors and workgroup tables for a configuration: clouds split by
+// branching factor and kernel, ordered as the configuration asks; each
+// workgroup takes tile_waves consecutive tiles of one cloud.  The occupancy
+// cap reserves LDS so that at most 4 waves_per_simd / tile_waves workgroups
+// fit on a compute unit (4 SIMDs); 8 waves per SIMD is the hardware's own limit.
 hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
 {
     std::vector<int> order(b->clouds.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     if (c.heavy_first)
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+    b->lds_bytes = 0;
+    if (c.waves_per_simd < 8) {
+        const int per_cu = std::max(1, 4 * c.waves_per_simd / c.tile_waves);
+        size_t lds = (size_t)(b->lds_per_cu / per_cu) & ~(size_t)511;
+        b->lds_bytes = std::min(lds, (size_t)b->lds_per_wg_max);
+    }
     for (int g = 0; g < sbh::kBatchGroups; ++g) {
         std::vector<sbh::BatchItem> v;
-        int64_t next = 0;
-        for (int i : order) {
-            sbh::BatchItem it = b->clouds[i];
-            if (3 * (it.d == 4 ? 1 : 0) + it.kernel != g || it.nq == 0) continue;
-            it.item_begin = next;
+        std::vector<int2> wg;
+        for (int idx : order) {
+            const sbh::BatchItem& it = b->clouds[idx];
+            if ((it.d == 4 ? 3 : 0) + it.kernel != g) continue;
             const int64_t tiles = (it.nq + 63) / 64;
-            next += (tiles + c.tile_waves - 1) / c.tile_waves;
+            for (int64_t t = 0; t < tiles; t += c.tile_waves) wg.push_back(make_int2((int)v.size(), (int)t));
             v.push_back(it);
         }
-        b->n_items[g] = (int)v.size();
-        b->total[g] = (uint32_t)next;
+        b->n_wg[g] = (int)wg.size();
         if (!v.empty()) {
-            const hipError_t e = hipMemcpy(b->d_items[g], v.data(), v.size() * sizeof(sbh::BatchItem),
-                                           hipMemcpyHostToDevice);
+            hipError_t e = hipMemcpy(b->d_items[g], v.data(), v.size() * sizeof(sbh::BatchItem), hipMemcpyHostToDevice);
+            if (e == hipSuccess && !wg.empty())
+                e = hipMemcpy(b->d_wg[g], wg.data(), wg.size() * sizeof(int2), hipMemcpyHostToDevice);
             if (e != hipSuccess) return e;
         }
     }
@@ -421,12 +434,11 @@ hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
 hipError_t batch_enqueue(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_t s)
 {
     hipError_t e = sbh::launch_batch_begin(b->d_state, seed, batch, s);
-    const int blocks = 256 * b->cfg.waves_per_simd;   // 256 CUs; a block of 4 wavefronts puts one on each SIMD
     for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g)
-        if (b->total[g] > 0)
-            e = sbh::launch_sbh_batch(g < 3 ? 2 : 4, g % 3, b->d_items[g], b->n_items[g], b->total[g],
-                                      b->cfg.tile_waves, blocks, b->d_state + g, b->samples, b->opts.group,
-                                      b->opts.rr_mode, b->opts.eps, b->opts.alpha, s);
+        if (b->n_wg[g] > 0)
+            e = sbh::launch_sbh_batch(g < 3 ? 2 : 4, g % 3, b->d_items[g], b->d_wg[g], b->n_wg[g], b->cfg.tile_waves,
+                                      b->lds_bytes, b->d_state + g, b->samples, b->opts.group, b->opts.rr_mode,
+                                      b->opts.eps, b->opts.alpha, s);
     return e;
 }
 
@@ -449,8 +461,8 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: only the uniform proposal is batched");
     if (o.paths) return fail(SBH_EINVAL, "sbh_batch_create: path records are not available in a batch");
     if (config) {
-        if (config->tile_waves < 1 || config->tile_waves > 1024)
-            return fail(SBH_EINVAL, "sbh_batch_create: tile_waves must be in [1, 1024]");
+        if (config->tile_waves != 1 && config->tile_waves != 2 && config->tile_waves != 4)
+            return fail(SBH_EINVAL, "sbh_batch_create: tile_waves must be 1, 2 or 4");
         if (config->waves_per_simd < 1 || config->waves_per_simd > 8)
             return fail(SBH_EINVAL, "sbh_batch_create: waves_per_simd must be in [1, 8]");
         if (config->heavy_first != 0 && config->heavy_first != 1)
@@ -486,10 +498,16 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         it.root_leaf = it.tv.root_internal ? 0 : 1;
         b->clouds.push_back(it);
         b->cost.push_back((double)it.nq * (double)(t->depth + 1) * (it.kernel == SBH_WINDING ? 1.5 : 1.0) * samples);
+        b->tiles[(it.d == 4 ? 3 : 0) + it.kernel] += (it.nq + 63) / 64;
     }
-    hipError_t e = hipSuccess;
-    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g)
+    hipError_t e = hipDeviceGetAttribute(&b->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                         b->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&b->lds_per_wg_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);
+    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g) {
         e = hipMalloc((void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem));
+        if (e == hipSuccess && b->tiles[g] > 0) e = hipMalloc((void**)&b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2));
+    }
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, sbh::kBatchGroups * sizeof(sbh::BatchState));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -506,8 +524,8 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         float best = INFINITY;
-        sbh_batch_config best_cfg{1, 8, 1, 0.0f};
-        const int tws[] = {1, 2, 4, 8};
+        sbh_batch_config best_cfg{4, 8, 1, 0.0f};
+        const int tws[] = {1, 2, 4};
         const int wpss[] = {4, 8};
         for (int heavy = 0; heavy < 2 && e == hipSuccess; ++heavy)
             for (int tw : tws)

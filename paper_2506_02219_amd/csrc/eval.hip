@@ -76,7 +76,7 @@ __device__ __forceinline__ float4 sel4(bool c, float4 a, float4 b)
 // reported distance is r0 - (log(sum) + log(wbar)) / alpha.
 __device__ __forceinline__ void smooth_setup(const TreeView& tv, float& wscale, float& logwbar)
 {
-    const float wbar = tv.nagg[0].w / (float)tv.n_points;
+    const float wbar = gld4(tv.nagg).w / (float)tv.n_points;
     wscale = 1.0f / wbar;
     logwbar = logf(wbar);
 }
@@ -376,7 +376,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 // (every lane loads one of the block's 16 words; lanes 8..63 then hold a zero count
                 // and none of them votes)
                 const int ln = threadIdx.x & 63;
-                const uint32_t bw = bt[ln & 15];
+                const uint32_t bw = gld(bt + (ln & 15));
                 const uint32_t cl = ln < D3 ? bw : 0u;
                 uint32_t inc = cl;
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
@@ -390,16 +390,16 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
                 nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
                 const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
-                aggC = ba[csel];
-                if constexpr (K == SBH_WINDING) dpC = bd[csel];
+                aggC = gld4(ba + csel);
+                if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
                 beginC = beginT + preC;
-                blkC = (int32_t)bt[D3] + nintC;
+                blkC = (int32_t)gld(bt + D3) + nintC;
             } else {
                 // uniform child selection from the point counts alone
                 uint32_t pre = 0u, preC = 0u;
                 int32_t nint = 0, nintC = 0;
                 for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = bt[c];
+                    const uint32_t cnt = gld(bt + c);
                     const bool hit = (r - pre) < cnt;
                     csel = hit ? c : csel;
                     preC = hit ? pre : preC;
@@ -408,14 +408,14 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
                     pre += cnt;
                 }
-                aggC = ba[csel];
-                if constexpr (K == SBH_WINDING) dpC = bd[csel];
+                aggC = gld4(ba + csel);
+                if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
                 beginC = beginT + preC;
-                blkC = (int32_t)bt[D3] + nintC;
+                blkC = (int32_t)gld(bt + D3) + nintC;
             }
         } else {
-            aggC = tv.pts[beginT + r];
-            if constexpr (K == SBH_WINDING) dpC = tv.pdip[beginT + r];
+            aggC = gld4(tv.pts + beginT + r);
+            if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + r);
             beginC = beginT + r;
         }
         // roulette first (Eq. (5)): the swap is only needed by lanes that continue
@@ -450,26 +450,26 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 // of them on a surface) are evaluated, behind wavefront-uniform branches
                 float4 g8[D3];
 #pragma unroll
-                for (int c = 0; c < D3; ++c) g8[c] = ba[c];
+                for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
 #pragma unroll
                 for (int c = 0; c < D3; ++c) {
                     if (!(((uint32_t)nonempty >> c) & 1u)) continue;
-                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                     sumc += term<K>(g8[c], gd, qx, qy, qz, kp, r0);
                 }
             } else {
 #pragma unroll 8
                 for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = bt[c];
-                    const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                    const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                    const uint32_t cnt = gld(bt + c);
+                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                    const float v = term<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0);
                     sumc += cnt ? v : 0.0f;
                 }
             }
         } else {
             for (uint32_t i = 0; i < nT; ++i) {
-                const float4 g = tv.pts[beginT + i];
-                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                const float4 g = gld4(tv.pts + beginT + i);
+                const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
                 sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
             }
         }
@@ -736,9 +736,9 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     const bool valid = j < nq;
     float qx = 0.f, qy = 0.f, qz = 0.f;
     if (valid) {
-        qx = queries[3 * j];
-        qy = queries[3 * j + 1];
-        qz = queries[3 * j + 2];
+        qx = gld(queries + 3 * j);
+        qy = gld(queries + 3 * j + 1);
+        qz = gld(queries + 3 * j + 2);
     }
     KParams kp{a.eps2, a.alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
@@ -750,13 +750,13 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     const float inv_valid = 1.0f / (float)__popcll(__ballot(valid));
     (void)inv_valid;
     const uint32_t* __restrict__ rt = tv.btopo;
-    const int32_t base_root = (int32_t)rt[D3];
+    const int32_t base_root = (int32_t)gld(rt + D3);
     uint32_t begin_a = 0u;
     int32_t nint = 0;
     float F = 0.0f;
     PathWords pw;
     for (int slot = 0; slot < D3; ++slot) {
-        const uint32_t n_a = rt[slot];
+        const uint32_t n_a = gld(rt + slot);
         if (n_a == 0u) {
             if constexpr (TRACE) {
                 if (valid)
@@ -766,8 +766,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
             continue;
         }
         const int32_t blk_a = base_root + nint;
-        const float4 agg_a = tv.bagg[slot];
-        const float4 dip_a = (K == SBH_WINDING) ? tv.bdip[slot] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 agg_a = gld4(tv.bagg + slot);
+        const float4 dip_a = (K == SBH_WINDING) ? gld4(tv.bdip + slot) : make_float4(0.f, 0.f, 0.f, 0.f);
         const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);  // control variate CV_a
         float fa = 0.0f;
         for (int s = 0; s < a.samples; ++s) {
@@ -789,8 +789,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
         nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
     }
     if (valid) {
-        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(F) + logwbar) / a.alpha;
-        else out[j] = F;
+        if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(F) + logwbar) / a.alpha);
+        else gst(out + j, F);
     }
 }
 
@@ -917,7 +917,7 @@ __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float
                                                  float eps2, float alpha, float* __restrict__ out)
 {
 #pragma clang fp contract(off)
-    const float qx = queries[3 * j], qy = queries[3 * j + 1], qz = queries[3 * j + 2];
+    const float qx = gld(queries + 3 * j), qy = gld(queries + 3 * j + 1), qz = gld(queries + 3 * j + 2);
     KParams kp{eps2, alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
@@ -927,9 +927,9 @@ __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float acc = 0.0f;
     for (int i = 0; i < tv.n_points; ++i)
-        acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
-    if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(acc) + logwbar) / alpha;
-    else out[j] = acc;
+        acc += term<K>(gld4(tv.pts + i), (K == SBH_WINDING) ? gld4(tv.pdip + i) : zero4, qx, qy, qz, kp, r0);
+    if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(acc) + logwbar) / alpha);
+    else gst(out + j, acc);
 }
 
 template <int K>
@@ -942,12 +942,11 @@ __global__ void __launch_bounds__(256) k_leaf_exact(TreeView tv, const float* __
 }
 
 // ---------------------------------------------------------------------------
-// Batched persistent evaluation: many trees and query sets in one launch.
-// A work item is a run of `wpi` wavefront-tiles (64 queries each) of one
-// cloud; every wavefront takes items from a global counter until none are
-// left, so that small clouds fill the machine together and large ones are
-// split.  Each tile runs exactly the code of the single-tree kernels, so a
-// cloud's results do not depend on the batch around it.
+// Batched evaluation: many trees and query sets in one launch per group.
+// A work item is one workgroup: a run of wavefront-tiles (64 queries each)
+// of one cloud, so that small clouds fill the machine together and large
+// ones are split.  Each tile runs exactly the code of the single-tree
+// kernels, so a cloud's results do not depend on the batch around it.
 // ---------------------------------------------------------------------------
 // key, batch word and a cleared work counter for every group of the batch
 __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint32_t batch)
@@ -956,48 +955,37 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
         st[threadIdx.x].key0 = key0;
         st[threadIdx.x].key1 = key1;
         st[threadIdx.x].batch = batch;
-        st[threadIdx.x].counter = 0u;
+        st[threadIdx.x].pad = 0u;
     }
 }
 
 // One launch per (branching factor, kernel) group present in the batch, so
-// that each instance keeps the registers of the single-tree kernel.
+// that each instance keeps the registers of the single-tree kernel.  A
+// workgroup is one work item: consecutive tiles of one cloud, one per
+// wavefront, looked up in the workgroup table; the hardware dispatcher
+// starts workgroups as earlier ones finish, which balances clouds of uneven
+// cost without a shared work counter.
 template <int D, int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
-k_sbh_batch(const BatchItem* __restrict__ items, int count, uint32_t total_items, int wpi, BatchState* st,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, const BatchState* __restrict__ st,
             SbhArgs base)
 {
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        uint32_t t = 0u;
-        if (lane == 0) t = atomicAdd(&st->counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= total_items) break;   // every wavefront ends here once the counter has passed the last item
-        int lo = 0, hi = count - 1;    // the last cloud whose first item is <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].item_begin <= (int64_t)t) lo = mid;
-            else hi = mid - 1;
-        }
-        // the descriptor stays in memory and its fields are read where they are used (scalar
-        // loads), as kernel arguments are: a register copy would not fit beside the walk
-        const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(lo);
-        SbhArgs a = base;
-        a.key0 = st->key0;
-        a.key1 = st->key1;
-        a.batch = st->batch;
-        const int64_t nq = it->nq;
-        const int64_t w0 = ((int64_t)t - it->item_begin) * wpi;
-        for (int w = 0; w < wpi; ++w) {
-            const int64_t wave = w0 + w;
-            if (wave * 64 >= nq) break;
-            if (it->root_leaf) {
-                const int64_t j = wave * 64 + lane;
-                if (j < nq) leaf_exact_query<K>(it->tv, it->queries, j, a.eps2, a.alpha, it->out);
-            } else {
-                sbh_wave_tile<D, K, false>(it->tv, it->queries, nq, a, it->out, wave);
-            }
-        }
+    const int2 w = wg[blockIdx.x];
+    const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(w.x);
+    const int64_t wave = (int64_t)__builtin_amdgcn_readfirstlane(w.y) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nq = it->nq;
+    if (wave * 64 >= nq) return;
+    SbhArgs a = base;
+    a.key0 = st->key0;
+    a.key1 = st->key1;
+    a.batch = st->batch;
+    // the descriptor stays in memory and its fields are read where they are used
+    // (scalar loads), as kernel arguments are
+    if (it->root_leaf) {
+        const int64_t j = wave * 64 + (threadIdx.x & 63);
+        if (j < nq) leaf_exact_query<K>(it->tv, it->queries, j, a.eps2, a.alpha, it->out);
+    } else {
+        sbh_wave_tile<D, K, false>(it->tv, it->queries, nq, a, it->out, wave);
     }
 }
 
@@ -1087,12 +1075,13 @@ hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hip
     return hipGetLastError();
 }
 
-hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, int count, uint32_t total_items, int wpi,
-                            int blocks, BatchState* st, int samples, int group, int rr_mode, float eps, float alpha,
-                            hipStream_t s)
+hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int2* wg, int blocks, int tile_waves,
+                            size_t lds_bytes, const BatchState* st, int samples, int group, int rr_mode, float eps,
+                            float alpha, hipStream_t s)
 {
     SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
-#define SBH_LAUNCH_B(DD, KK) k_sbh_batch<DD, KK><<<blocks, 256, 0, s>>>(items, count, total_items, wpi, st, a)
+    const dim3 block(64 * tile_waves);
+#define SBH_LAUNCH_B(DD, KK) k_sbh_batch<DD, KK><<<blocks, block, lds_bytes, s>>>(items, wg, st, a)
     if (d == 2) {
         if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(2, SBH_POTENTIAL);
         else if (kernel == SBH_WINDING) SBH_LAUNCH_B(2, SBH_WINDING);

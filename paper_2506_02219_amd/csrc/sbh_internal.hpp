@@ -52,6 +52,22 @@ struct TreeView {
     float diam0;          // root cell diagonal; level l has diam0 / d^l
 };
 
+// Loads and stores through the global address space.  Kernels that read
+// their tree pointers from memory (batched descriptors) would otherwise see
+// generic addresses and use flat vector loads where scalar loads serve; for
+// pointers passed as kernel arguments these are the loads the compiler emits
+// anyway.
+#define SBH_GLOBAL __attribute__((address_space(1)))
+typedef float sbh_f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gld4(const float4* p)
+{
+    const sbh_f32x4 v = *(const SBH_GLOBAL sbh_f32x4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float gld(const float* p) { return *(const SBH_GLOBAL float*)p; }
+__device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const SBH_GLOBAL uint32_t*)p; }
+__device__ __forceinline__ void gst(float* p, float v) { *(SBH_GLOBAL float*)p = v; }
+
 struct sbh_tree_impl {
     int device;
     int d, d3, bits, leaf_size, max_level, depth, has_normals;
@@ -206,17 +222,19 @@ struct BatchItem {          // one cloud of a batch (device copy)
     const float* queries;
     float* out;
     int64_t nq;
-    int64_t item_begin;     // index of the cloud's first work item
     int32_t kernel, d, root_leaf, pad;
 };
-struct BatchState {         // per-launch key and batch word, and the work counter of one group
-    uint32_t key0, key1, batch, counter;
+struct BatchState {         // per-launch Philox key and batch word
+    uint32_t key0, key1, batch, pad;
 };
 constexpr int kBatchGroups = 6;   // (branching factor 2 or 4) x (kernel)
 hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hipStream_t s);
-hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, int count, uint32_t total_items, int wpi,
-                            int blocks, BatchState* st, int samples, int group, int rr_mode, float eps, float alpha,
-                            hipStream_t s);
+// One launch of a group: workgroup b (of `blocks`, each of `tile_waves` wavefronts) evaluates tiles
+// wg[b].y, wg[b].y + 1, ... of cloud items[wg[b].x]; `lds_bytes` of dynamic LDS per workgroup (not
+// touched) cap the number of workgroups resident on a compute unit.
+hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int2* wg, int blocks, int tile_waves,
+                            size_t lds_bytes, const BatchState* st, int samples, int group, int rr_mode, float eps,
+                            float alpha, hipStream_t s);
 void* batch_begin_kernel();
 
 // learned proposal (mlp.hip)

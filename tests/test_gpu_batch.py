@@ -1,5 +1,5 @@
-"""Batched persistent evaluation (sbh_batch_*): many clouds of uneven size in
-one persistent launch replayed from a HIP graph.
+"""Batched evaluation (sbh_batch_*): many clouds of uneven size in one launch
+per group, replayed from a HIP graph.
 
 Bar: every cloud's output is bit-identical to its own sbh_eval call (same
 seed, batch word and options), for the autotuned and for fixed launch
@@ -47,7 +47,7 @@ def single(trees, qs, kernels, samples, seed, batch):
             for t, q, k in zip(trees, qs, kernels)]
 
 
-@pytest.mark.parametrize("config", [None, (1, 8, 0), (4, 4, 1), (3, 1, 0)])
+@pytest.mark.parametrize("config", [None, (1, 8, 0), (4, 4, 1), (2, 1, 0), (1, 3, 1)])
 def test_batch_equals_single_calls(config):
     clouds, trees, qs = make_batch()
     kernels = [s[2] for s in SPECS]
@@ -98,6 +98,10 @@ def test_batch_argument_errors():
     with pytest.raises(P.SbhError):
         P.Batch(trees, qs, [0, 1], group=32)            # not a multiple of 64
     with pytest.raises(P.SbhError):
-        P.Batch(trees, qs, [0, 1], config=(0, 8, 0))   # tile_waves < 1
+        P.Batch(trees, qs, [0, 1], config=(0, 8, 0))   # tile_waves not 1, 2 or 4
+    with pytest.raises(P.SbhError):
+        P.Batch(trees, qs, [0, 1], config=(3, 8, 0))
+    with pytest.raises(P.SbhError):
+        P.Batch(trees, qs, [0, 1], config=(2, 9, 0))   # waves_per_simd > 8
     with pytest.raises(P.SbhError):
         P.Batch(trees[:1], qs[:1], [1])                 # winding on a tree without normals
