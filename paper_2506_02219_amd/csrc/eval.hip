@@ -282,6 +282,10 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 // implementation section on 64-wide wavefronts.  Per query the subdomain
 // totals CV_a + F_a / S are added in slot order.
 // ---------------------------------------------------------------------------
+// The uniform variate of a 32-bit random word: its top 24 bits times 2^-24
+// (exactly representable, in [0, 1)).
+__device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
+
 // max(a, b) of two non-negative finite floats as one instruction (fmaxf quiets
 // NaN inputs first, two more instructions that the walk does not need)
 __device__ __forceinline__ float vmax(float a, float b)
@@ -294,7 +298,8 @@ __device__ __forceinline__ float vmax(float a, float b)
 // Random words of the coherent walk.  They do not depend on the query, so one
 // vector Philox evaluation serves eight paths of a wavefront: lane l holds the
 // block (counter word 2 = step pair) of step pair l & 7 of path 8m + (l >> 3).
-// Step k of path p reads its two words from lane 8 (p & 7) + k / 2.  Steps
+// Step k of path p reads its two words from lane 8 (p & 7) + k / 2, the
+// roulette word already as its uniform variate u = (x >> 8) 2^-24.  Steps
 // past the sixteenth (rare: the roulette ends most paths within a few steps,
 // and trees are seldom that deep) compute their block again on the vector
 // unit (lane 0 holds it).  Counters are those of the per-query walk.
@@ -307,20 +312,22 @@ struct PathWords {
             chunk = (int)(path >> 3);
             const uint32_t l = threadIdx.x & 63;
             vr = philox4x32_10(ctr0, (path & ~7u) + (l >> 3), l & 7u, ctr3, key0, key1);
+            vr.y = __float_as_uint(unit24(vr.y));
+            vr.w = __float_as_uint(unit24(vr.w));
         }
     }
-    // the two words (child selection, roulette) of step k of `path`
+    // the selection word and the roulette variate of step k of `path`
     __device__ __forceinline__ void step(int k, uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0,
-                                         uint32_t key1, uint32_t& xsel, uint32_t& xrr) const
+                                         uint32_t key1, uint32_t& xsel, float& u) const
     {
         if (k < 16) {
             const int src = (int)((path & 7u) << 3) + (k >> 1);
             xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, src);
-            xrr = __builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, src);
+            u = __uint_as_float(__builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, src));
         } else {
             const u32x4 e = philox4x32_10(ctr0, path, (uint32_t)(k >> 1) + (threadIdx.x & 7u), ctr3, key0, key1);
             xsel = __builtin_amdgcn_readlane((k & 1) ? e.z : e.x, 0);
-            xrr = __builtin_amdgcn_readlane((k & 1) ? e.w : e.y, 0);
+            u = unit24(__builtin_amdgcn_readlane((k & 1) ? e.w : e.y, 0));
         }
     }
 };
@@ -351,13 +358,17 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
+    // all ones in lanes 0 .. D^3 - 1: the lanes that hold a child slot's count (kept in a
+    // vector register; as a lane mask it would take scalar registers for the whole walk)
+    uint32_t keep = (threadIdx.x & 63) < D3 ? ~0u : 0u;
     for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
-        uint32_t xsel, xrr;
-        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, xrr);
+        uint32_t xsel;
+        float u;
+        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
         const uint32_t r = __umulhi(xsel, nT);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
         const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
@@ -377,7 +388,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 // and none of them votes)
                 const int ln = threadIdx.x & 63;
                 const uint32_t bw = gld(bt + (ln & 15));
-                const uint32_t cl = ln < D3 ? bw : 0u;
+                const uint32_t cl = bw & keep;
                 uint32_t inc = cl;
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
@@ -431,7 +442,6 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
-        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
         const bool lt = u < p;
         const uint64_t contm = __ballot(lt) & actm;
         const bool cont = act && lt;
@@ -564,8 +574,9 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
-        uint32_t xsel, xrr;
-        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, xrr);
+        uint32_t xsel;
+        float u;
+        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
         float4 aggC;
         uint32_t nC = 1u, beginC;
@@ -667,7 +678,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
-        const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+
         const bool cont = act && (u < p);
         if (act && !cont) {
             flag = 0;
