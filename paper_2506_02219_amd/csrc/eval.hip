@@ -358,9 +358,6 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    // all ones in lanes 0 .. D^3 - 1: the lanes that hold a child slot's count (kept in a
-    // vector register; as a lane mask it would take scalar registers for the whole walk)
-    uint32_t keep = (threadIdx.x & 63) < D3 ? ~0u : 0u;
     for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
@@ -384,11 +381,11 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 // child selection across lanes 0..7 (one slot each): an exclusive scan of the
                 // counts by DPP row shifts, then ballots give the slot whose range holds r, the
                 // internal slots before it and the non-empty slots
-                // (every lane loads one of the block's 16 words; lanes 8..63 then hold a zero count
-                // and none of them votes)
+                // (lanes 8..63 load the block's last word, padding that the build leaves zero: they
+                // hold a zero count and none of them votes)
+                static_assert(TS - 1 > D3, "the topology row needs a padding word");
                 const int ln = threadIdx.x & 63;
-                const uint32_t bw = gld(bt + (ln & 15));
-                const uint32_t cl = bw & keep;
+                const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
                 uint32_t inc = cl;
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
                 inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
