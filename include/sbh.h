@@ -260,8 +260,8 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
 /* ------------------------------------------------------------------------
  * Batched evaluation: many trees and query sets (of uneven sizes) evaluated
  * by one launch per (branching factor, kernel) group present, replayed from
- * a HIP graph.  A work item is one workgroup of tile_waves wavefronts, each
- * taking one tile (64 consecutive queries) of the same cloud; the hardware
+ * a HIP graph.  A work item is one workgroup that evaluates tile_waves tiles
+ * (64 consecutive queries each) of the same cloud; the hardware
  * dispatcher starts workgroups as earlier ones finish, so clouds of uneven
  * cost balance without a shared work counter.  Each tile runs the same code
  * as sbh_eval with samples >= 1 and opts->group a multiple of 64, so every
@@ -280,9 +280,10 @@ typedef struct sbh_batch_item {
 } sbh_batch_item;
 
 typedef struct sbh_batch_config {
-    int32_t tile_waves;      /* wavefronts (64-query tiles) per workgroup: 1, 2 or 4 */
-    int32_t waves_per_simd;  /* 1..8: at most this many resident wavefronts per SIMD (8 = the hardware's
-                                own limit; below it, LDS is reserved per workgroup to cap residency) */
+    int32_t tile_waves;      /* 64-query tiles per workgroup: 1 or 2 */
+    int32_t waves_per_simd;  /* 1..8: resident wavefronts per SIMD to aim for (8 = the hardware's own
+                                limit; below it, LDS is reserved per workgroup to cap residency, as far
+                                as the per-workgroup LDS limit allows) */
     int32_t heavy_first;     /* 1: workgroups of the costliest clouds (queries x depth) first */
     float ms;                /* autotuned plans: measured time of one batch; else 0 */
 } sbh_batch_config;
@@ -294,7 +295,7 @@ typedef struct sbh_batch_config {
  *   sbh_eval with group a multiple of 64, proposal 0 and no path records
  *   (NULL: the defaults with group 64).
  *   config (host): the launch configuration, or NULL to autotune: every
- *   candidate (tile_waves 1, 2, 4; waves_per_simd 4, 8; heavy_first 0, 1)
+ *   candidate (tile_waves 1, 2; waves_per_simd 4, 8; heavy_first 0, 1)
  *   is timed on the batch itself (seed 0) and the fastest kept; this writes
  *   the outputs and synchronises `stream`.
  * The plan keeps pointers to the trees, queries and outputs, which must

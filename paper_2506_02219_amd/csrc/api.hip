@@ -364,14 +364,15 @@ struct sbh_batch {
     sbh_eval_opts opts{};
     std::vector<sbh::BatchItem> clouds;   // as given
     std::vector<double> cost;             // work estimate per cloud
-    // groups g = 3 (d == 4) + kernel: one launch each
-    sbh::BatchItem* d_items[sbh::kBatchGroups] = {};   // the group's clouds, in launch order
-    int2* d_wg[sbh::kBatchGroups] = {};                 // workgroup table: (cloud in d_items, first tile)
-    int64_t tiles[sbh::kBatchGroups] = {};              // 64-query tiles of the group (table capacity)
-    int n_wg[sbh::kBatchGroups] = {};
+    // groups g = 3 (d == 4) + kernel for the walk, 6 + kernel for root leaves: one launch each
+    sbh::BatchItem* d_items[sbh::kBatchLaunchGroups] = {};   // the group's clouds, in launch order
+    int2* d_wg[sbh::kBatchLaunchGroups] = {};                 // workgroup table: (cloud in d_items, first tile)
+    int64_t tiles[sbh::kBatchLaunchGroups] = {};              // 64-query tiles of the group (table capacity)
+    int n_wg[sbh::kBatchLaunchGroups] = {};
     sbh::BatchState* d_state = nullptr;   // [kBatchGroups]
     sbh_batch_config cfg{};
     size_t lds_bytes = 0;                 // per workgroup, for the occupancy cap
+    size_t lds_static = 0;                // the batch kernels' own LDS per workgroup
     int lds_per_cu = 0, lds_per_wg_max = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -386,7 +387,7 @@ void batch_release(sbh_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    for (int g = 0; g < sbh::kBatchGroups; ++g) {
+    for (int g = 0; g < sbh::kBatchLaunchGroups; ++g) {
         if (b->d_items[g]) (void)hipFree(b->d_items[g]);
         if (b->d_wg[g]) (void)hipFree(b->d_wg[g]);
     }
@@ -395,9 +396,16 @@ void batch_release(sbh_batch* b)
 
 // Device descriptors and workgroup tables for a configuration: clouds split by
 // branching factor and kernel, ordered as the configuration asks; each
-// workgroup takes tile_waves consecutive tiles of one cloud.  The occupancy
-// cap reserves LDS so that at most 4 waves_per_simd / tile_waves workgroups
-// fit on a compute unit (4 SIMDs); 8 waves per SIMD is the hardware's own limit.
+// workgroup takes tile_waves consecutive tiles of one cloud (kWaveParts
+// wavefronts each).  The occupancy cap reserves LDS so that at most
+// 4 waves_per_simd / (tile_waves kWaveParts) workgroups fit on a compute unit
+// (4 SIMDs); 8 waves per SIMD is the hardware's own limit.
+// the launch group of a cloud: the walk by (branching factor, kernel), or the exact sum of a root leaf
+int batch_group(const sbh::BatchItem& it)
+{
+    return it.root_leaf ? sbh::kBatchGroups + it.kernel : (it.d == 4 ? 3 : 0) + it.kernel;
+}
+
 hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
 {
     std::vector<int> order(b->clouds.size());
@@ -406,16 +414,18 @@ hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
     b->lds_bytes = 0;
     if (c.waves_per_simd < 8) {
-        const int per_cu = std::max(1, 4 * c.waves_per_simd / c.tile_waves);
-        size_t lds = (size_t)(b->lds_per_cu / per_cu) & ~(size_t)511;
-        b->lds_bytes = std::min(lds, (size_t)b->lds_per_wg_max);
+        // a workgroup's LDS (its own arrays plus the reservation) is the unit's share
+        // for per_cu workgroups, so that one more does not fit
+        const int per_cu = std::max(1, 4 * c.waves_per_simd / (c.tile_waves * sbh::kWaveParts));
+        const size_t total = std::min((size_t)(b->lds_per_cu / per_cu), (size_t)b->lds_per_wg_max) & ~(size_t)511;
+        b->lds_bytes = total > b->lds_static ? total - b->lds_static : 0;
     }
-    for (int g = 0; g < sbh::kBatchGroups; ++g) {
+    for (int g = 0; g < sbh::kBatchLaunchGroups; ++g) {
         std::vector<sbh::BatchItem> v;
         std::vector<int2> wg;
         for (int idx : order) {
             const sbh::BatchItem& it = b->clouds[idx];
-            if ((it.d == 4 ? 3 : 0) + it.kernel != g) continue;
+            if (batch_group(it) != g) continue;
             const int64_t tiles = (it.nq + 63) / 64;
             for (int64_t t = 0; t < tiles; t += c.tile_waves) wg.push_back(make_int2((int)v.size(), (int)t));
             v.push_back(it);
@@ -434,11 +444,16 @@ hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
 hipError_t batch_enqueue(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_t s)
 {
     hipError_t e = sbh::launch_batch_begin(b->d_state, seed, batch, s);
-    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g)
-        if (b->n_wg[g] > 0)
+    for (int g = 0; g < sbh::kBatchLaunchGroups && e == hipSuccess; ++g) {
+        if (b->n_wg[g] == 0) continue;
+        if (g < sbh::kBatchGroups)
             e = sbh::launch_sbh_batch(g < 3 ? 2 : 4, g % 3, b->d_items[g], b->d_wg[g], b->n_wg[g], b->cfg.tile_waves,
                                       b->lds_bytes, b->d_state + g, b->samples, b->opts.group, b->opts.rr_mode,
                                       b->opts.eps, b->opts.alpha, s);
+        else
+            e = sbh::launch_leaf_batch(g - sbh::kBatchGroups, b->d_items[g], b->d_wg[g], b->n_wg[g], b->cfg.tile_waves,
+                                       b->opts.eps, b->opts.alpha, s);
+    }
     return e;
 }
 
@@ -461,8 +476,8 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: only the uniform proposal is batched");
     if (o.paths) return fail(SBH_EINVAL, "sbh_batch_create: path records are not available in a batch");
     if (config) {
-        if (config->tile_waves != 1 && config->tile_waves != 2 && config->tile_waves != 4)
-            return fail(SBH_EINVAL, "sbh_batch_create: tile_waves must be 1, 2 or 4");
+        if (config->tile_waves < 1 || config->tile_waves > sbh::kBatchMaxTileWaves)
+            return fail(SBH_EINVAL, "sbh_batch_create: tile_waves must be 1 or 2");
         if (config->waves_per_simd < 1 || config->waves_per_simd > 8)
             return fail(SBH_EINVAL, "sbh_batch_create: waves_per_simd must be in [1, 8]");
         if (config->heavy_first != 0 && config->heavy_first != 1)
@@ -498,13 +513,14 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         it.root_leaf = it.tv.root_internal ? 0 : 1;
         b->clouds.push_back(it);
         b->cost.push_back((double)it.nq * (double)(t->depth + 1) * (it.kernel == SBH_WINDING ? 1.5 : 1.0) * samples);
-        b->tiles[(it.d == 4 ? 3 : 0) + it.kernel] += (it.nq + 63) / 64;
+        b->tiles[batch_group(it)] += (it.nq + 63) / 64;
     }
     hipError_t e = hipDeviceGetAttribute(&b->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
                                          b->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&b->lds_per_wg_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);
-    for (int g = 0; g < sbh::kBatchGroups && e == hipSuccess; ++g) {
+    if (e == hipSuccess) e = sbh::batch_static_lds(&b->lds_static);
+    for (int g = 0; g < sbh::kBatchLaunchGroups && e == hipSuccess; ++g) {
         e = hipMalloc((void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem));
         if (e == hipSuccess && b->tiles[g] > 0) e = hipMalloc((void**)&b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2));
     }
@@ -524,8 +540,8 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         float best = INFINITY;
-        sbh_batch_config best_cfg{4, 8, 1, 0.0f};
-        const int tws[] = {1, 2, 4};
+        sbh_batch_config best_cfg{1, 8, 1, 0.0f};
+        const int tws[] = {1, 2};
         const int wpss[] = {4, 8};
         for (int heavy = 0; heavy < 2 && e == hipSuccess; ++heavy)
             for (int tw : tws)

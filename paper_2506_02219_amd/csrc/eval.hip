@@ -30,6 +30,8 @@
 
 #include <cmath>
 
+#include <algorithm>
+
 #include "sbh_internal.hpp"
 
 namespace sbh {
@@ -731,12 +733,22 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
 // One wavefront-tile of 64 consecutive queries (j = 64 wave + lane) with the
 // shared walk; used by the single-tree kernel and by the batched kernel.
 // TILE: the tile-shared score proposal (d = 2) instead of the uniform path index.
-template <int D, int K, bool TRACE, bool TILE = false>
+// A tile's root slots may be split over P wavefronts of one workgroup: part p
+// takes slots [p D^3 / P, (p + 1) D^3 / P) and keeps its own sum; the last
+// part of the tile to finish adds the P sums in part order and writes the
+// output.  This shortens the chain of dependent steps one wavefront walks
+// (the launch's floor on its duration) at the price of one more Philox
+// evaluation per part.  LDS: part_f [wavefronts of the block][64] and one
+// counter per tile of the block in `done`, zeroed before the block's first
+// barrier.
+template <int D, int K, bool TRACE, bool TILE = false, int P = 1>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
-                                              const SbhArgs& a, float* __restrict__ out, int64_t wave)
+                                              const SbhArgs& a, float* __restrict__ out, int64_t wave, int part = 0,
+                                              int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
+    static_assert(D3 % P == 0, "parts must split the root slots evenly");
     const int lane = threadIdx.x & 63;
     const int64_t j0 = wave * 64;
     if (j0 >= nq) return;
@@ -759,11 +771,17 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     (void)inv_valid;
     const uint32_t* __restrict__ rt = tv.btopo;
     const int32_t base_root = (int32_t)gld(rt + D3);
+    const int slot_lo = part * (D3 / P), slot_hi = slot_lo + D3 / P;
     uint32_t begin_a = 0u;
     int32_t nint = 0;
+    for (int slot = 0; slot < slot_lo; ++slot) {   // points and internal blocks of the slots before the part
+        const uint32_t n_a = gld(rt + slot);
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
     float F = 0.0f;
     PathWords pw;
-    for (int slot = 0; slot < D3; ++slot) {
+    for (int slot = slot_lo; slot < slot_hi; ++slot) {
         const uint32_t n_a = gld(rt + slot);
         if (n_a == 0u) {
             if constexpr (TRACE) {
@@ -796,6 +814,18 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
         begin_a += n_a;
         nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
     }
+    if constexpr (P > 1) {
+        const int tl = w / P;   // the tile's index within the block
+        part_f[w][lane] = F;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t prev = 0u;
+        if (lane == 0) prev = __hip_atomic_fetch_add(&done[tl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__builtin_amdgcn_readfirstlane(prev) != (uint32_t)(P - 1)) return;   // another part finishes the tile
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        F = part_f[tl * P][lane];
+#pragma unroll
+        for (int q = 1; q < P; ++q) F += part_f[tl * P + q][lane];
+    }
     if (valid) {
         if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(F) + logwbar) / a.alpha);
         else gst(out + j, F);
@@ -806,8 +836,16 @@ template <int D, int K, bool TRACE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    sbh_wave_tile<D, K, TRACE>(tv, queries, nq, a, out, wave);
+    constexpr int P = kWaveParts, TPB = 4 / P;   // 4 wavefronts per block, TPB tiles
+    __shared__ float part_f[4][64];
+    __shared__ uint32_t done[TPB];
+    if constexpr (P > 1) {
+        if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
+    sbh_wave_tile<D, K, TRACE, false, P>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // the coherent walk with the tile-shared score proposal (d = 2)
@@ -974,13 +1012,21 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
 // starts workgroups as earlier ones finish, which balances clouds of uneven
 // cost without a shared work counter.
 template <int D, int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(64 * kBatchMaxTileWaves * kWaveParts) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, const BatchState* __restrict__ st,
             SbhArgs base)
 {
-    const int2 w = wg[blockIdx.x];
-    const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(w.x);
-    const int64_t wave = (int64_t)__builtin_amdgcn_readfirstlane(w.y) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int P = kWaveParts;
+    __shared__ float part_f[kBatchMaxTileWaves * P][64];
+    __shared__ uint32_t done[kBatchMaxTileWaves];
+    if constexpr (P > 1) {
+        if (threadIdx.x < kBatchMaxTileWaves) done[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const int2 g = wg[blockIdx.x];
+    const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(g.x);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wave = (int64_t)__builtin_amdgcn_readfirstlane(g.y) + w / P;   // the tile
     const int64_t nq = it->nq;
     if (wave * 64 >= nq) return;
     SbhArgs a = base;
@@ -989,12 +1035,20 @@ k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, co
     a.batch = st->batch;
     // the descriptor stays in memory and its fields are read where they are used
     // (scalar loads), as kernel arguments are
-    if (it->root_leaf) {
-        const int64_t j = wave * 64 + (threadIdx.x & 63);
-        if (j < nq) leaf_exact_query<K>(it->tv, it->queries, j, a.eps2, a.alpha, it->out);
-    } else {
-        sbh_wave_tile<D, K, false>(it->tv, it->queries, nq, a, it->out, wave);
-    }
+    sbh_wave_tile<D, K, false, false, P>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
+}
+
+// Clouds whose root is a leaf are summed exactly, as sbh_eval does, in launches
+// of their own (one per kernel): kept out of k_sbh_batch, the branch would
+// cost the walk its registers.
+template <int K>
+__global__ void __launch_bounds__(64 * kBatchMaxTileWaves)
+k_leaf_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, float eps2, float alpha)
+{
+    const int2 g = wg[blockIdx.x];
+    const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(g.x);
+    const int64_t j = ((int64_t)__builtin_amdgcn_readfirstlane(g.y) + (threadIdx.x >> 6)) * 64 + (threadIdx.x & 63);
+    if (j < it->nq) leaf_exact_query<K>(it->tv, it->queries, j, eps2, alpha, it->out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,8 +1079,10 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             }
             return hipErrorInvalidValue;
         }
-        if (e.paths) k_sbh_wave<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
-        else k_sbh_wave<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        const int64_t tiles = (nq + 63) / 64;
+        const unsigned wblocks = (unsigned)((tiles + (4 / kWaveParts) - 1) / (4 / kWaveParts));
+        if (e.paths) k_sbh_wave<D, K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+        else k_sbh_wave<D, K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
         return hipGetLastError();
     }
     const int64_t waves = (nq + QPW - 1) / QPW;
@@ -1088,7 +1144,7 @@ hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int
                             float alpha, hipStream_t s)
 {
     SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
-    const dim3 block(64 * tile_waves);
+    const dim3 block(64 * tile_waves * kWaveParts);
 #define SBH_LAUNCH_B(DD, KK) k_sbh_batch<DD, KK><<<blocks, block, lds_bytes, s>>>(items, wg, st, a)
     if (d == 2) {
         if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(2, SBH_POTENTIAL);
@@ -1103,6 +1159,35 @@ hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int
     return hipGetLastError();
 }
 
+hipError_t launch_leaf_batch(int kernel, const BatchItem* items, const int2* wg, int blocks, int tile_waves, float eps,
+                             float alpha, hipStream_t s)
+{
+    const dim3 block(64 * tile_waves);
+    if (kernel == SBH_POTENTIAL) k_leaf_batch<SBH_POTENTIAL><<<blocks, block, 0, s>>>(items, wg, eps * eps, alpha);
+    else if (kernel == SBH_WINDING) k_leaf_batch<SBH_WINDING><<<blocks, block, 0, s>>>(items, wg, eps * eps, alpha);
+    else k_leaf_batch<SBH_SMOOTHDIST><<<blocks, block, 0, s>>>(items, wg, eps * eps, alpha);
+    return hipGetLastError();
+}
+
 void* batch_begin_kernel() { return reinterpret_cast<void*>(&k_batch_begin); }
+
+hipError_t batch_static_lds(size_t* bytes)
+{
+    size_t m = 0;
+    const void* fns[] = {reinterpret_cast<const void*>(&k_sbh_batch<2, SBH_POTENTIAL>),
+                         reinterpret_cast<const void*>(&k_sbh_batch<2, SBH_WINDING>),
+                         reinterpret_cast<const void*>(&k_sbh_batch<2, SBH_SMOOTHDIST>),
+                         reinterpret_cast<const void*>(&k_sbh_batch<4, SBH_POTENTIAL>),
+                         reinterpret_cast<const void*>(&k_sbh_batch<4, SBH_WINDING>),
+                         reinterpret_cast<const void*>(&k_sbh_batch<4, SBH_SMOOTHDIST>)};
+    for (const void* f : fns) {
+        hipFuncAttributes fa{};
+        const hipError_t e = hipFuncGetAttributes(&fa, f);
+        if (e != hipSuccess) return e;
+        m = std::max(m, (size_t)fa.sharedSizeBytes);
+    }
+    *bytes = m;
+    return hipSuccess;
+}
 
 }  // namespace sbh

@@ -228,6 +228,11 @@ struct BatchState {         // per-launch Philox key and batch word
     uint32_t key0, key1, batch, pad;
 };
 constexpr int kBatchGroups = 6;   // (branching factor 2 or 4) x (kernel)
+constexpr int kBatchLaunchGroups = kBatchGroups + 3;   // and one exact-sum group per kernel (root leaves)
+constexpr int kBatchMaxTileWaves = 2;   // tiles per batch workgroup
+// Wavefronts that share one 64-query tile in the coherent kernels (single-tree
+// and batched), each walking an equal share of the root slots.
+constexpr int kWaveParts = 2;
 hipError_t launch_batch_begin(BatchState* st, uint64_t seed, uint32_t batch, hipStream_t s);
 // One launch of a group: workgroup b (of `blocks`, each of `tile_waves` wavefronts) evaluates tiles
 // wg[b].y, wg[b].y + 1, ... of cloud items[wg[b].x]; `lds_bytes` of dynamic LDS per workgroup (not
@@ -236,6 +241,9 @@ hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int
                             size_t lds_bytes, const BatchState* st, int samples, int group, int rr_mode, float eps,
                             float alpha, hipStream_t s);
 void* batch_begin_kernel();
+hipError_t batch_static_lds(size_t* bytes);   // the batch kernels' own LDS per workgroup
+hipError_t launch_leaf_batch(int kernel, const BatchItem* items, const int2* wg, int blocks, int tile_waves, float eps,
+                             float alpha, hipStream_t s);
 
 // learned proposal (mlp.hip)
 constexpr int kMlpParams = 1608;
