@@ -509,30 +509,31 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     return acc;
 }
 
-// Sum over the 64 lanes of eight values per lane, in a fixed order: three
-// halving exchanges leave lane l with one partial sum of value l >> 3, three
-// more complete it; value c is then in lanes 8c .. 8c + 7.
+// Sum over the 64 lanes of eight values per lane, in a fixed order, on the
+// vector unit (no LDS): a swap between the wavefront's halves and one between
+// row pairs (gfx950 lane-swap instructions) each halve the values a lane
+// holds, a row rotation by 8 leaves lanes 8c .. 8c + 7 with value c, and a
+// segmented shift-add scan leaves its total in lane 8c + 7.
 __device__ __forceinline__ float wave_sum8(const float v[8])
 {
     const int l = threadIdx.x & 63;
-    const bool b5 = (l >> 5) & 1, b4 = (l >> 4) & 1, b3 = (l >> 3) & 1;
     float w4[4], w2[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float send = b5 ? v[i] : v[4 + i];
-        const float keep = b5 ? v[4 + i] : v[i];
-        w4[i] = keep + __shfl_xor(send, 32, 64);
+    for (int i = 0; i < 4; ++i) {   // lanes 0..31 keep values 0..3, lanes 32..63 values 4..7
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[4 + i]), false, false);
+        w4[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float send = b4 ? w4[i] : w4[2 + i];
-        const float keep = b4 ? w4[2 + i] : w4[i];
-        w2[i] = keep + __shfl_xor(send, 16, 64);
+    for (int i = 0; i < 2; ++i) {   // rows 0..3 keep values (0, 1), (2, 3), (4, 5), (6, 7)
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w4[i]), __float_as_uint(w4[2 + i]), false, false);
+        w2[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    float w = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8, 64);
-    w += __shfl_xor(w, 4, 64);
-    w += __shfl_xor(w, 2, 64);
-    w += __shfl_xor(w, 1, 64);
+    const bool b3 = (l >> 3) & 1;
+    const float keep = b3 ? w2[1] : w2[0], send = b3 ? w2[0] : w2[1];
+    float w = keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0x128, 0xF, 0xF, false));  // row_ror:8
+    w += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w), 0x111, 0xF, 0xF, true));   // row_shr:1
+    w += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w), 0x112, 0xF, 0xF, true));   // row_shr:2
+    w += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w), 0x114, 0xF, 0xF, true));   // row_shr:4
     return w;
 }
 
@@ -563,12 +564,12 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
     int level = 1;
     float diamT = tv.diam0 * 0.5f;
     bool act = valid;
+    uint64_t actm = __ballot(valid);   // lanes still walking, as a lane mask
     float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
     float tT = t_a, prr = 1.0f, psel = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    for (int k = 0;; ++k) {
-        if (__ballot(act) == 0ull) break;
+    for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
         if (nT == 1u) {
             if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
@@ -577,42 +578,44 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         float u;
         pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
         const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
-        float4 aggC;
+        float4 aggC, dpC = zero4;
         uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
-        float sumc = 0.0f, tC = 0.0f, qsel;
+        float qsel;
         uint32_t rleaf = 0u;
-        uint64_t nonempty_step = 0ull;
-        int csel_step = 0;
-        int32_t blk_step = 0;
+        uint32_t nonempty = 0u;   // slots with points (wavefront-uniform)
+        float4 g8[D3];            // the block's aggregates, kept for the swap
+        float r2[D3];             // this lane's squared distances to them, shared by score and term
         if (internal) {
             const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
             const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
             const float* __restrict__ bs = tv.bspr + (int64_t)blk * D3;
             const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
-            const uint32_t cl = ln < D3 ? bt[ln] : 0u;
+            // counts in lanes 0..7 (lanes 8..63 read the row's zero padding word)
+            const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
             uint32_t inc = cl;
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);
             const uint32_t excl = inc - cl;
-            const uint64_t im = __ballot(ln < D3 && (int)cl > tv.leaf_size && level + 1 < tv.max_level);
-            const uint64_t nonempty = __ballot(ln < D3 && cl != 0u);
+            const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
+            nonempty = (uint32_t)__ballot(cl != 0u);
             // this lane's scores from the block (one batch of scalar loads); the terms of the
             // swap wait until the roulette has kept some lane
-            float4 g8[D3];
             float s8[D3], pi[D3];
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
-                g8[c] = ba[c];
-                s8[c] = bs[c];
+                g8[c] = gld4(ba + c);
+                s8[c] = gld(bs + c);
             }
             float smax = 0.0f;
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
                 pi[c] = 0.0f;
-                if (!((nonempty >> c) & 1ull)) continue;
-                const float x = norm2(g8[c].x - qx, g8[c].y - qy, g8[c].z - qz) + s8[c];
+                r2[c] = 0.0f;
+                if (!((nonempty >> c) & 1u)) continue;
+                r2[c] = norm2(g8[c].x - qx, g8[c].y - qy, g8[c].z - qz);
+                const float x = r2[c] + s8[c];
                 const float rs = x > 0.0f ? __builtin_amdgcn_rsqf(x) : 0.0f;
                 pi[c] = g8[c].w * s8[c] * (rs * rs * rs);
                 smax = fmaxf(smax, pi[c]);
@@ -621,85 +624,76 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             float tot = 0.0f;
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
-                const float r = smax > 0.0f ? fmaxf(pi[c] * inv, 1.12535175e-7f) : 1.0f;
-                pi[c] = ((nonempty >> c) & 1ull) ? r : 0.0f;
+                if (!((nonempty >> c) & 1u)) continue;
+                pi[c] = smax > 0.0f ? fmaxf(pi[c] * inv, 1.12535175e-7f) : 1.0f;
                 tot += pi[c];
             }
             const float invt = valid ? frcp(tot) : 0.0f;   // lanes past the end of the query set add nothing
 #pragma unroll
             for (int c = 0; c < D3; ++c) pi[c] *= invt;
-            const float msum = wave_sum8(pi);                 // lane 8c holds the sum of pi_c
-            // q and the inverse-CDF selection, the same in every lane (uniform values)
-            const float u_sel = (float)(xsel >> 8) * 5.9604644775390625e-8f;
+            const float msum = wave_sum8(pi);                 // lane 8c + 7 holds the sum of pi_c
+            // q and the inverse-CDF selection across lanes 0..7, one slot each: lane c takes its
+            // slot's tile sum from lane 8c + 7 and forms q_c (zero for an empty slot); an
+            // inclusive scan gives the running totals, and the first lane whose total exceeds
+            // u is the selected slot (the last non-empty one if rounding left the total below u)
+            const float u_sel = unit24(xsel);
             const float fnT = frcp((float)nT);
-            float cum = 0.0f;
-            int csel = -1, last = 0;
-            float qL = 0.0f;
-            qsel = 0.0f;
-#pragma unroll
-            for (int c = 0; c < D3; ++c) {
-                if (!((nonempty >> c) & 1ull)) continue;
-                const float mc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(msum), 8 * c));
-                const uint32_t nc = (uint32_t)__builtin_amdgcn_readlane((int)cl, c);
-                const float qc = (1.0f - kLam) * (mc * inv_valid) + kLam * ((float)nc * fnT);
-                cum += qc;
-                last = c;
-                qL = qc;
-                if (csel < 0 && u_sel < cum) {
-                    csel = c;
-                    qsel = qc;
-                }
-            }
-            if (csel < 0) {   // rounding left the total just below u: the last non-empty slot
-                csel = last;
-                qsel = qL;
-            }
-            csel = __builtin_amdgcn_readfirstlane(csel);
-            qsel = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(qsel)));
+            const float mc = __int_as_float(__builtin_amdgcn_ds_bpermute(((8 * ln + 7) & 63) << 2, __float_as_int(msum)));
+            const float qc = ln < D3 ? (1.0f - kLam) * (mc * inv_valid) + kLam * ((float)cl * fnT) : 0.0f;
+            float cum = qc;
+            cum += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cum), 0x111, 0xF, 0xF, true));   // row_shr:1
+            cum += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cum), 0x112, 0xF, 0xF, true));   // row_shr:2
+            cum += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cum), 0x114, 0xF, 0xF, true));   // row_shr:4
+            const uint64_t hit = __ballot(u_sel < cum) & ((1ull << D3) - 1ull);
+            const int csel = hit ? __ffsll((unsigned long long)hit) - 1 : 31 - __builtin_clz(nonempty);
+            qsel = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc), csel));
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
             nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
-            aggC = ba[csel];
-            nonempty_step = nonempty;
-            csel_step = csel;
-            blk_step = blk;
+            aggC = gld4(ba + csel);
+            if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
             beginC = beginT + preC;
-            blkC = (int32_t)bt[D3] + __popcll(im & ((1ull << csel) - 1ull));
+            blkC = (int32_t)gld(bt + D3) + __popcll(im & ((1ull << csel) - 1ull));
         } else {
             rleaf = __umulhi(xsel, nT);
-            aggC = tv.pts[beginT + rleaf];
+            aggC = gld4(tv.pts + beginT + rleaf);
+            if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + rleaf);
             beginC = beginT + rleaf;
             qsel = frcp((float)nT);
         }
+        // roulette (Eq. (5)); its offset and squared distance also give the selected child's
+        // own term, bit for bit the value the swap's sum takes for it
         float p, dC = 0.0f;
+        const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+        const float r2C = norm2(cx, cy, cz);
         if (rr_mode == 0) {
-            dC = fsqrt(norm2(aggC.x - qx, aggC.y - qy, aggC.z - qz));
-            p = fminf(1.0f, fmaxf(diamT, dT) * frcp(2.0f * dC));
+            dC = fsqrt(r2C);
+            p = fminf(1.0f, vmax(diamT, dT) * frcp(2.0f * dC));
         } else {
             p = rr_mode == 1 ? 1.0f : 0.5f;
         }
-
-        const bool cont = act && (u < p);
+        const bool lt = u < p;
+        const uint64_t contm = __ballot(lt) & actm;
+        const bool cont = act && lt;
         if (act && !cont) {
             flag = 0;
             end_b = (int32_t)beginT;
             end_l = level;
         }
-        if (__ballot(cont) == 0ull) break;
+        if (contm == 0ull) break;
+        float sumc = 0.0f;
+        const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
         if (internal) {   // contribution swap over the non-empty children, Eq. (6)
-            const float4* __restrict__ ba = tv.bagg + (int64_t)blk_step * D3;
-            const float4* __restrict__ bd = tv.bdip + (int64_t)blk_step * D3;
+            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
-                if (!((nonempty_step >> c) & 1ull)) continue;
-                const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
-                const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
-                sumc += v;
-                if (c == csel_step) tC = v;
+                if (!((nonempty >> c) & 1u)) continue;
+                const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                sumc += term_r2<K>(g8[c], gd, g8[c].x - qx, g8[c].y - qy, g8[c].z - qz, r2[c], kp, r0);
             }
         } else {   // leaf: its points are the virtual children
             for (uint32_t i = 0; i < nT; ++i) {
-                const float4 g = tv.pts[beginT + i];
-                const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                const float4 g = gld4(tv.pts + beginT + i);
+                const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
                 sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
             }
         }
@@ -719,6 +713,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             break;
         }
         act = cont;
+        actm = contm;
         dT = dC;
         nT = nC;
         beginT = beginC;
@@ -850,11 +845,19 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
 
 // the coherent walk with the tile-shared score proposal (d = 2)
 template <int K, bool TRACE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave_tile(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    sbh_wave_tile<2, K, TRACE, true>(tv, queries, nq, a, out, wave);
+    constexpr int P = kWaveParts, TPB = 4 / P;   // as k_sbh_wave
+    __shared__ float part_f[4][64];
+    __shared__ uint32_t done[TPB];
+    if constexpr (P > 1) {
+        if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
+    sbh_wave_tile<2, K, TRACE, true, P>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // ---------------------------------------------------------------------------
@@ -1070,17 +1073,16 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
     SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
               e.eps * e.eps, e.alpha, e.paths};
     if (e.group % 64 == 0) {
-        const unsigned blocks = (unsigned)((nq + 255) / 256);
+        const int64_t tiles = (nq + 63) / 64;
+        const unsigned wblocks = (unsigned)((tiles + (4 / kWaveParts) - 1) / (4 / kWaveParts));
         if (e.tile_score) {
             if constexpr (D == 2) {
-                if (e.paths) k_sbh_wave_tile<K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
-                else k_sbh_wave_tile<K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+                if (e.paths) k_sbh_wave_tile<K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                else k_sbh_wave_tile<K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
         }
-        const int64_t tiles = (nq + 63) / 64;
-        const unsigned wblocks = (unsigned)((tiles + (4 / kWaveParts) - 1) / (4 / kWaveParts));
         if (e.paths) k_sbh_wave<D, K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
         else k_sbh_wave<D, K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
         return hipGetLastError();
