@@ -282,7 +282,9 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 // once for all its lanes, and only the Russian-roulette test (p depends on q)
 // retires lanes individually.  This is the shared-seed design of the paper's
 // implementation section on 64-wide wavefronts.  Per query the subdomain
-// totals CV_a + F_a / S are added in slot order.
+// totals CV_a + F_a / S are added in slot order within each part of the
+// slots that one wavefront walks (kWaveParts parts), then the parts' sums in
+// part order.
 // ---------------------------------------------------------------------------
 // The uniform variate of a 32-bit random word: its top 24 bits times 2^-24
 // (exactly representable, in [0, 1)).
