@@ -274,6 +274,250 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Per-lane estimator with lane refill.  Each lane walks its own path, so the
+// paths of a wavefront end at different steps; instead of idling, a lane
+// whose path has ended takes the next path of the wavefront's pool
+// (kPoolPaths paths: Q queries x d^3 subdomains x S samples, handed out in
+// lane order).  Every path's sum is stored at its own place in LDS, and once
+// the pool is drained each query adds CV_a + F_a / S over its subdomains in
+// slot order, so the result does not depend on which lane walked what.  The
+// step is the one of sample_path, operation for operation.
+// ---------------------------------------------------------------------------
+constexpr int kPoolPaths = 256;
+
+// The uniform variate of a 32-bit random word: its top 24 bits times 2^-24
+// (exactly representable, in [0, 1)).
+__device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
+
+template <int D, int K, bool TRACE>
+__global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                  SbhArgs a, float* __restrict__ out)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kInvD = 1.0f / (float)D;
+    __shared__ float res[4][kPoolPaths];   // per path: its sum F (before the division by S)
+    __shared__ float cvs[4][kPoolPaths];   // per (query, subdomain): the control variate CV_a
+    __shared__ uint32_t tab[4][D3][3];     // per subdomain: point count, first point, block id
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int S = a.samples;
+    const int Q = kPoolPaths / (D3 * S);   // queries per wavefront (the launcher keeps D^3 S <= kPoolPaths)
+    const int NP = Q * D3 * S;
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + wv) * Q;
+    if (q0 >= nq) return;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) smooth_setup(tv, kp.wscale, logwbar);
+    {   // the root block's subdomains, once per wavefront
+        const uint32_t* __restrict__ rt = tv.btopo;
+        const int32_t base = (int32_t)gld(rt + D3);
+        uint32_t begin = 0u;
+        int32_t nint = 0;
+        for (int c = 0; c < D3; ++c) {
+            const uint32_t n = gld(rt + c);
+            if (lane == 0) {
+                tab[wv][c][0] = n;
+                tab[wv][c][1] = begin;
+                tab[wv][c][2] = (uint32_t)(base + nint);
+            }
+            begin += n;
+            nint += ((int)n > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // lane state: the path (p < 0: none left) and its walk
+    int p = lane, slot = 0, smp = 0, k = 0, level = 1, steps = 0, flag = 0;
+    int64_t j = 0;
+    float qx = 0.f, qy = 0.f, qz = 0.f, r0 = 0.f;
+    uint32_t nT = 0u, beginT = 0u, ctr0 = 0u, ctr1 = 0u;
+    int32_t blk = 0, end_b = 0, end_l = 1;
+    float diamT = 0.f, dT = 0.f, tT = 0.f, prr = 1.f, acc = 0.f, fna = 0.f;
+    u32x4 rnd = {0u, 0u, 0u, 0u};
+    bool open = false;   // a path with points is being walked
+    auto start = [&](int np) {
+        p = np;
+        open = false;
+        if (p >= NP) {
+            p = -1;
+            return;
+        }
+        const int qi = p / (D3 * S), rem = p % (D3 * S);
+        slot = rem / S;
+        smp = rem % S;
+        j = q0 + qi;
+        acc = 0.0f;
+        if (j >= nq) return;   // past the end of the query set: an empty path
+        qx = gld(queries + 3 * j);
+        qy = gld(queries + 3 * j + 1);
+        qz = gld(queries + 3 * j + 2);
+        if constexpr (K == SBH_SMOOTHDIST) r0 = cube_distance(tv, qx, qy, qz);
+        const uint32_t n_a = tab[wv][slot][0];
+        if (n_a == 0u) {   // empty subdomain
+            if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(-1, 0, 0, 0);
+            return;
+        }
+        const float4 agg_a = gld4(tv.bagg + slot);
+        const float4 dip_a = (K == SBH_WINDING) ? gld4(tv.bdip + slot) : zero4;
+        const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);   // control variate CV_a
+        if (smp == 0) cvs[wv][p / S] = cv;
+        nT = n_a;
+        beginT = tab[wv][slot][1];
+        blk = (int32_t)tab[wv][slot][2];
+        level = 1;
+        diamT = tv.diam0 * kInvD;
+        dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
+        tT = cv;
+        prr = 1.0f;
+        fna = (float)n_a;
+        steps = 0;
+        flag = 0;
+        k = 0;
+        ctr0 = (uint32_t)(a.group == 1 ? j : j / a.group);
+        ctr1 = (uint32_t)(slot * S + smp);
+        end_b = (int32_t)beginT;
+        end_l = level;
+        open = true;
+    };
+    start(lane);
+    int next = 64;   // the next path of the pool to hand out
+    while (__ballot(p >= 0) != 0ull) {
+        bool done = p >= 0 && !open;   // an empty path ends at once
+        if (open) {
+            end_b = (int32_t)beginT;
+            end_l = level;
+            if (nT == 1u) {
+                flag = 1;
+                done = true;
+            } else {
+                if ((k & 1) == 0) rnd = philox4x32_10(ctr0, ctr1, (uint32_t)(k >> 1), a.batch, a.key0, a.key1);
+                const uint32_t xsel = (k & 1) ? rnd.z : rnd.x;
+                const uint32_t xrr = (k & 1) ? rnd.w : rnd.y;
+                const uint32_t r = __umulhi(xsel, nT);
+                const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
+                const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+                const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+                const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+                float4 aggC, dpC = zero4;
+                uint32_t nC = 1u, beginC;
+                int32_t blkC = 0;
+                if (internal) {
+                    // child selection from the point counts alone
+                    uint32_t pre = 0u, preC = 0u;
+                    int32_t nint = 0, nintC = 0;
+                    int csel = 0;
+#pragma unroll
+                    for (int c = 0; c < D3; ++c) {
+                        const uint32_t cnt = gld(bt + c);
+                        const bool hit = (r - pre) < cnt;
+                        csel = hit ? c : csel;
+                        preC = hit ? pre : preC;
+                        nintC = hit ? nint : nintC;
+                        nC = hit ? cnt : nC;
+                        nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                        pre += cnt;
+                    }
+                    aggC = gld4(ba + csel);
+                    if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
+                    beginC = beginT + preC;
+                    blkC = (int32_t)gld(bt + D3) + nintC;
+                } else {
+                    aggC = gld4(tv.pts + beginT + r);
+                    if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + r);
+                    beginC = beginT + r;
+                }
+                // roulette first (Eq. (5)); its offset and squared distance also give the
+                // selected child's own term, bit for bit the value the swap's sum takes for it
+                float pr;
+                float dC = 0.0f;
+                const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+                const float r2C = norm2(cx, cy, cz);
+                if (a.rr_mode == 0) {
+                    dC = fsqrt(r2C);
+                    pr = fminf(1.0f, fmaxf(diamT, dT) * frcp((float)D * dC));
+                } else {
+                    pr = a.rr_mode == 1 ? 1.0f : 0.5f;
+                }
+                if (unit24(xrr) >= pr) {
+                    flag = 0;
+                    done = true;
+                } else {
+                    // contribution swap, Eq. (6)
+                    float sumc = 0.0f;
+                    const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
+                    if (internal) {
+#pragma unroll
+                        for (int c = 0; c < D3; ++c) {
+                            const uint32_t cnt = gld(bt + c);
+                            const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                            const float v = term<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0);
+                            sumc += cnt ? v : 0.0f;
+                        }
+                    } else {
+                        for (uint32_t i = 0; i < nT; ++i) {
+                            const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
+                            sumc += term<K>(gld4(tv.pts + beginT + i), gd, qx, qy, qz, kp, r0);
+                        }
+                    }
+                    prr *= pr;
+                    acc += (sumc - tT) * (fna * frcp((float)nT * prr));
+                    ++steps;
+                    if (!internal) {
+                        end_b = (int32_t)beginC;
+                        end_l = level + 1;
+                        flag = 2;
+                        done = true;
+                    } else {
+                        dT = dC;
+                        tT = tC;
+                        nT = nC;
+                        beginT = beginC;
+                        blk = blkC;
+                        ++level;
+                        diamT *= kInvD;
+                        ++k;
+                    }
+                }
+            }
+        }
+        if (done && open) {
+            if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(end_b, end_l, steps, flag);
+        }
+        if (done) res[wv][p] = acc;
+        // hand the next paths of the pool to the lanes that finished, in lane order
+        const uint64_t fin = __ballot(done);
+        if (fin != 0ull) {
+            if (done) start(next + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fin >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fin, 0u)));
+            next += __popcll(fin);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // per query: the subdomain totals CV_a + F_a / S in slot order
+    const int64_t jq = q0 + lane;
+    if (lane < Q && jq < nq) {
+        float val = 0.0f;
+        for (int c = 0; c < D3; ++c) {
+            if (tab[wv][c][0] == 0u) continue;
+            float fa = 0.0f;
+            for (int t = 0; t < S; ++t) fa += res[wv][(lane * D3 + c) * S + t];
+            val += cvs[wv][lane * D3 + c] + fa / (float)S;
+        }
+        if constexpr (K == SBH_SMOOTHDIST) {
+            const float rq = cube_distance(tv, gld(queries + 3 * jq), gld(queries + 3 * jq + 1), gld(queries + 3 * jq + 2));
+            gst(out + jq, rq - (logf(val) + logwbar) / a.alpha);
+        } else {
+            gst(out + jq, val);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Coherent estimator: one lane per query, one random stream per wavefront.
 // When G is a multiple of 64 the 64 queries of a wavefront share their
 // Philox stream, so under the uniform proposal the selected child at every
@@ -286,10 +530,6 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 // slots that one wavefront walks (kWaveParts parts), then the parts' sums in
 // part order.
 // ---------------------------------------------------------------------------
-// The uniform variate of a 32-bit random word: its top 24 bits times 2^-24
-// (exactly representable, in [0, 1)).
-__device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
-
 // max(a, b) of two non-negative finite floats as one instruction (fmaxf quiets
 // NaN inputs first, two more instructions that the walk does not need)
 __device__ __forceinline__ float vmax(float a, float b)
@@ -1087,6 +1327,15 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
         }
         if (e.paths) k_sbh_wave<D, K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
         else k_sbh_wave<D, K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+        return hipGetLastError();
+    }
+    if ((int64_t)D * D * D * e.samples <= kPoolPaths) {
+        // per-lane walks with lane refill: Q queries per wavefront, four wavefronts per block
+        const int64_t qpw = kPoolPaths / (D * D * D * e.samples);
+        const int64_t waves = (nq + qpw - 1) / qpw;
+        const unsigned blocks = (unsigned)((waves + 3) / 4);
+        if (e.paths) k_sbh_pool<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        else k_sbh_pool<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
         return hipGetLastError();
     }
     const int64_t waves = (nq + QPW - 1) / QPW;
