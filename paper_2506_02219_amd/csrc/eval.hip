@@ -300,12 +300,20 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
     __shared__ float res[4][kPoolPaths];   // per path: its sum F (before the division by S)
     __shared__ float cvs[4][kPoolPaths];   // per (query, subdomain): the control variate CV_a
     __shared__ uint32_t tab[4][D3][3];     // per subdomain: point count, first point, block id
+    __shared__ float4 root_agg[D3];        // the subdomains' aggregates (and dipoles), for every path start
+    __shared__ float4 root_dip[K == SBH_WINDING ? D3 : 1];
+    __shared__ float qpos[4][kPoolPaths / 8 * 3];   // the wavefront's query positions (Q <= kPoolPaths / d^3)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int S = a.samples;
     const int Q = kPoolPaths / (D3 * S);   // queries per wavefront (the launcher keeps D^3 S <= kPoolPaths)
     const int NP = Q * D3 * S;
     const int64_t q0 = ((int64_t)blockIdx.x * 4 + wv) * Q;
+    for (int c = threadIdx.x; c < D3; c += 256) {   // before the block's waves part: all reach the barrier
+        root_agg[c] = gld4(tv.bagg + c);
+        if constexpr (K == SBH_WINDING) root_dip[c] = gld4(tv.bdip + c);
+    }
+    __syncthreads();
     if (q0 >= nq) return;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     KParams kp{a.eps2, a.alpha, 1.0f};
@@ -326,6 +334,8 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
             begin += n;
             nint += ((int)n > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
         }
+        for (int i = lane; i < 3 * Q; i += 64)   // the wavefront's queries (past the end: zero)
+            qpos[wv][i] = q0 * 3 + i < 3 * nq ? gld(queries + 3 * q0 + i) : 0.0f;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -352,17 +362,17 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
         j = q0 + qi;
         acc = 0.0f;
         if (j >= nq) return;   // past the end of the query set: an empty path
-        qx = gld(queries + 3 * j);
-        qy = gld(queries + 3 * j + 1);
-        qz = gld(queries + 3 * j + 2);
+        qx = qpos[wv][3 * qi];
+        qy = qpos[wv][3 * qi + 1];
+        qz = qpos[wv][3 * qi + 2];
         if constexpr (K == SBH_SMOOTHDIST) r0 = cube_distance(tv, qx, qy, qz);
         const uint32_t n_a = tab[wv][slot][0];
         if (n_a == 0u) {   // empty subdomain
             if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(-1, 0, 0, 0);
             return;
         }
-        const float4 agg_a = gld4(tv.bagg + slot);
-        const float4 dip_a = (K == SBH_WINDING) ? gld4(tv.bdip + slot) : zero4;
+        const float4 agg_a = root_agg[slot];
+        const float4 dip_a = (K == SBH_WINDING) ? root_dip[slot] : zero4;
         const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);   // control variate CV_a
         if (smp == 0) cvs[wv][p / S] = cv;
         nT = n_a;

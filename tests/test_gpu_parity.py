@@ -74,6 +74,8 @@ def test_tree_small_and_ragged(m):
 # ----------------------------------------------------------------------------- stochastic estimator
 @pytest.mark.parametrize("d,S,G,rr", [(2, 1, 1, 0), (2, 4, 1, 0), (4, 1, 1, 0), (4, 2, 1, 0),
                                       (2, 2, 1, 1), (2, 2, 1, 2), (2, 1, 8, 0),
+                                      # d^3 S above the per-wavefront path pool: one path per lane, no refill
+                                      (4, 8, 1, 0), (2, 40, 1, 0),
                                       # G a multiple of 64: one shared stream per wavefront (coherent kernel)
                                       (2, 1, 64, 0), (2, 3, 128, 0), (4, 1, 64, 0), (2, 2, 64, 2)])
 def test_sbh_parity_c1(d, S, G, rr):
