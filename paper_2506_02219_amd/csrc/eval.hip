@@ -872,12 +872,16 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
                 pi[c] = g8[c].w * s8[c] * (rs * rs * rs);
                 smax = fmaxf(smax, pi[c]);
             }
-            const float inv = smax > 0.0f ? frcp(smax) : 0.0f;
+            // every slot takes the same instructions, with no branch: an empty slot's score is 0
+            // and its floor 0; a lane whose scores are all 0 gets 1 for every non-empty slot
+            constexpr float kFloor = 1.12535175e-7f;   // e^-16
+            const bool pos = smax > 0.0f;
+            const float inv = pos ? frcp(smax) : 0.0f;
+            const float fl = pos ? kFloor : 1.0f;
             float tot = 0.0f;
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
-                if (!((nonempty >> c) & 1u)) continue;
-                pi[c] = smax > 0.0f ? fmaxf(pi[c] * inv, 1.12535175e-7f) : 1.0f;
+                pi[c] = fmaxf(pi[c] * inv, ((nonempty >> c) & 1u) ? fl : 0.0f);
                 tot += pi[c];
             }
             const float invt = valid ? frcp(tot) : 0.0f;   // lanes past the end of the query set add nothing
