@@ -76,6 +76,9 @@ def test_tree_small_and_ragged(m):
                                       (2, 2, 1, 1), (2, 2, 1, 2), (2, 1, 8, 0),
                                       # d^3 S above the per-wavefront path pool: one path per lane, no refill
                                       (4, 8, 1, 0), (2, 40, 1, 0),
+                                      # the pool at its limit (one query per wavefront); a group that is
+                                      # not a multiple of 64
+                                      (2, 32, 1, 0), (2, 1, 100, 0),
                                       # G a multiple of 64: one shared stream per wavefront (coherent kernel)
                                       (2, 1, 64, 0), (2, 3, 128, 0), (4, 1, 64, 0), (2, 2, 64, 2)])
 def test_sbh_parity_c1(d, S, G, rr):
