@@ -807,6 +807,310 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
     }
 }
 
+// The same estimator with lane refill: a wavefront owns a pool of kLearnPool
+// paths (Q queries x 8 subdomains x S samples); a lane whose path has ended
+// takes the next one, handed out in lane order, so lanes do not idle while
+// the wavefront's longest path finishes.  The network still runs once per
+// step for all 64 lanes.  Every path's sum is stored at its own place in LDS,
+// and each query adds CV_a + F_a / S over its subdomains in slot order at the
+// end.  The step is the one above, operation for operation.
+constexpr int kLearnPool = 256;
+
+template <int K, bool TRACE, bool NET>
+__global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                          LearnArgs a, float* __restrict__ out)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    constexpr int TS = topo_stride(D3);
+    __shared__ float res[4][kLearnPool];
+    __shared__ float cvs[4][kLearnPool];
+    __shared__ uint32_t tab[4][D3][3];
+    __shared__ float4 root_agg[D3];
+    __shared__ float4 root_dip[K == SBH_WINDING ? D3 : 1];
+    __shared__ float qpos[4][kLearnPool / D3 * 3];
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int S = a.samples;
+    const int Q = kLearnPool / (D3 * S);   // the launcher keeps 8 S <= kLearnPool
+    const int NP = Q * D3 * S;
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + wv) * Q;
+    for (int c = threadIdx.x; c < D3; c += 256) {   // before the block's waves part: all reach the barrier
+        root_agg[c] = tv.bagg[c];
+        if constexpr (K == SBH_WINDING) root_dip[c] = tv.bdip[c];
+    }
+    __syncthreads();
+    if (q0 >= nq) return;
+    MlpRegs R;
+    bool net = NET;
+    if constexpr (NET) {
+        // parameters that are not all finite are ignored (the zero network: the score proposal)
+        bool bad = false;
+        for (int i = lane; i < kMlpParams; i += 64) bad |= !__builtin_isfinite(a.prm[i]);
+        net = __ballot(bad) == 0ull;
+        mlp_load_regs(R, a.prm, lane);
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        const float wbar = tv.nagg[0].w / (float)tv.n_points;
+        kp.wscale = 1.0f / wbar;
+        logwbar = logf(wbar);
+    }
+    {   // the root block's subdomains and the wavefront's queries, once per wavefront
+        const uint32_t* __restrict__ rt = tv.btopo;
+        const int32_t base = (int32_t)rt[D3];
+        uint32_t begin = 0u;
+        int32_t nint = 0;
+        for (int c = 0; c < D3; ++c) {
+            const uint32_t n = rt[c];
+            if (lane == 0) {
+                tab[wv][c][0] = n;
+                tab[wv][c][1] = begin;
+                tab[wv][c][2] = (uint32_t)(base + nint);
+            }
+            begin += n;
+            nint += ((int)n > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+        }
+        for (int i = lane; i < 3 * Q; i += 64) qpos[wv][i] = q0 * 3 + i < 3 * nq ? queries[3 * q0 + i] : 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    int p = lane, slot = 0, smp = 0, k = 0, level = 1, steps = 0, flag = 0;
+    int64_t j = 0;
+    float qx = 0.f, qy = 0.f, qz = 0.f, r0 = 0.f;
+    uint32_t nT = 0u, beginT = 0u, stream = 0u, ctr1 = 0u;
+    int32_t blk = 0, end_b = 0, end_l = 1;
+    float diamT = 0.f, dT = 0.f, tT = 0.f, prr = 1.f, psel = 1.f, acc = 0.f;
+    u32x4 rnd = {0u, 0u, 0u, 0u};
+    bool open = false;   // a path with points is being walked
+    auto start = [&](int np) {
+        p = np;
+        open = false;
+        if (p >= NP) {
+            p = -1;
+            return;
+        }
+        const int qi = p / (D3 * S), rem = p % (D3 * S);
+        slot = rem / S;
+        smp = rem % S;
+        j = q0 + qi;
+        acc = 0.0f;
+        if (j >= nq) return;   // past the end of the query set: an empty path
+        qx = qpos[wv][3 * qi];
+        qy = qpos[wv][3 * qi + 1];
+        qz = qpos[wv][3 * qi + 2];
+        if constexpr (K == SBH_SMOOTHDIST) r0 = cube_distance(tv, qx, qy, qz);
+        const uint32_t n_a = tab[wv][slot][0];
+        if (n_a == 0u) {   // empty subdomain
+            if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(-1, 0, 0, 0);
+            return;
+        }
+        const float4 agg_a = root_agg[slot];
+        const float cv = term<K>(agg_a, (K == SBH_WINDING) ? root_dip[slot] : zero4, qx, qy, qz, kp, r0);
+        if (smp == 0) cvs[wv][p / S] = cv;
+        nT = n_a;
+        beginT = tab[wv][slot][1];
+        blk = (int32_t)tab[wv][slot][2];
+        level = 1;
+        diamT = tv.diam0 * 0.5f;
+        dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
+        tT = cv;
+        prr = 1.0f;
+        psel = 1.0f;
+        steps = 0;
+        flag = 0;
+        k = 0;
+        stream = (uint32_t)(a.group == 1 ? j : j / a.group);
+        ctr1 = (uint32_t)(slot * S + smp);
+        end_b = (int32_t)beginT;
+        end_l = level;
+        open = true;
+    };
+    start(lane);
+    int next = 64;   // the next path of the pool to hand out
+    while (__ballot(p >= 0) != 0ull) {
+        bool done = p >= 0 && !open;   // an empty path ends at once
+        bool internal = false;
+        uint32_t xsel = 0u, xrr = 0u;
+        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
+        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+        uint32_t cnt[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        float tv8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float sumc = 0.0f;
+        if (open) {
+            if (nT == 1u) {
+                flag = 1;
+                end_b = (int32_t)beginT;
+                end_l = level;
+                done = true;
+            } else {
+                if ((k & 1) == 0) rnd = philox4x32_10(stream, ctr1, (uint32_t)(k >> 1), a.batch, a.key0, a.key1);
+                xsel = (k & 1) ? rnd.z : rnd.x;
+                xrr = (k & 1) ? rnd.w : rnd.y;
+                internal = (int)nT > tv.leaf_size && level < tv.max_level;
+                if (internal) {
+                    // the child block: terms for the swap, scores for the proposal
+                    const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+#pragma unroll
+                    for (int c = 0; c < D3; ++c) {
+                        cnt[c] = bt[c];
+                        const float4 gd = (K == SBH_WINDING) ? bd[c] : zero4;
+                        const float v = term<K>(ba[c], gd, qx, qy, qz, kp, r0);
+                        tv8[c] = cnt[c] ? v : 0.0f;
+                        sumc += tv8[c];
+                    }
+                    if constexpr (NET) score_features(ba, tv.bspr + (int64_t)blk * D3, cnt, qx, qy, qz, f);
+                }
+            }
+        }
+        float z[8];
+        if constexpr (NET) {
+            if (net) {
+                if (__ballot(internal) != 0ull) mlp_forward_wave(R, f, z, lane);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) z[c] = 16.0f * f[c];
+            }
+        }
+        if (open && !done) {
+            float4 aggC;
+            uint32_t nC = 1u, beginC;
+            int32_t blkC = 0;
+            int csel = 0;
+            float qsel, tC = 0.0f;
+            if (internal) {
+                float qv[8];
+                if constexpr (NET) learned_probs(z, cnt, nT, qv);
+                else score_probs(ba, tv.bspr + (int64_t)blk * D3, cnt, nT, qx, qy, qz, qv);
+                const float u_sel = (float)(xsel >> 8) * 5.9604644775390625e-8f;
+                // first slot whose running sum exceeds u; rounding can leave the
+                // total just below u, then the last non-empty slot is taken
+                float cum = 0.0f;
+                uint32_t pre = 0u, preC = 0u, preL = 0u, nL = 0u;
+                int32_t ni = 0, niC = 0, niL = 0;
+                int last = 0;
+                float qL = 0.0f, tL = 0.0f;
+                bool found = false;
+                nC = 0u;
+                qsel = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const bool ne = cnt[c] != 0u;
+                    last = ne ? c : last;
+                    preL = ne ? pre : preL;
+                    niL = ne ? ni : niL;
+                    nL = ne ? cnt[c] : nL;
+                    qL = ne ? qv[c] : qL;
+                    tL = ne ? tv8[c] : tL;
+                    cum += qv[c];
+                    const bool hit = !found && ne && u_sel < cum;
+                    csel = hit ? c : csel;
+                    preC = hit ? pre : preC;
+                    niC = hit ? ni : niC;
+                    nC = hit ? cnt[c] : nC;
+                    qsel = hit ? qv[c] : qsel;
+                    tC = hit ? tv8[c] : tC;
+                    found = found || hit;
+                    ni += ((int)cnt[c] > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                    pre += cnt[c];
+                }
+                if (!found) {
+                    csel = last;
+                    preC = preL;
+                    niC = niL;
+                    nC = nL;
+                    qsel = qL;
+                    tC = tL;
+                }
+                aggC = ba[csel];
+                beginC = beginT + preC;
+                blkC = (int32_t)bt[D3] + niC;
+            } else {
+                const uint32_t r = __umulhi(xsel, nT);
+                aggC = tv.pts[beginT + r];
+                beginC = beginT + r;
+                qsel = 1.0f / (float)nT;
+            }
+            float pr, dC = 0.0f;
+            if (a.rr_mode == 0) {
+                const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+                dC = fsqrt(norm2(cx, cy, cz));
+                pr = fminf(1.0f, fmaxf(diamT, dT) * frcp(2.0f * dC));
+            } else {
+                pr = a.rr_mode == 1 ? 1.0f : 0.5f;
+            }
+            const float u = (float)(xrr >> 8) * 5.9604644775390625e-8f;
+            if (u >= pr) {
+                flag = 0;
+                end_b = (int32_t)beginT;
+                end_l = level;
+                done = true;
+            } else {
+                if (!internal) {   // leaf: its points are the virtual children
+                    for (uint32_t i = 0; i < nT; ++i) {
+                        const float4 g = tv.pts[beginT + i];
+                        const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
+                        sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+                    }
+                }
+                prr *= pr;
+                acc += (sumc - tT) * frcp(psel * prr);
+                psel *= qsel;
+                ++steps;
+                if (!internal) {
+                    flag = 2;
+                    end_b = (int32_t)beginC;
+                    end_l = level + 1;
+                    done = true;
+                } else {
+                    dT = dC;
+                    tT = tC;
+                    nT = nC;
+                    beginT = beginC;
+                    blk = blkC;
+                    ++level;
+                    diamT *= 0.5f;
+                    ++k;
+                }
+            }
+        }
+        if (done && open) {
+            if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(end_b, end_l, steps, flag);
+        }
+        if (done) res[wv][p] = acc;
+        // hand the next paths of the pool to the lanes that finished, in lane order
+        const uint64_t fin = __ballot(done);
+        if (fin != 0ull) {
+            if (done) start(next + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fin >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fin, 0u)));
+            next += __popcll(fin);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // per query: the subdomain totals CV_a + F_a / S in slot order
+    const int64_t jq = q0 + lane;
+    if (lane < Q && jq < nq) {
+        float val = 0.0f;
+        for (int c = 0; c < D3; ++c) {
+            if (tab[wv][c][0] == 0u) continue;
+            float fa = 0.0f;
+            for (int t = 0; t < S; ++t) fa += res[wv][(lane * D3 + c) * S + t];
+            val += cvs[wv][lane * D3 + c] + fa / (float)S;
+        }
+        if constexpr (K == SBH_SMOOTHDIST) {
+            const float rq = cube_distance(tv, queries[3 * jq], queries[3 * jq + 1], queries[3 * jq + 2]);
+            out[jq] = rq - (logf(val) + logwbar) / a.alpha;
+        } else {
+            out[jq] = val;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -863,12 +1167,20 @@ hipError_t launch_sbh_learned(const sbh_tree_impl* t, const float* queries, int6
     const TreeView tv = make_view(t);
     LearnArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
                 e.eps * e.eps, e.alpha, e.paths, prm};
-    const int64_t waves = (nq + 7) / 8;
+    // lane refill from a pool of paths per wavefront while 8 S <= kLearnPool (one path per lane beyond)
+    const bool pool = 8 * (int64_t)e.samples <= kLearnPool;
+    const int64_t qpw = pool ? kLearnPool / (8 * e.samples) : 8;
+    const int64_t waves = (nq + qpw - 1) / qpw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-#define SBH_LAUNCH_L(KK, NN)                                                                     \
-    do {                                                                                         \
-        if (e.paths) k_sbh_learned<KK, true, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);  \
-        else k_sbh_learned<KK, false, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);         \
+#define SBH_LAUNCH_L(KK, NN)                                                                               \
+    do {                                                                                                   \
+        if (pool) {                                                                                        \
+            if (e.paths) k_sbh_learned_pool<KK, true, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);   \
+            else k_sbh_learned_pool<KK, false, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);          \
+        } else {                                                                                           \
+            if (e.paths) k_sbh_learned<KK, true, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);        \
+            else k_sbh_learned<KK, false, NN><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);               \
+        }                                                                                                  \
     } while (0)
 #define SBH_LAUNCH_K(NN)                                        \
     do {                                                        \
