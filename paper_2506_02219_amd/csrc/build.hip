@@ -551,23 +551,37 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
 // ---------------------------------------------------------------------------
 namespace {
 
+// Temporaries of one build: a bump allocator over a few large chunks.  A
+// build takes some two hundred temporaries, and one hipMalloc / hipFree pair
+// each (hipFree waits for the device) cost several times the build's kernels.
 struct DevPool {
-    std::vector<void*> ptrs;
+    static constexpr size_t kChunk = (size_t)64 << 20;
+    std::vector<void*> chunks;
+    char* cur = nullptr;
+    size_t left = 0;
     hipError_t err = hipSuccess;
     template <class T>
     T* alloc(int64_t count)
     {
         if (err != hipSuccess) return nullptr;
-        void* p = nullptr;
-        const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-        err = hipMalloc(&p, bytes);
-        if (err != hipSuccess) return nullptr;
-        ptrs.push_back(p);
-        return (T*)p;
+        const size_t bytes = (((size_t)(count > 0 ? count : 1) * sizeof(T)) + 255) & ~(size_t)255;
+        if (bytes > left) {
+            void* p = nullptr;
+            const size_t sz = bytes > kChunk ? bytes : kChunk;
+            err = hipMalloc(&p, sz);
+            if (err != hipSuccess) return nullptr;
+            chunks.push_back(p);
+            cur = (char*)p;
+            left = sz;
+        }
+        T* r = (T*)cur;
+        cur += bytes;
+        left -= bytes;
+        return r;
     }
     ~DevPool()
     {
-        for (void* p : ptrs)
+        for (void* p : chunks)
             if (p) (void)hipFree(p);
     }
 };
