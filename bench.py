@@ -169,11 +169,11 @@ def main():
     src = torch.from_numpy(cl.sources).to(dev)
     wts = torch.from_numpy(cl.weights).to(dev)
     nrm = None if cl.normals is None else torch.from_numpy(cl.normals).to(dev)
-    # the stochastic method sees the queries shuffled (its wavefronts share random streams, so
-    # neighbouring pixels must not share a wavefront); Barnes-Hut runs on the original grid order
+    # the headline sees the queries shuffled (a wavefront's queries share random streams, so
+    # neighbouring pixels must not share a wavefront); the comparisons also run on the grid order
     qry_np, perm = W.shuffle_queries(cl.queries, 4242)
     qry = torch.from_numpy(qry_np).to(dev)
-    qry_bh = torch.from_numpy(cl.queries).to(dev)
+    qry_grid = torch.from_numpy(cl.queries).to(dev)
     N = qry.shape[0]
     stream = torch.cuda.current_stream()
 
@@ -204,9 +204,6 @@ def main():
     def run_sbh(tr, samples, group=args.group):
         P.sbh_eval(tr, qry, kernel, samples=samples, seed=0, group=group, out=out)
 
-    def run_bh(tr, beta):
-        P.sbh_eval(tr, qry_bh, kernel, beta=beta, samples=0, out=out)
-
     def timed(fn, steps, warmup):
         for _ in range(warmup):
             fn()
@@ -220,7 +217,7 @@ def main():
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / steps
 
-    bh_idx_t = torch.from_numpy(perm[sidx]).to(dev)
+    grid_idx_t = torch.from_numpy(perm[sidx]).to(dev)
 
     def err_of(fn, idx_t=sidx_t):
         fn()
@@ -334,24 +331,24 @@ def main():
     # wavefront (and its random stream); per-query estimates have the same distribution, but
     # neighbours' errors are correlated, which the paper avoids by shuffling
     def run_grid():
-        P.sbh_eval(tree, qry_bh, kernel, samples=S, seed=0, group=args.group, out=out)
+        P.sbh_eval(tree, qry_grid, kernel, samples=S, seed=0, group=args.group, out=out)
 
     grid_order = None
     if not args.no_grid:
         grid_order = dict(group=args.group, ms=timed(run_grid, args.steps, args.warmup),
-                          median_rel_err=err_of(run_grid, bh_idx_t))
+                          median_rel_err=err_of(run_grid, grid_idx_t))
         grid_order["queries_per_s"] = N / (grid_order["ms"] * 1e-3)
 
     # --- the tile-shared score proposal on the plane's own order (tiles of 64 neighbouring pixels)
     tile_grid = None
     if not args.no_grid and args.branching == 2:
         def run_tile(samples):
-            P.sbh_eval(tree, qry_bh, kernel, samples=samples, seed=0, group=args.group, out=out, proposal=3)
+            P.sbh_eval(tree, qry_grid, kernel, samples=samples, seed=0, group=args.group, out=out, proposal=3)
 
         tile_grid = dict(group=args.group, sweep=[])
         for sv in (1, 2, 4):
             ms_t = timed(lambda: run_tile(sv), args.steps if sv == 1 else 3, args.warmup if sv == 1 else 1)
-            tile_grid["sweep"].append(dict(samples=sv, ms=ms_t, median_rel_err=err_of(lambda: run_tile(sv), bh_idx_t)))
+            tile_grid["sweep"].append(dict(samples=sv, ms=ms_t, median_rel_err=err_of(lambda: run_tile(sv), grid_idx_t)))
         tile_grid["queries_per_s"] = N / (tile_grid["sweep"][0]["ms"] * 1e-3)
 
     # --- samples-per-subdomain sweep (error / time curve of the stochastic method)
@@ -362,39 +359,60 @@ def main():
             ms_s = timed(lambda: run_sbh(tree, sv), 3, 1)
             sweep.append(dict(samples=sv, ms=ms_s, median_rel_err=err_of(lambda: run_sbh(tree, sv))))
 
-    # --- Barnes-Hut sweep and equal-error interpolation
+    # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
+    # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
+    # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
+    # and the plane's own pixel order (coherent lanes, Barnes-Hut's best case).
     bh = None
     if not args.no_bh:
         bh_tree = tree if args.bh_branching == args.branching else build(args.bh_branching)[0]
-        pts = []
-        for beta in BETAS:
-            ms = timed(lambda: run_bh(bh_tree, beta), 3, 1)
-            e = err_of(lambda: run_bh(bh_tree, beta), bh_idx_t)
-            pts.append((beta, ms, e))
-            if e < err_star / 4 and len(pts) > 2:
-                break
-        t_eq = None
-        kind = "interpolated"
-        for (b0, m0, e0), (b1, m1, e1) in zip(pts, pts[1:]):
-            if (e0 - err_star) * (e1 - err_star) <= 0 and e0 != e1 and e0 > 0 and e1 > 0:
-                f = (math.log(err_star) - math.log(e0)) / (math.log(e1) - math.log(e0))
-                t_eq = math.exp(math.log(m0) + f * (math.log(m1) - math.log(m0)))
-                break
-        if t_eq is None:
-            if pts[0][2] <= err_star:
-                t_eq, kind = pts[0][1], "upper_bound_at_smallest_beta"
-            else:
-                kind = "not_reached"
+
+        def bh_sweep(qset, idx_t):
+            pts = []
+            for beta in BETAS:
+                def run(beta=beta):
+                    P.sbh_eval(bh_tree, qset, kernel, beta=beta, samples=0, out=out)
+                ms = timed(run, 3, 1)
+                e = err_of(run, idx_t)
+                pts.append((beta, ms, e))
+                if e < err_star / 4 and len(pts) > 2:
+                    break
+            return pts
+
+        def at_error(pts, e_target):
+            """Barnes-Hut's time at median error e_target: log-log interpolation between the bracketing betas"""
+            t = log_interp([p_[2] for p_ in pts], [p_[1] for p_ in pts], e_target)
+            if t is not None:
+                return t, "interpolated"
+            if pts[0][2] <= e_target:
+                return pts[0][1], "upper_bound_at_smallest_beta"
+            return None, "not_reached"
+
+        def summary(pts):
+            t_eq, kind = at_error(pts, err_star)
+            return dict(sweep=[dict(beta=b, ms=round(m, 4), median_rel_err=e) for b, m, e in pts],
+                        ms_at_equal_error=None if t_eq is None else round(t_eq, 4),
+                        queries_per_s_at_equal_error=None if t_eq is None else N / (t_eq * 1e-3), match=kind), t_eq
+
+        pts_s = bh_sweep(qry, sidx_t)
+        pts_g = bh_sweep(qry_grid, grid_idx_t)
+        sum_s, t_s = summary(pts_s)
+        sum_g, t_g = summary(pts_g)
         if tile_grid is not None:
-            # Barnes-Hut's time at the tile-proposal estimator's (lower) error
+            # Barnes-Hut (same pixel order) at the tile-proposal estimator's (lower) error
             e1 = tile_grid["sweep"][0]["median_rel_err"]
-            tb = log_interp([p_[2] for p_ in pts], [p_[1] for p_ in pts], e1)
+            tb = at_error(pts_g, e1)[0]
             tile_grid["bh_ms_at_this_error"] = tb
             tile_grid["speedup_vs_bh_at_this_error"] = None if tb is None else tb / tile_grid["sweep"][0]["ms"]
-        bh = dict(branching=args.bh_branching, sweep=[dict(beta=b, ms=round(m, 4), median_rel_err=e) for b, m, e in pts],
-                  ms_at_equal_error=None if t_eq is None else round(t_eq, 4),
-                  queries_per_s_at_equal_error=None if t_eq is None else N / (t_eq * 1e-3),
-                  match=kind, speedup_stochastic_vs_bh=None if t_eq is None else t_eq / ms_per_step)
+        if grid_order is not None:
+            tb = at_error(pts_g, grid_order["median_rel_err"])[0]
+            grid_order["bh_ms_at_this_error"] = tb
+            grid_order["speedup_vs_bh_at_this_error"] = None if tb is None else tb / grid_order["ms"]
+        bh = dict(branching=args.bh_branching, shuffled=sum_s, grid_order=sum_g,
+                  # the headline's queries, order and error for both methods
+                  speedup_stochastic_vs_bh=None if t_s is None else t_s / ms_per_step,
+                  # Barnes-Hut on the coherent pixel order against the headline (shuffled) estimator
+                  speedup_stochastic_vs_bh_on_grid_order=None if t_g is None else t_g / ms_per_step)
 
     # --- learned proposal: trained on the held-out surfaces, evaluated on this one
     learned = None

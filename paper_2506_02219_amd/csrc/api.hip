@@ -41,9 +41,7 @@ sbh_status hip_fail(hipError_t e, const char* where)
 
 void free_impl(sbh::sbh_tree_impl* t)
 {
-    void* bufs[] = {t->pts,  t->pdip, t->perm, t->codes, t->nbegin, t->ncount, t->nlevel, t->ndigit, t->nparent,
-                    t->nfirst, t->nnchild, t->nagg, t->ndip, t->nspr, t->bagg, t->bdip, t->bspr, t->btopo};
-    for (void* p : bufs)
+    for (void* p : t->slab)
         if (p) (void)hipFree(p);
 }
 

@@ -551,6 +551,24 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
 // ---------------------------------------------------------------------------
 namespace {
 
+// The tree's own arrays are carved, at 256-B boundaries, out of three
+// allocations (points, nodes, blocks) that the tree frees when it is released.
+template <class T>
+size_t carve_bytes(int64_t count)
+{
+    return ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+}
+
+struct Carver {
+    char* p;
+    template <class T> T* take(int64_t count)
+    {
+        T* r = (T*)p;
+        p += carve_bytes<T>(count);
+        return r;
+    }
+};
+
 // Temporaries of one build: a bump allocator over a few large chunks.  A
 // build takes some two hundred temporaries, and one hipMalloc / hipFree pair
 // each (hipFree waits for the device) cost several times the build's kernels.
@@ -652,10 +670,16 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     SBH_TRY(radix_sort_pairs(keys, vals, keys2, vals2, n, 0, 64, hist, stmp, s), "radix sort");
 
     // sorted points (owned by the tree)
-    SBH_TRY(hipMalloc(&t->pts, n * sizeof(float4)), "allocating points");
-    if (nrm) SBH_TRY(hipMalloc(&t->pdip, n * sizeof(float4)), "allocating dipoles");
-    SBH_TRY(hipMalloc(&t->perm, n * sizeof(uint32_t)), "allocating permutation");
-    SBH_TRY(hipMalloc(&t->codes, n * sizeof(uint64_t)), "allocating codes");
+    SBH_TRY(hipMalloc(&t->slab[0], carve_bytes<float4>(n) * (nrm ? 2 : 1) + carve_bytes<uint32_t>(n) +
+                                        carve_bytes<uint64_t>(n)),
+            "allocating points");
+    {
+        Carver c{(char*)t->slab[0]};
+        t->pts = c.take<float4>(n);
+        if (nrm) t->pdip = c.take<float4>(n);
+        t->perm = c.take<uint32_t>(n);
+        t->codes = c.take<uint64_t>(n);
+    }
     k_gather_points<<<nblk(n), 256, 0, s>>>(src, w, nrm, vals, n, t->pts, t->pdip);
     SBH_TRY(hipGetLastError(), "gather kernel");
     SBH_TRY(hipMemcpyAsync(t->perm, vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "perm copy");
@@ -766,16 +790,22 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     }
 
     // concatenate level arrays into node arrays
-    SBH_TRY(hipMalloc(&t->nbegin, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->ncount, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nlevel, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->ndigit, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nparent, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nfirst, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nnchild, n_nodes * 4), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nagg, n_nodes * sizeof(float4)), "allocating nodes");
-    if (nrm) SBH_TRY(hipMalloc(&t->ndip, n_nodes * sizeof(float4)), "allocating nodes");
-    SBH_TRY(hipMalloc(&t->nspr, n_nodes * sizeof(float)), "allocating nodes");
+    SBH_TRY(hipMalloc(&t->slab[1], carve_bytes<int32_t>(n_nodes) * 7 + carve_bytes<float4>(n_nodes) * (nrm ? 2 : 1) +
+                                        carve_bytes<float>(n_nodes)),
+            "allocating nodes");
+    {
+        Carver c{(char*)t->slab[1]};
+        t->nbegin = c.take<int32_t>(n_nodes);
+        t->ncount = c.take<int32_t>(n_nodes);
+        t->nlevel = c.take<int32_t>(n_nodes);
+        t->ndigit = c.take<int32_t>(n_nodes);
+        t->nparent = c.take<int32_t>(n_nodes);
+        t->nfirst = c.take<int32_t>(n_nodes);
+        t->nnchild = c.take<int32_t>(n_nodes);
+        t->nagg = c.take<float4>(n_nodes);
+        if (nrm) t->ndip = c.take<float4>(n_nodes);
+        t->nspr = c.take<float>(n_nodes);
+    }
     int32_t* npblk = tmp.alloc<int32_t>(n_nodes);
     SBH_ALLOC_OK("allocating parent blocks");
     {
@@ -797,15 +827,16 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     }
     // block arrays
     const int64_t nbk = n_blocks > 0 ? n_blocks : 1;
-    SBH_TRY(hipMalloc(&t->btopo, (size_t)nbk * ts * sizeof(uint32_t)), "allocating blocks");
-    SBH_TRY(hipMalloc(&t->bagg, (size_t)nbk * d3 * sizeof(float4)), "allocating blocks");
-    SBH_TRY(hipMemsetAsync(t->btopo, 0, (size_t)nbk * ts * sizeof(uint32_t), s), "blocks clear");
-    SBH_TRY(hipMemsetAsync(t->bagg, 0, (size_t)nbk * d3 * sizeof(float4), s), "blocks clear");
-    SBH_TRY(hipMalloc(&t->bspr, (size_t)nbk * d3 * sizeof(float)), "allocating blocks");
-    SBH_TRY(hipMemsetAsync(t->bspr, 0, (size_t)nbk * d3 * sizeof(float), s), "blocks clear");
-    if (nrm) {
-        SBH_TRY(hipMalloc(&t->bdip, (size_t)nbk * d3 * sizeof(float4)), "allocating blocks");
-        SBH_TRY(hipMemsetAsync(t->bdip, 0, (size_t)nbk * d3 * sizeof(float4), s), "blocks clear");
+    {
+        const size_t bytes = carve_bytes<uint32_t>(nbk * ts) + carve_bytes<float4>(nbk * d3) * (nrm ? 2 : 1) +
+                             carve_bytes<float>(nbk * d3);
+        SBH_TRY(hipMalloc(&t->slab[2], bytes), "allocating blocks");
+        SBH_TRY(hipMemsetAsync(t->slab[2], 0, bytes, s), "blocks clear");
+        Carver c{(char*)t->slab[2]};
+        t->btopo = c.take<uint32_t>(nbk * ts);
+        t->bagg = c.take<float4>(nbk * d3);
+        t->bspr = c.take<float>(nbk * d3);
+        if (nrm) t->bdip = c.take<float4>(nbk * d3);
     }
     for (int l = 0; l < n_levels; ++l) {
         if (n_int_lv[l] > 0 && btopo_lv[l]) {

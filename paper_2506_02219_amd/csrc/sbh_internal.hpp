@@ -83,6 +83,7 @@ struct sbh_tree_impl {
     float4 *bagg, *bdip;
     float* bspr;
     uint32_t* btopo;
+    void* slab[3];   // the allocations the arrays above are carved from: points, nodes, blocks
 };
 
 // ---------------------------------------------------------------------------
