@@ -464,13 +464,13 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                         for (int c = 0; c < D3; ++c) {
                             const uint32_t cnt = gld(bt + c);
                             const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                            const float v = term<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0);
-                            sumc += cnt ? v : 0.0f;
+                            const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                            sumc = cnt ? v : sumc;
                         }
                     } else {
                         for (uint32_t i = 0; i < nT; ++i) {
                             const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
-                            sumc += term<K>(gld4(tv.pts + beginT + i), gd, qx, qy, qz, kp, r0);
+                            sumc = term_acc<K>(gld4(tv.pts + beginT + i), gd, qx, qy, qz, kp, r0, sumc);
                         }
                     }
                     prr *= pr;
@@ -716,22 +716,22 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                 for (int c = 0; c < D3; ++c) {
                     if (!(((uint32_t)nonempty >> c) & 1u)) continue;
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    sumc += term<K>(g8[c], gd, qx, qy, qz, kp, r0);
+                    sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
                 }
             } else {
 #pragma unroll 8
                 for (int c = 0; c < D3; ++c) {
                     const uint32_t cnt = gld(bt + c);
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    const float v = term<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0);
-                    sumc += cnt ? v : 0.0f;
+                    const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                    sumc = cnt ? v : sumc;
                 }
             }
         } else {
             for (uint32_t i = 0; i < nT; ++i) {
                 const float4 g = gld4(tv.pts + beginT + i);
                 const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
-                sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+                sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
             }
         }
         if (cont) {
@@ -944,13 +944,13 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             for (int c = 0; c < D3; ++c) {
                 if (!((nonempty >> c) & 1u)) continue;
                 const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                sumc += term_r2<K>(g8[c], gd, g8[c].x - qx, g8[c].y - qy, g8[c].z - qz, r2[c], kp, r0);
+                sumc = term_r2_acc<K>(g8[c], gd, g8[c].x - qx, g8[c].y - qy, g8[c].z - qz, r2[c], kp, r0, sumc);
             }
         } else {   // leaf: its points are the virtual children
             for (uint32_t i = 0; i < nT; ++i) {
                 const float4 g = gld4(tv.pts + beginT + i);
                 const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
-                sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+                sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
             }
         }
         if (cont) {
@@ -1168,7 +1168,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             acc = term<K>(g, (K == SBH_WINDING) ? tv.ndip[0] : zero4, qx, qy, qz, kp, r0);
         } else if (!tv.root_internal) {
             for (int i = 0; i < tv.n_points; ++i)
-                acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
+                acc = term_acc<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0, acc);
         } else {
             if (lane == 0) stack[wv][0] = make_int2(0, 0);  // block 0, level 0 (packed), begin 0
             sp = 1;
@@ -1195,15 +1195,16 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             const bool internal_c = (int)cnt > tv.leaf_size && level + 1 < tv.max_level;
             const float4 g = ba[c];
             const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
-            const bool near = valid && !(norm2(dx, dy, dz) >= limC * limC);
+            const float r2 = norm2(dx, dy, dz);
+            const bool near = valid && !(r2 >= limC * limC);
             if (__ballot(near) == 0ull) {
-                acc += term<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, qx, qy, qz, kp, r0);
+                acc = term_r2_acc<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, dx, dy, dz, r2, kp, r0, acc);
             } else if (internal_c) {
                 if (lane == 0) stack[wv][sp] = make_int2((int32_t)(((uint32_t)(level + 1) << 27) | (uint32_t)(base + nint)), (int32_t)pre);
                 ++sp;
             } else {
                 for (uint32_t i = pre; i < pre + cnt; ++i)
-                    acc += term<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0);
+                    acc = term_acc<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0, acc);
             }
             nint += internal_c ? 1 : 0;
             pre += cnt;
@@ -1232,7 +1233,7 @@ __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float acc = 0.0f;
     for (int i = 0; i < tv.n_points; ++i)
-        acc += term<K>(gld4(tv.pts + i), (K == SBH_WINDING) ? gld4(tv.pdip + i) : zero4, qx, qy, qz, kp, r0);
+        acc = term_acc<K>(gld4(tv.pts + i), (K == SBH_WINDING) ? gld4(tv.pdip + i) : zero4, qx, qy, qz, kp, r0, acc);
     if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(acc) + logwbar) / alpha);
     else gst(out + j, acc);
 }

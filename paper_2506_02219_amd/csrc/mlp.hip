@@ -768,7 +768,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
                 for (uint32_t i = 0; i < nT; ++i) {
                     const float4 g = tv.pts[beginT + i];
                     const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
-                    sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+                    sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
                 }
             }
             prr *= p;
@@ -1054,7 +1054,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const flo
                     for (uint32_t i = 0; i < nT; ++i) {
                         const float4 g = tv.pts[beginT + i];
                         const float4 gd = (K == SBH_WINDING) ? tv.pdip[beginT + i] : zero4;
-                        sumc += term<K>(g, gd, qx, qy, qz, kp, r0);
+                        sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
                     }
                 }
                 prr *= pr;

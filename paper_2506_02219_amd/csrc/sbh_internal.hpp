@@ -165,6 +165,41 @@ __device__ __forceinline__ float term(float4 a, float4 dp, float qx, float qy, f
     return term_r2<K>(a, dp, dx, dy, dz, norm2(dx, dy, dz), kp, r0);
 }
 
+// acc + term_r2<K>(...), with the final add fused into a multiply-add.
+template <int K>
+__device__ __forceinline__ float term_r2_acc(float4 a, float4 dp, float dx, float dy, float dz, float r2,
+                                             const KParams& kp, float r0, float acc)
+{
+#pragma clang fp contract(off)
+    if constexpr (K == SBH_POTENTIAL) {
+        return fmaf(a.w, __builtin_amdgcn_rsqf(r2 + kp.eps2), acc);
+    } else if constexpr (K == SBH_WINDING) {
+        const float inv = __builtin_amdgcn_rsqf(r2);
+        const float s = r2 > 0.0f ? (inv * inv * inv) * kInv4Pi : 0.0f;   // 0 at r = 0, where the dot is 0 too
+        return fmaf(fmaf(dp.z, dz, fmaf(dp.x, dx, dp.y * dy)), s, acc);
+    } else {
+        const float r = fsqrt(r2);
+        return fmaf(a.w * kp.wscale, __expf(-kp.alpha * (r - r0)), acc);
+    }
+}
+
+// acc + term<K>(...): the sums of the walks.  For the potential the softening
+// enters the first multiply-add of the squared distance and the weight the
+// accumulating one (the value differs from term() by rounding only).
+template <int K>
+__device__ __forceinline__ float term_acc(float4 a, float4 dp, float qx, float qy, float qz, const KParams& kp,
+                                          float r0, float acc)
+{
+#pragma clang fp contract(off)
+    const float dx = a.x - qx, dy = a.y - qy, dz = a.z - qz;
+    if constexpr (K == SBH_POTENTIAL) {
+        const float r2e = fmaf(dz, dz, fmaf(dx, dx, fmaf(dy, dy, kp.eps2)));
+        return fmaf(a.w, __builtin_amdgcn_rsqf(r2e), acc);
+    } else {
+        return term_r2_acc<K>(a, dp, dx, dy, dz, norm2(dx, dy, dz), kp, r0, acc);
+    }
+}
+
 // Lower bound on the distance from q to any source (distance to the root
 // cube); used as the shift of the smooth-distance sum so that no term
 // overflows: with it every exp(-alpha (r - r0)) of a point or of a centre of
