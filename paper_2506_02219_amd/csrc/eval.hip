@@ -702,19 +702,22 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             end_l = level;
         }
         if (contm == 0ull) break;
-        // contribution swap, Eq. (6)
-        float sumc = 0.0f;
+        // contribution swap, Eq. (6).  The selected child's own term (from the roulette's
+        // offset and squared distance) opens the sum and is the next step's control
+        // variate, so the two agree bit for bit and the child is not evaluated twice.
         const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
+        float sumc = tC;
         if (internal) {
             if constexpr (D == 2) {
-                // the block in one batch of scalar loads; only the non-empty slots (about half
-                // of them on a surface) are evaluated, behind wavefront-uniform branches
+                // the block in one batch of scalar loads; only the other non-empty slots (about
+                // half of them on a surface) are evaluated, behind wavefront-uniform branches
+                const uint32_t rest = (uint32_t)nonempty & ~(1u << csel);
                 float4 g8[D3];
 #pragma unroll
                 for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
 #pragma unroll
                 for (int c = 0; c < D3; ++c) {
-                    if (!(((uint32_t)nonempty >> c) & 1u)) continue;
+                    if (!((rest >> c) & 1u)) continue;
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                     sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
                 }
@@ -724,11 +727,12 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     const uint32_t cnt = gld(bt + c);
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                     const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
-                    sumc = cnt ? v : sumc;
+                    sumc = (cnt && c != csel) ? v : sumc;
                 }
             }
         } else {
             for (uint32_t i = 0; i < nT; ++i) {
+                if (i == r) continue;   // the selected point: its term opened the sum
                 const float4 g = gld4(tv.pts + beginT + i);
                 const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
                 sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
@@ -836,6 +840,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         float qsel;
         uint32_t rleaf = 0u;
         uint32_t nonempty = 0u;   // slots with points (wavefront-uniform)
+        int csel = 0;
         float4 g8[D3];            // the block's aggregates, kept for the swap
         float r2[D3];             // this lane's squared distances to them, shared by score and term
         if (internal) {
@@ -901,7 +906,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             cum += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cum), 0x112, 0xF, 0xF, true));   // row_shr:2
             cum += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cum), 0x114, 0xF, 0xF, true));   // row_shr:4
             const uint64_t hit = __ballot(u_sel < cum) & ((1ull << D3) - 1ull);
-            const int csel = hit ? __ffsll((unsigned long long)hit) - 1 : 31 - __builtin_clz(nonempty);
+            csel = hit ? __ffsll((unsigned long long)hit) - 1 : 31 - __builtin_clz(nonempty);
             qsel = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc), csel));
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
             nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
@@ -936,18 +941,22 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             end_l = level;
         }
         if (contm == 0ull) break;
-        float sumc = 0.0f;
+        // the selected child's own term opens the swap's sum (and is the next step's
+        // control variate), the other non-empty children follow
         const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
+        float sumc = tC;
         if (internal) {   // contribution swap over the non-empty children, Eq. (6)
             const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+            const uint32_t rest = nonempty & ~(1u << csel);
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
-                if (!((nonempty >> c) & 1u)) continue;
+                if (!((rest >> c) & 1u)) continue;
                 const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                 sumc = term_r2_acc<K>(g8[c], gd, g8[c].x - qx, g8[c].y - qy, g8[c].z - qz, r2[c], kp, r0, sumc);
             }
         } else {   // leaf: its points are the virtual children
             for (uint32_t i = 0; i < nT; ++i) {
+                if (i == rleaf) continue;   // the selected point: its term opened the sum
                 const float4 g = gld4(tv.pts + beginT + i);
                 const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
                 sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
