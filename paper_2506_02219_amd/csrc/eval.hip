@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include <algorithm>
 
@@ -61,6 +62,13 @@ TreeView make_view(const sbh_tree_impl* t)
     v.leaf_size = t->leaf_size;
     v.max_level = t->max_level;
     v.root_internal = (t->n_points > t->leaf_size && t->max_level > 0) ? 1 : 0;
+    const uint64_t nbk = (uint64_t)(t->n_blocks > 0 ? t->n_blocks : 1);
+    const uint64_t big = std::max({nbk * (uint64_t)t->d3 * 16u, nbk * (uint64_t)topo_stride(t->d3) * 4u,
+                                   (uint64_t)t->n_points * 16u});
+    // SBH_FORCE_WIDE_OFFSETS=1 takes the 64-bit offsets for any tree (a diagnostic:
+    // both forms give the same values bit for bit)
+    const char* force = std::getenv("SBH_FORCE_WIDE_OFFSETS");
+    v.wide = (big >= ((uint64_t)1 << 32) || (force && force[0] == '1')) ? 1 : 0;
     v.lo[0] = t->lo[0]; v.lo[1] = t->lo[1]; v.lo[2] = t->lo[2];
     v.side = t->side;
     v.diam0 = t->diam[0];
@@ -542,6 +550,23 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
 // ---------------------------------------------------------------------------
 // max(a, b) of two non-negative finite floats as one instruction (fmaxf quiets
 // NaN inputs first, two more instructions that the walk does not need)
+// Byte offsets into the tree's arrays: 32-bit while every array of the tree is
+// below 4 GiB (scalar loads then take the offset as a register operand, with no
+// 64-bit address arithmetic), 64-bit otherwise.
+template <bool O64>
+struct TreeOff {
+    using T = uint32_t;
+};
+template <>
+struct TreeOff<true> {
+    using T = uint64_t;
+};
+template <class T, class O>
+__device__ __forceinline__ const T* at_off(const T* base, O byte_off)
+{
+    return (const T*)((const char*)base + byte_off);
+}
+
 __device__ __forceinline__ float vmax(float a, float b)
 {
     float r;
@@ -586,7 +611,7 @@ struct PathWords {
     }
 };
 
-template <int D, int K, bool TRACE>
+template <int D, int K, bool TRACE, bool O64>
 __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
                                            const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
                                            int32_t blk_a, float4 agg_a, float t_a, const PathWords& pw,
@@ -597,6 +622,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
+    using Off = typename TreeOff<O64>::T;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     // wavefront-uniform walk state
     uint32_t nT = n_a, beginT = begin_a;
@@ -612,87 +638,82 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
-        if (nT == 1u) {
-            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
-            break;
+    // the roulette (Eq. (5)); the offset and squared distance it takes also give the
+    // selected child's own term, which opens the swap's sum and is the next step's control
+    // variate (the two agree bit for bit and the child is not evaluated twice)
+    auto roulette = [&](float r2C, float& dC) -> float {
+        if (rr_mode == 0) {
+            dC = fsqrt(r2C);
+            return fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
         }
+        dC = 0.0f;
+        return rr_mode == 1 ? 1.0f : 0.5f;
+    };
+    int k = 0;
+    // internal nodes: the walk leaves the loop at a leaf, or when the roulette has
+    // stopped every lane (actm then 0)
+    while (actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level) {
         uint32_t xsel;
         float u;
         pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
         const uint32_t r = __umulhi(xsel, nT);
-        const bool internal = (int)nT > tv.leaf_size && level < tv.max_level;
-        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
-        const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+        const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);   // the block's aggregates and dipoles
+        const Off toff = (Off)(uint32_t)blk * (Off)(TS * 4);    // its topology row
+        const uint32_t* __restrict__ bt = at_off(tv.btopo, toff);
         float4 aggC, dpC = zero4;   // the selected child's aggregate (and dipole)
         uint32_t nC = 1u, beginC;
         int32_t blkC = 0;
         int csel = 0;
-        uint64_t nonempty = 0ull;   // d = 2: slots with points (wavefront-uniform)
-        if (internal) {
-            if constexpr (D == 2) {
-                // child selection across lanes 0..7 (one slot each): an exclusive scan of the
-                // counts by DPP row shifts, then ballots give the slot whose range holds r, the
-                // internal slots before it and the non-empty slots
-                // (lanes 8..63 load the block's last word, padding that the build leaves zero: they
-                // hold a zero count and none of them votes)
-                static_assert(TS - 1 > D3, "the topology row needs a padding word");
-                const int ln = threadIdx.x & 63;
-                const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
-                uint32_t inc = cl;
-                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
-                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
-                inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
-                const uint32_t excl = inc - cl;
-                const uint64_t hm = __ballot((r - excl) < cl);
-                const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
-                nonempty = __ballot(cl != 0u);
-                csel = __ffsll((unsigned long long)hm) - 1;
-                const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
-                nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
-                const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
-                aggC = gld4(ba + csel);
-                if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
-                beginC = beginT + preC;
-                blkC = (int32_t)gld(bt + D3) + nintC;
-            } else {
-                // uniform child selection from the point counts alone
-                uint32_t pre = 0u, preC = 0u;
-                int32_t nint = 0, nintC = 0;
-                for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = gld(bt + c);
-                    const bool hit = (r - pre) < cnt;
-                    csel = hit ? c : csel;
-                    preC = hit ? pre : preC;
-                    nintC = hit ? nint : nintC;
-                    nC = hit ? cnt : nC;
-                    nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
-                    pre += cnt;
-                }
-                aggC = gld4(ba + csel);
-                if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
-                beginC = beginT + preC;
-                blkC = (int32_t)gld(bt + D3) + nintC;
-            }
+        uint32_t nonempty = 0u;   // d = 2: slots with points (wavefront-uniform)
+        if constexpr (D == 2) {
+            // child selection across lanes 0..7 (one slot each): an exclusive scan of the
+            // counts by DPP row shifts, then ballots give the slot whose range holds r, the
+            // internal slots before it and the non-empty slots
+            // (lanes 8..63 load the row's last word, padding that the build leaves zero: they
+            // hold a zero count and none of them votes)
+            static_assert(TS - 1 > D3, "the topology row needs a padding word");
+            const int ln = threadIdx.x & 63;
+            const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
+            uint32_t inc = cl;
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
+            const uint32_t excl = inc - cl;
+            const uint64_t hm = __ballot((r - excl) < cl);
+            const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
+            nonempty = (uint32_t)__ballot(cl != 0u);
+            csel = __ffsll((unsigned long long)hm) - 1;
+            const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+            nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+            const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
+            aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
+            if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
+            beginC = beginT + preC;
+            blkC = (int32_t)gld(bt + D3) + nintC;
         } else {
-            aggC = gld4(tv.pts + beginT + r);
-            if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + r);
-            beginC = beginT + r;
+            // uniform child selection from the point counts alone
+            uint32_t pre = 0u, preC = 0u;
+            int32_t nint = 0, nintC = 0;
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = gld(bt + c);
+                const bool hit = (r - pre) < cnt;
+                csel = hit ? c : csel;
+                preC = hit ? pre : preC;
+                nintC = hit ? nint : nintC;
+                nC = hit ? cnt : nC;
+                nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+                pre += cnt;
+            }
+            aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
+            if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
+            beginC = beginT + preC;
+            blkC = (int32_t)gld(bt + D3) + nintC;
         }
-        // roulette first (Eq. (5)): the swap is only needed by lanes that continue
-        // (the offset and squared distance also give the selected child's own term below,
-        // bit for bit the value the swap's sum takes for it)
-        float p;
-        float dC = 0.0f;
+        // roulette first: the swap is only needed by lanes that continue
+        float dC;
         const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
         const float r2C = norm2(cx, cy, cz);
-        if (rr_mode == 0) {
-            dC = fsqrt(r2C);
-            p = fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
-        } else {
-            p = rr_mode == 1 ? 1.0f : 0.5f;
-        }
+        const float p = roulette(r2C, dC);
         const bool lt = u < p;
         const uint64_t contm = __ballot(lt) & actm;
         const bool cont = act && lt;
@@ -701,41 +722,35 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             end_b = (int32_t)beginT;
             end_l = level;
         }
-        if (contm == 0ull) break;
-        // contribution swap, Eq. (6).  The selected child's own term (from the roulette's
-        // offset and squared distance) opens the sum and is the next step's control
-        // variate, so the two agree bit for bit and the child is not evaluated twice.
+        if (contm == 0ull) {
+            actm = 0ull;
+            break;
+        }
+        // contribution swap, Eq. (6)
         const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
         float sumc = tC;
-        if (internal) {
-            if constexpr (D == 2) {
-                // the block in one batch of scalar loads; only the other non-empty slots (about
-                // half of them on a surface) are evaluated, behind wavefront-uniform branches
-                const uint32_t rest = (uint32_t)nonempty & ~(1u << csel);
-                float4 g8[D3];
+        const float4* __restrict__ ba = at_off(tv.bagg, boff);
+        const float4* __restrict__ bd = at_off(tv.bdip, boff);
+        if constexpr (D == 2) {
+            // the block in one batch of scalar loads; only the other non-empty slots (about
+            // half of them on a surface) are evaluated, behind wavefront-uniform branches
+            const uint32_t rest = nonempty & ~(1u << csel);
+            float4 g8[D3];
 #pragma unroll
-                for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
+            for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
 #pragma unroll
-                for (int c = 0; c < D3; ++c) {
-                    if (!((rest >> c) & 1u)) continue;
-                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
-                }
-            } else {
-#pragma unroll 8
-                for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = gld(bt + c);
-                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
-                    sumc = (cnt && c != csel) ? v : sumc;
-                }
+            for (int c = 0; c < D3; ++c) {
+                if (!((rest >> c) & 1u)) continue;
+                const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
             }
         } else {
-            for (uint32_t i = 0; i < nT; ++i) {
-                if (i == r) continue;   // the selected point: its term opened the sum
-                const float4 g = gld4(tv.pts + beginT + i);
-                const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
-                sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
+#pragma unroll 8
+            for (int c = 0; c < D3; ++c) {
+                const uint32_t cnt = gld(bt + c);
+                const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                sumc = (cnt && c != csel) ? v : sumc;
             }
         }
         if (cont) {
@@ -743,14 +758,6 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             acc += (sumc - tT) * (fna * frcp((float)nT * prr));
             ++steps;
             tT = tC;
-        }
-        if (!internal) {
-            if (cont) {
-                flag = 2;
-                end_b = (int32_t)beginC;
-                end_l = level + 1;
-            }
-            break;
         }
         act = cont;
         actm = contm;
@@ -760,6 +767,46 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         blk = blkC;
         ++level;
         diamT *= kInvD;
+        ++k;
+    }
+    if (actm != 0ull) {
+        if (nT == 1u) {   // a single point: the walk is exact from here
+            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+        } else {          // a leaf: its points are the virtual children, one drawn uniformly
+            uint32_t xsel;
+            float u;
+            pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+            const uint32_t r = __umulhi(xsel, nT);
+            const float4 aggC = gld4(at_off(tv.pts, (Off)(beginT + r) * (Off)16));
+            const float4 dpC = (K == SBH_WINDING) ? gld4(at_off(tv.pdip, (Off)(beginT + r) * (Off)16)) : zero4;
+            float dC;
+            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+            const float r2C = norm2(cx, cy, cz);
+            const float p = roulette(r2C, dC);
+            const bool cont = act && u < p;
+            if (act && !cont) {
+                flag = 0;
+                end_b = (int32_t)beginT;
+                end_l = level;
+            }
+            if (__ballot(cont) != 0ull) {
+                float sumc = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
+                for (uint32_t i = 0; i < nT; ++i) {
+                    if (i == r) continue;   // the selected point: its term opened the sum
+                    const Off po = (Off)(beginT + i) * (Off)16;
+                    const float4 gd = (K == SBH_WINDING) ? gld4(at_off(tv.pdip, po)) : zero4;
+                    sumc = term_acc<K>(gld4(at_off(tv.pts, po)), gd, qx, qy, qz, kp, r0, sumc);
+                }
+                if (cont) {
+                    prr *= p;
+                    acc += (sumc - tT) * (fna * frcp((float)nT * prr));
+                    ++steps;
+                    flag = 2;
+                    end_b = (int32_t)(beginT + r);
+                    end_l = level + 1;
+                }
+            }
+        }
     }
     if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
     return acc;
@@ -1001,7 +1048,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
 // evaluation per part.  LDS: part_f [wavefronts of the block][64] and one
 // counter per tile of the block in `done`, zeroed before the block's first
 // barrier.
-template <int D, int K, bool TRACE, bool TILE = false, int P = 1>
+template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave, int part = 0,
                                               int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr)
@@ -1064,8 +1111,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
                 fa += wave_path_tile<K, TRACE>(tv, qx, qy, qz, r0, kp, valid, inv_valid, n_a, begin_a, blk_a, agg_a,
                                                cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             else
-                fa += wave_path<D, K, TRACE>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw,
-                                             stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
+                fa += wave_path<D, K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw,
+                                                  stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
             }
@@ -1092,7 +1139,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     }
 }
 
-template <int D, int K, bool TRACE>
+template <int D, int K, bool TRACE, bool O64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
@@ -1105,7 +1152,7 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
     }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile<D, K, TRACE, false, P>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+    sbh_wave_tile<D, K, TRACE, false, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // the coherent walk with the tile-shared score proposal (d = 2)
@@ -1304,7 +1351,10 @@ k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, co
     a.batch = st->batch;
     // the descriptor stays in memory and its fields are read where they are used
     // (scalar loads), as kernel arguments are
-    sbh_wave_tile<D, K, false, false, P>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
+    if (it->tv.wide)
+        sbh_wave_tile<D, K, false, false, P, true>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
+    else
+        sbh_wave_tile<D, K, false, false, P, false>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
 }
 
 // Clouds whose root is a leaf are summed exactly, as sbh_eval does, in launches
@@ -1349,8 +1399,13 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             }
             return hipErrorInvalidValue;
         }
-        if (e.paths) k_sbh_wave<D, K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
-        else k_sbh_wave<D, K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+        if (tv.wide) {
+            if (e.paths) k_sbh_wave<D, K, true, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+            else k_sbh_wave<D, K, false, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+        } else {
+            if (e.paths) k_sbh_wave<D, K, true, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+            else k_sbh_wave<D, K, false, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+        }
         return hipGetLastError();
     }
     if ((int64_t)D * D * D * e.samples <= kPoolPaths) {

@@ -47,6 +47,7 @@ struct TreeView {
     int32_t leaf_size;
     int32_t max_level;
     int32_t root_internal;
+    int32_t wide;         // an array of the tree reaches 4 GiB: the walks take 64-bit offsets
     float lo[3];
     float side;
     float diam0;          // root cell diagonal; level l has diam0 / d^l

@@ -62,6 +62,20 @@ def test_batch_equals_single_calls(config):
     b.free()
 
 
+def test_batch_with_wide_offsets_equals_single_calls(monkeypatch):
+    """A plan made while 64-bit tree offsets are forced (see the parity tests) gives the
+    values of the ordinary 32-bit single calls."""
+    clouds, trees, qs = make_batch(SPECS[:8])
+    kernels = [s[2] for s in SPECS[:8]]
+    ref = single(trees, qs, kernels, 1, 9, 2)
+    monkeypatch.setenv("SBH_FORCE_WIDE_OFFSETS", "1")
+    b = P.Batch(trees, qs, kernels, samples=1, alpha=ALPHA, config=(2, 8, 1))
+    outs = [host(o) for o in b.launch(9, 2)]
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o, r, equal_nan=True)
+    b.free()
+
+
 def test_graph_replays_with_eager_work_between():
     clouds, trees, qs = make_batch(SPECS[:6])
     kernels = [s[2] for s in SPECS[:6]]
