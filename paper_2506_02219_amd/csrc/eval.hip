@@ -630,9 +630,9 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     int level = 1;
     float diamT = tv.diam0 * kInvD;
     const float fna = (float)n_a;
-    // per-lane state; actm holds the lanes still walking (wavefront-uniform), kept as a mask
-    // so that the votes below are single compares
-    bool act = valid;
+    // per-lane state; actm holds the lanes still walking (wavefront-uniform): a lane's own
+    // flag is its bit, so that the votes below are single compares and no per-lane flag is
+    // carried from step to step
     uint64_t actm = __ballot(valid);
     float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));   // |com_T - q|, carried step to step
     float tT = t_a, prr = 1.0f, acc = 0.0f;
@@ -651,8 +651,9 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     };
     int k = 0;
     // internal nodes: the walk leaves the loop at a leaf, or when the roulette has
-    // stopped every lane (actm then 0)
-    while (actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level) {
+    // stopped every lane (actm then 0); the loop has this one exit
+    bool go = actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level;
+    while (go) {
         uint32_t xsel;
         float u;
         pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
@@ -714,64 +715,60 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
         const float r2C = norm2(cx, cy, cz);
         const float p = roulette(r2C, dC);
-        const bool lt = u < p;
-        const uint64_t contm = __ballot(lt) & actm;
-        const bool cont = act && lt;
-        if (act && !cont) {
+        const uint64_t contm = __ballot(u < p) & actm;
+        if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {   // lanes this roulette stops
             flag = 0;
             end_b = (int32_t)beginT;
             end_l = level;
         }
-        if (contm == 0ull) {
-            actm = 0ull;
-            break;
-        }
-        // contribution swap, Eq. (6)
-        const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
-        float sumc = tC;
-        const float4* __restrict__ ba = at_off(tv.bagg, boff);
-        const float4* __restrict__ bd = at_off(tv.bdip, boff);
-        if constexpr (D == 2) {
-            // the block in one batch of scalar loads; only the other non-empty slots (about
-            // half of them on a surface) are evaluated, behind wavefront-uniform branches
-            const uint32_t rest = nonempty & ~(1u << csel);
-            float4 g8[D3];
-#pragma unroll
-            for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
-#pragma unroll
-            for (int c = 0; c < D3; ++c) {
-                if (!((rest >> c) & 1u)) continue;
-                const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
-            }
-        } else {
-#pragma unroll 8
-            for (int c = 0; c < D3; ++c) {
-                const uint32_t cnt = gld(bt + c);
-                const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
-                sumc = (cnt && c != csel) ? v : sumc;
-            }
-        }
-        if (cont) {
-            prr *= p;
-            acc += (sumc - tT) * (fna * frcp((float)nT * prr));
-            ++steps;
-            tT = tC;
-        }
-        act = cont;
         actm = contm;
-        dT = dC;
-        nT = nC;
-        beginT = beginC;
-        blk = blkC;
-        ++level;
-        diamT *= kInvD;
-        ++k;
+        if (contm != 0ull) {
+            // contribution swap, Eq. (6)
+            const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
+            float sumc = tC;
+            const float4* __restrict__ ba = at_off(tv.bagg, boff);
+            const float4* __restrict__ bd = at_off(tv.bdip, boff);
+            if constexpr (D == 2) {
+                // the block in one batch of scalar loads; only the other non-empty slots (about
+                // half of them on a surface) are evaluated, behind wavefront-uniform branches
+                const uint32_t rest = nonempty & ~(1u << csel);
+                float4 g8[D3];
+#pragma unroll
+                for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
+#pragma unroll
+                for (int c = 0; c < D3; ++c) {
+                    if (!((rest >> c) & 1u)) continue;
+                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                    sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
+                }
+            } else {
+#pragma unroll 8
+                for (int c = 0; c < D3; ++c) {
+                    const uint32_t cnt = gld(bt + c);
+                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                    const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                    sumc = (cnt && c != csel) ? v : sumc;
+                }
+            }
+            if (__builtin_amdgcn_inverse_ballot_w64(contm)) {
+                prr *= p;
+                acc += (sumc - tT) * (fna * frcp((float)nT * prr));
+                ++steps;
+                tT = tC;
+            }
+            dT = dC;
+            nT = nC;
+            beginT = beginC;
+            blk = blkC;
+            ++level;
+            diamT *= kInvD;
+            ++k;
+        }
+        go = actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level;
     }
     if (actm != 0ull) {
         if (nT == 1u) {   // a single point: the walk is exact from here
-            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+            if (__builtin_amdgcn_inverse_ballot_w64(actm)) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
         } else {          // a leaf: its points are the virtual children, one drawn uniformly
             uint32_t xsel;
             float u;
@@ -783,13 +780,13 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
             const float r2C = norm2(cx, cy, cz);
             const float p = roulette(r2C, dC);
-            const bool cont = act && u < p;
-            if (act && !cont) {
+            const uint64_t contm = __ballot(u < p) & actm;
+            if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
                 flag = 0;
                 end_b = (int32_t)beginT;
                 end_l = level;
             }
-            if (__ballot(cont) != 0ull) {
+            if (contm != 0ull) {
                 float sumc = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
                 for (uint32_t i = 0; i < nT; ++i) {
                     if (i == r) continue;   // the selected point: its term opened the sum
@@ -797,7 +794,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     const float4 gd = (K == SBH_WINDING) ? gld4(at_off(tv.pdip, po)) : zero4;
                     sumc = term_acc<K>(gld4(at_off(tv.pts, po)), gd, qx, qy, qz, kp, r0, sumc);
                 }
-                if (cont) {
+                if (__builtin_amdgcn_inverse_ballot_w64(contm)) {
                     prr *= p;
                     acc += (sumc - tT) * (fna * frcp((float)nT * prr));
                     ++steps;
