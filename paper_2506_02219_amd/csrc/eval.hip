@@ -652,7 +652,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     int k = 0;
     // internal nodes: the walk leaves the loop at a leaf, or when the roulette has
     // stopped every lane (actm then 0); the loop has this one exit
-    bool go = actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level;
+    // (leaf_size >= 1, so an internal node holds at least two points)
+    bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
     while (go) {
         uint32_t xsel;
         float u;
@@ -680,13 +681,14 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
             const uint32_t excl = inc - cl;
-            const uint64_t hm = __ballot((r - excl) < cl);
-            const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
+            // (r < n_T, so exactly one slot holds it)
+            const uint32_t hm = (uint32_t)__ballot((r - excl) < cl);
+            const uint32_t im = level + 1 < tv.max_level ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
             nonempty = (uint32_t)__ballot(cl != 0u);
-            csel = __ffsll((unsigned long long)hm) - 1;
+            csel = __builtin_ctz(hm);
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
             nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
-            const int32_t nintC = __popcll(im & ((1ull << csel) - 1ull));
+            const int32_t nintC = __popc(im & ((1u << csel) - 1u));
             aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
             if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
             beginC = beginT + preC;
@@ -750,12 +752,14 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     sumc = (cnt && c != csel) ? v : sumc;
                 }
             }
-            if (__builtin_amdgcn_inverse_ballot_w64(contm)) {
-                prr *= p;
-                acc += (sumc - tT) * (fna * frcp((float)nT * prr));
-                ++steps;
-                tT = tC;
-            }
+            // the lanes the roulette keeps take the step (selects, not a branch)
+            const bool cont = __builtin_amdgcn_inverse_ballot_w64(contm);
+            const float prr2 = prr * p;
+            const float acc2 = acc + (sumc - tT) * (fna * frcp((float)nT * prr2));
+            prr = cont ? prr2 : prr;
+            acc = cont ? acc2 : acc;
+            tT = cont ? tC : tT;
+            steps += cont ? 1 : 0;
             dT = dC;
             nT = nC;
             beginT = beginC;
@@ -764,7 +768,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             diamT *= kInvD;
             ++k;
         }
-        go = actm != 0ull && nT != 1u && (int)nT > tv.leaf_size && level < tv.max_level;
+        go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
     }
     if (actm != 0ull) {
         if (nT == 1u) {   // a single point: the walk is exact from here
