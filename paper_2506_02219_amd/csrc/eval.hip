@@ -30,6 +30,7 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include <algorithm>
 
@@ -609,6 +610,22 @@ struct PathWords {
             u = unit24(__builtin_amdgcn_readlane((k & 1) ? e.w : e.y, 0));
         }
     }
+    // the same for a step whose parity is known at compile time (ODD: k odd); the
+    // variate stays a wavefront-uniform scalar on both branches
+    template <bool ODD>
+    __device__ __forceinline__ void step_p(int k, uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0,
+                                           uint32_t key1, uint32_t& xsel, float& u) const
+    {
+        if (k < 16) {
+            const int src = (int)((path & 7u) << 3) + (k >> 1);
+            xsel = __builtin_amdgcn_readlane(ODD ? vr.z : vr.x, src);
+            u = __uint_as_float(__builtin_amdgcn_readlane(ODD ? vr.w : vr.y, src));
+        } else {
+            const u32x4 e = philox4x32_10(ctr0, path, (uint32_t)(k >> 1) + (threadIdx.x & 7u), ctr3, key0, key1);
+            xsel = __builtin_amdgcn_readlane(ODD ? e.z : e.x, 0);
+            u = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(unit24(ODD ? e.w : e.y))));
+        }
+    }
 };
 
 template <int D, int K, bool TRACE, bool O64>
@@ -641,23 +658,26 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // the roulette (Eq. (5)); the offset and squared distance it takes also give the
     // selected child's own term, which opens the swap's sum and is the next step's control
     // variate (the two agree bit for bit and the child is not evaluated twice)
+    // (Eq. (5) is evaluated in every mode and replaced by the mode's constant, a select
+    // rather than a branch)
+    const bool rr_eq5 = rr_mode == 0;
+    const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     auto roulette = [&](float r2C, float& dC) -> float {
-        if (rr_mode == 0) {
-            dC = fsqrt(r2C);
-            return fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
-        }
-        dC = 0.0f;
-        return rr_mode == 1 ? 1.0f : 0.5f;
+        dC = fsqrt(r2C);
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
+        return rr_eq5 ? p5 : rr_fixed;
     };
     int k = 0;
     // internal nodes: the walk leaves the loop at a leaf, or when the roulette has
     // stopped every lane (actm then 0); the loop has this one exit
     // (leaf_size >= 1, so an internal node holds at least two points)
     bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
-    while (go) {
+    // one internal step; the loop below takes two per iteration (k even, then odd), so that
+    // each knows where its random words are held
+    auto internal_step = [&](auto odd) {
         uint32_t xsel;
         float u;
-        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        pw.template step_p<decltype(odd)::value>(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
         const uint32_t r = __umulhi(xsel, nT);
         const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);   // the block's aggregates and dipoles
         const Off toff = (Off)(uint32_t)blk * (Off)(TS * 4);    // its topology row
@@ -769,6 +789,10 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             ++k;
         }
         go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
+    };
+    while (go) {
+        internal_step(std::false_type{});
+        if (go) internal_step(std::true_type{});
     }
     if (actm != 0ull) {
         if (nT == 1u) {   // a single point: the walk is exact from here
