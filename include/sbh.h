@@ -180,9 +180,9 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   estimator stays unbiased for every query.  It pays when a tile's queries
  *   are close to one another (e.g. a grid in its own order).
  *
- *   The shared-stream walk addresses a tree with 32-bit byte offsets while
- *   each of its arrays is below 4 GiB, with 64-bit ones beyond (the values
- *   are the same).  Setting the environment variable
+ *   The shared-stream walk and Barnes-Hut address a tree with 32-bit byte
+ *   offsets while each of its arrays is below 4 GiB, with 64-bit ones beyond
+ *   (the values are the same).  Setting the environment variable
  *   SBH_FORCE_WIDE_OFFSETS=1 takes the 64-bit form for every tree; it is
  *   read when sbh_eval runs and when a batch plan is created.
  */

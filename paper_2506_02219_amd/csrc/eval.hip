@@ -1211,13 +1211,14 @@ constexpr int bh_stack_depth()
     return D == 2 ? (8 - 1) * 20 + 2 : (64 - 1) * 10 + 2;
 }
 
-template <int D, int K>
+template <int D, int K, bool O64>
 __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict__ queries, int64_t nq, BhArgs a,
                                             float* __restrict__ out)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
+    using Off = typename TreeOff<O64>::T;   // byte offsets into the tree's arrays, as in the walks
     constexpr int MAXS = bh_stack_depth<D>();
     __shared__ int2 stack[256 / 64][MAXS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1265,9 +1266,10 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         __builtin_amdgcn_wave_barrier();
         const float diamC = ldexpf(tv.diam0, -(level + 1) * (D == 2 ? 1 : 2));
         const float limC = a.beta * diamC;
-        const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
-        const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-        const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+        const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);
+        const float4* __restrict__ ba = at_off(tv.bagg, boff);
+        const float4* __restrict__ bd = at_off(tv.bdip, boff);
+        const uint32_t* __restrict__ bt = at_off(tv.btopo, (Off)(uint32_t)blk * (Off)(TS * 4));
         const int32_t base = (int32_t)bt[D3];
         int32_t nint = 0;
         for (int c = 0; c < D3; ++c) {
@@ -1284,8 +1286,11 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
                 if (lane == 0) stack[wv][sp] = make_int2((int32_t)(((uint32_t)(level + 1) << 27) | (uint32_t)(base + nint)), (int32_t)pre);
                 ++sp;
             } else {
-                for (uint32_t i = pre; i < pre + cnt; ++i)
-                    acc = term_acc<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0, acc);
+                for (uint32_t i = pre; i < pre + cnt; ++i) {
+                    const Off po = (Off)i * (Off)16;
+                    acc = term_acc<K>(*at_off(tv.pts, po), (K == SBH_WINDING) ? *at_off(tv.pdip, po) : zero4, qx, qy,
+                                      qz, kp, r0, acc);
+                }
             }
             nint += internal_c ? 1 : 0;
             pre += cnt;
@@ -1454,7 +1459,8 @@ static hipError_t launch_bh_dk(const TreeView& tv, const float* q, int64_t nq, c
                                hipStream_t s)
 {
     BhArgs a{e.beta, e.eps * e.eps, e.alpha};
-    k_bh<D, K><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(tv, q, nq, a, out);
+    if (tv.wide) k_bh<D, K, true><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(tv, q, nq, a, out);
+    else k_bh<D, K, false><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(tv, q, nq, a, out);
     return hipGetLastError();
 }
 
