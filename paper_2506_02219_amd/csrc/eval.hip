@@ -610,21 +610,21 @@ struct PathWords {
             u = unit24(__builtin_amdgcn_readlane((k & 1) ? e.w : e.y, 0));
         }
     }
-    // the same for a step whose parity is known at compile time (ODD: k odd); the
-    // variate stays a wavefront-uniform scalar on both branches
+    // the same for a step k < 16 whose parity is known at compile time (ODD: k odd)
     template <bool ODD>
-    __device__ __forceinline__ void step_p(int k, uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0,
-                                           uint32_t key1, uint32_t& xsel, float& u) const
+    __device__ __forceinline__ void step_held(int k, uint32_t path, uint32_t& xsel, float& u) const
     {
-        if (k < 16) {
-            const int src = (int)((path & 7u) << 3) + (k >> 1);
-            xsel = __builtin_amdgcn_readlane(ODD ? vr.z : vr.x, src);
-            u = __uint_as_float(__builtin_amdgcn_readlane(ODD ? vr.w : vr.y, src));
-        } else {
-            const u32x4 e = philox4x32_10(ctr0, path, (uint32_t)(k >> 1) + (threadIdx.x & 7u), ctr3, key0, key1);
-            xsel = __builtin_amdgcn_readlane(ODD ? e.z : e.x, 0);
-            u = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(unit24(ODD ? e.w : e.y))));
-        }
+        const int src = (int)((path & 7u) << 3) + (k >> 1);
+        xsel = __builtin_amdgcn_readlane(ODD ? vr.z : vr.x, src);
+        u = __uint_as_float(__builtin_amdgcn_readlane(ODD ? vr.w : vr.y, src));
+    }
+    // and for a step k >= 16 (the variate as a wavefront-uniform scalar)
+    __device__ __forceinline__ void step_late(int k, uint32_t path, uint32_t ctr0, uint32_t ctr3, uint32_t key0,
+                                              uint32_t key1, uint32_t& xsel, float& u) const
+    {
+        const u32x4 e = philox4x32_10(ctr0, path, (uint32_t)(k >> 1) + (threadIdx.x & 7u), ctr3, key0, key1);
+        xsel = __builtin_amdgcn_readlane((k & 1) ? e.z : e.x, 0);
+        u = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(unit24((k & 1) ? e.w : e.y))));
     }
 };
 
@@ -672,12 +672,16 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // stopped every lane (actm then 0); the loop has this one exit
     // (leaf_size >= 1, so an internal node holds at least two points)
     bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
-    // one internal step; the loop below takes two per iteration (k even, then odd), so that
-    // each knows where its random words are held
-    auto internal_step = [&](auto odd) {
+    const int lvl_int = tv.max_level - 1;   // a child below this level can be internal
+    // one internal step.  mode 0 / 1: an even / odd step k < 16, whose random words the
+    // wavefront holds (the first loop below takes them in pairs, so that each knows where
+    // its words are); mode 2: a step k >= 16, which computes them again
+    auto internal_step = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
         uint32_t xsel;
         float u;
-        pw.template step_p<decltype(odd)::value>(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        if constexpr (M == 2) pw.step_late(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        else pw.template step_held<M == 1>(k, ctr1, xsel, u);
         const uint32_t r = __umulhi(xsel, nT);
         const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);   // the block's aggregates and dipoles
         const Off toff = (Off)(uint32_t)blk * (Off)(TS * 4);    // its topology row
@@ -703,7 +707,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             const uint32_t excl = inc - cl;
             // (r < n_T, so exactly one slot holds it)
             const uint32_t hm = (uint32_t)__ballot((r - excl) < cl);
-            const uint32_t im = level + 1 < tv.max_level ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
+            const uint32_t im = level < lvl_int ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
             nonempty = (uint32_t)__ballot(cl != 0u);
             csel = __builtin_ctz(hm);
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
@@ -790,10 +794,11 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         }
         go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
     };
-    while (go) {
-        internal_step(std::false_type{});
-        if (go) internal_step(std::true_type{});
+    while (go && k < 16) {   // k is even here, so both steps are below 16
+        internal_step(std::integral_constant<int, 0>{});
+        if (go) internal_step(std::integral_constant<int, 1>{});
     }
+    while (go) internal_step(std::integral_constant<int, 2>{});
     if (actm != 0ull) {
         if (nT == 1u) {   // a single point: the walk is exact from here
             if (__builtin_amdgcn_inverse_ballot_w64(actm)) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
