@@ -879,7 +879,7 @@ __device__ __forceinline__ float wave_sum8(const float v[8])
 // so that the walk stays shared; each lane's swap is divided by the product
 // of the q's drawn (Eq. (7) with p(I in T) = prod q).  The child block is
 // scanned before the selection (its distances feed the scores).
-template <int K, bool TRACE>
+template <int K, bool TRACE, bool O64>
 __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, float qy, float qz, float r0,
                                                 const KParams& kp, bool valid, float inv_valid, uint32_t n_a,
                                                 uint32_t begin_a, int32_t blk_a, float4 agg_a, float t_a,
@@ -890,21 +890,23 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
     constexpr int D3 = 8;
     constexpr int TS = topo_stride(D3);
     constexpr float kLam = 0.125f;
+    using Off = typename TreeOff<O64>::T;   // byte offsets into the tree's arrays, as in wave_path
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     const int ln = threadIdx.x & 63;
     uint32_t nT = n_a, beginT = begin_a;
     int32_t blk = blk_a;
     int level = 1;
     float diamT = tv.diam0 * 0.5f;
-    bool act = valid;
-    uint64_t actm = __ballot(valid);   // lanes still walking, as a lane mask
+    uint64_t actm = __ballot(valid);   // lanes still walking, as a lane mask (a lane's flag is its bit)
+    const bool rr_eq5 = rr_mode == 0;
+    const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
     float tT = t_a, prr = 1.0f, psel = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
     for (int k = 0; actm != 0ull; ++k) {   // later steps leave by the roulette's vote
         if (nT == 1u) {
-            if (act) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+            if (__builtin_amdgcn_inverse_ballot_w64(actm)) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
             break;
         }
         uint32_t xsel;
@@ -921,10 +923,11 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         float4 g8[D3];            // the block's aggregates, kept for the swap
         float r2[D3];             // this lane's squared distances to them, shared by score and term
         if (internal) {
-            const float4* __restrict__ ba = tv.bagg + (int64_t)blk * D3;
-            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
-            const float* __restrict__ bs = tv.bspr + (int64_t)blk * D3;
-            const uint32_t* __restrict__ bt = tv.btopo + (int64_t)blk * TS;
+            const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);
+            const float4* __restrict__ ba = at_off(tv.bagg, boff);
+            const float4* __restrict__ bd = at_off(tv.bdip, boff);
+            const float* __restrict__ bs = at_off(tv.bspr, (Off)(uint32_t)blk * (Off)(D3 * 4));
+            const uint32_t* __restrict__ bt = at_off(tv.btopo, (Off)(uint32_t)blk * (Off)(TS * 4));
             // counts in lanes 0..7 (lanes 8..63 read the row's zero padding word)
             const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
             uint32_t inc = cl;
@@ -932,7 +935,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);
             inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);
             const uint32_t excl = inc - cl;
-            const uint64_t im = __ballot((int)cl > tv.leaf_size) & (level + 1 < tv.max_level ? ~0ull : 0ull);
+            const uint32_t im = level + 1 < tv.max_level ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
             nonempty = (uint32_t)__ballot(cl != 0u);
             // this lane's scores from the block (one batch of scalar loads); the terms of the
             // swap wait until the roulette has kept some lane
@@ -987,32 +990,27 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             qsel = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc), csel));
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
             nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
-            aggC = gld4(ba + csel);
-            if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
+            aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
+            if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
             beginC = beginT + preC;
-            blkC = (int32_t)gld(bt + D3) + __popcll(im & ((1ull << csel) - 1ull));
+            blkC = (int32_t)gld(bt + D3) + __popc(im & ((1u << csel) - 1u));
         } else {
             rleaf = __umulhi(xsel, nT);
-            aggC = gld4(tv.pts + beginT + rleaf);
-            if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + rleaf);
+            aggC = gld4(at_off(tv.pts, (Off)(beginT + rleaf) * (Off)16));
+            if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.pdip, (Off)(beginT + rleaf) * (Off)16));
             beginC = beginT + rleaf;
             qsel = frcp((float)nT);
         }
         // roulette (Eq. (5)); its offset and squared distance also give the selected child's
         // own term, bit for bit the value the swap's sum takes for it
-        float p, dC = 0.0f;
         const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
         const float r2C = norm2(cx, cy, cz);
-        if (rr_mode == 0) {
-            dC = fsqrt(r2C);
-            p = fminf(1.0f, vmax(diamT, dT) * frcp(2.0f * dC));
-        } else {
-            p = rr_mode == 1 ? 1.0f : 0.5f;
-        }
-        const bool lt = u < p;
-        const uint64_t contm = __ballot(lt) & actm;
-        const bool cont = act && lt;
-        if (act && !cont) {
+        const float dC = fsqrt(r2C);
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * frcp(2.0f * dC));
+        const float p = rr_eq5 ? p5 : rr_fixed;   // the roulette mode as a select
+        const uint64_t contm = __ballot(u < p) & actm;
+        const bool cont = __builtin_amdgcn_inverse_ballot_w64(contm);
+        if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
             flag = 0;
             end_b = (int32_t)beginT;
             end_l = level;
@@ -1023,7 +1021,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
         float sumc = tC;
         if (internal) {   // contribution swap over the non-empty children, Eq. (6)
-            const float4* __restrict__ bd = tv.bdip + (int64_t)blk * D3;
+            const float4* __restrict__ bd = at_off(tv.bdip, (Off)(uint32_t)blk * (Off)(D3 * 16));
             const uint32_t rest = nonempty & ~(1u << csel);
 #pragma unroll
             for (int c = 0; c < D3; ++c) {
@@ -1034,16 +1032,19 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         } else {   // leaf: its points are the virtual children
             for (uint32_t i = 0; i < nT; ++i) {
                 if (i == rleaf) continue;   // the selected point: its term opened the sum
-                const float4 g = gld4(tv.pts + beginT + i);
-                const float4 gd = (K == SBH_WINDING) ? gld4(tv.pdip + beginT + i) : zero4;
+                const Off po = (Off)(beginT + i) * (Off)16;
+                const float4 g = gld4(at_off(tv.pts, po));
+                const float4 gd = (K == SBH_WINDING) ? gld4(at_off(tv.pdip, po)) : zero4;
                 sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
             }
         }
-        if (cont) {
-            prr *= p;
-            acc += (sumc - tT) * frcp(psel * prr);
-            ++steps;
-            tT = tC;
+        {   // the lanes the roulette keeps take the step (selects, not a branch)
+            const float prr2 = prr * p;
+            const float acc2 = acc + (sumc - tT) * frcp(psel * prr2);
+            prr = cont ? prr2 : prr;
+            acc = cont ? acc2 : acc;
+            tT = cont ? tC : tT;
+            steps += cont ? 1 : 0;
         }
         psel *= qsel;
         if (!internal) {
@@ -1054,7 +1055,6 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
             }
             break;
         }
-        act = cont;
         actm = contm;
         dT = dC;
         nT = nC;
@@ -1138,8 +1138,9 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
             const uint32_t path = (uint32_t)(slot * a.samples + s);
             pw.need(path, stream, a.batch, a.key0, a.key1);
             if constexpr (TILE && D == 2)
-                fa += wave_path_tile<K, TRACE>(tv, qx, qy, qz, r0, kp, valid, inv_valid, n_a, begin_a, blk_a, agg_a,
-                                               cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
+                fa += wave_path_tile<K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, inv_valid, n_a, begin_a, blk_a,
+                                                    agg_a, cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode,
+                                                    &rec);
             else
                 fa += wave_path<D, K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw,
                                                   stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
@@ -1186,7 +1187,7 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
 }
 
 // the coherent walk with the tile-shared score proposal (d = 2)
-template <int K, bool TRACE>
+template <int K, bool TRACE, bool O64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave_tile(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
@@ -1199,7 +1200,7 @@ k_sbh_wave_tile(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhA
     }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile<2, K, TRACE, true, P>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+    sbh_wave_tile<2, K, TRACE, true, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // ---------------------------------------------------------------------------
@@ -1428,8 +1429,13 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
         const unsigned wblocks = (unsigned)((tiles + (4 / kWaveParts) - 1) / (4 / kWaveParts));
         if (e.tile_score) {
             if constexpr (D == 2) {
-                if (e.paths) k_sbh_wave_tile<K, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
-                else k_sbh_wave_tile<K, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                if (tv.wide) {
+                    if (e.paths) k_sbh_wave_tile<K, true, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                    else k_sbh_wave_tile<K, false, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                } else {
+                    if (e.paths) k_sbh_wave_tile<K, true, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                    else k_sbh_wave_tile<K, false, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+                }
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;

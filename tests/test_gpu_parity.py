@@ -124,7 +124,7 @@ def test_sbh_deterministic_and_launch_independent(G):
 
 @pytest.mark.parametrize("kernel,branching", [(P.POTENTIAL, 2), (P.WINDING, 2), (P.SMOOTHDIST, 4)])
 def test_sbh_wide_offsets_give_the_same_walk(kernel, branching, monkeypatch):
-    """The coherent walk and Barnes-Hut take 32-bit byte offsets into trees below 4 GiB and
+    """The coherent walks and Barnes-Hut take 32-bit byte offsets into trees below 4 GiB and
     64-bit ones beyond; forcing the 64-bit form on a small tree must change no value and no
     path."""
     src, nrm, w = surface(20000, seed=33)
@@ -137,7 +137,10 @@ def test_sbh_wide_offsets_give_the_same_walk(kernel, branching, monkeypatch):
         out = P.sbh_eval(gt, q, kernel, samples=2, seed=5, group=64, paths=paths, alpha=20.0)
         plain = P.sbh_eval(gt, q, kernel, samples=2, seed=5, group=64, alpha=20.0)
         bh = P.sbh_eval(gt, q, kernel, beta=0.7, samples=0, alpha=20.0)   # Barnes-Hut takes the same offsets
-        return host(out), host(paths), host(plain), host(bh)
+        res = [host(out), host(paths), host(plain), host(bh)]
+        if branching == 2:   # and the tile-shared score proposal's walk
+            res.append(host(P.sbh_eval(gt, q, kernel, samples=1, seed=5, group=64, alpha=20.0, proposal=3)))
+        return res
 
     a = run()
     monkeypatch.setenv("SBH_FORCE_WIDE_OFFSETS", "1")
