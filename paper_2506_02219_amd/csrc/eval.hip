@@ -662,9 +662,13 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // rather than a branch)
     const bool rr_eq5 = rr_mode == 0;
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    // One reciprocal square root gives both |c - q| and 1 / (D |c - q|).  At |c - q| = 0
+    // the distance is NaN, which the next step's max ignores (v_max returns the other
+    // operand), and p = min(1, inf) = 1 as Eq. (5)'s limit.
     auto roulette = [&](float r2C, float& dC) -> float {
-        dC = fsqrt(r2C);
-        const float p5 = fminf(1.0f, vmax(diamT, dT) * frcp((float)D * dC));
+        const float ic = __builtin_amdgcn_rsqf(r2C);
+        dC = r2C * ic;
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
         return rr_eq5 ? p5 : rr_fixed;
     };
     int k = 0;
@@ -1005,8 +1009,9 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         // own term, bit for bit the value the swap's sum takes for it
         const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
         const float r2C = norm2(cx, cy, cz);
-        const float dC = fsqrt(r2C);
-        const float p5 = fminf(1.0f, vmax(diamT, dT) * frcp(2.0f * dC));
+        const float ic = __builtin_amdgcn_rsqf(r2C);   // |c - q| and 1 / (2 |c - q|) from one rsq, as in wave_path
+        const float dC = r2C * ic;
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * (0.5f * ic));
         const float p = rr_eq5 ? p5 : rr_fixed;   // the roulette mode as a select
         const uint64_t contm = __ballot(u < p) & actm;
         const bool cont = __builtin_amdgcn_inverse_ballot_w64(contm);
