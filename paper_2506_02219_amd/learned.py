@@ -27,7 +27,7 @@ OFF_W1, OFF_B1, OFF_W2, OFF_B2, OFF_W3, OFF_B3 = 0, 256, 288, 1312, 1344, 1600
 
 def init_params(seed: int, device="cuda") -> torch.Tensor:
     """Uniform fan-in initialisation of the two hidden layers; output layer zero,
-    so that the untrained network is exactly the uniform path index."""
+    so that the untrained network is exactly the score proposal (logits 16 f)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     p = np.zeros(MLP_NPARAM, np.float32)
     p[OFF_W1:OFF_B1] = rng.uniform(-1, 1, 256) / np.sqrt(8.0)

@@ -40,7 +40,7 @@ import torch
 import oracle
 import paper_2506_02219_amd as P
 import workloads as W
-from gpu_helpers import DEV, NEAR_TIE, T, build_both, check_sbh, compare_trees, host
+from gpu_helpers import DEV, NEAR_TIE, T, build_both, check_sbh, compare_trees, fp64_reference, host
 
 pytestmark = pytest.mark.gpu
 
@@ -211,6 +211,50 @@ def test_training_lowers_the_loss_on_real_rows():
     print(dict(before=before, after=after))
     assert after < before - 1e-3, (before, after)
     assert np.all(np.isfinite(host(losses)))
+
+
+def test_trained_network_against_the_score_proposal():
+    """What training buys: a network trained on rows from three surfaces, kept at the
+    chunk with the lowest validation error on a fourth (the untrained network, which is
+    the score proposal, included), evaluated on a fifth.  Model selection may never
+    return a network that validates worse than the score proposal; on the held-out
+    surface it stays within 10% of the score proposal's error, and both importance
+    proposals beat the uniform path index.  The measured errors are printed."""
+    import paper_2506_02219_amd.learned as L
+
+    def surface_case(seed):
+        pts, nrm, w, _ = W.star_surface(1 << 14, seed, level=5)
+        q = np.random.Generator(np.random.PCG64(seed + 1000)).uniform(-1.3, 1.3, (2048, 3)).astype(np.float32)
+        q[:, 2] *= 0.25   # a slab around the surface's equator
+        gt = P.sbh_build(T(pts.astype(np.float32)), T(w.astype(np.float32)))
+        ref = fp64_reference(pts.astype(np.float32), w.astype(np.float32), None, q, P.POTENTIAL)
+        return gt, T(q), ref
+
+    def med_err(gt, q, ref, proposal, params=None, seeds=(1, 2, 3)):
+        errs = []
+        for s in seeds:
+            v = host(P.sbh_eval(gt, q, P.POTENTIAL, samples=1, seed=s, proposal=proposal, mlp=params))
+            errs.append(np.median(np.abs(v - ref) / np.abs(ref)))
+        return float(np.mean(errs))
+
+    rows = []
+    for seed in (61, 62, 63):
+        gt, q, _ = surface_case(seed)
+        rows.append(L.training_rows(gt, q, P.POTENTIAL, seed=seed))
+    X = torch.cat([r[0] for r in rows]); Tg = torch.cat([r[1] for r in rows]); Cn = torch.cat([r[2] for r in rows])
+    gv, qv, rv = surface_case(64)
+    gh, qh, rh = surface_case(65)
+    p0 = L.init_params(0)
+    best, hist = L.train_selected(p0.clone(), X, Tg, Cn, steps=400, chunks=4, batch_rows=2048, lr=2e-3,
+                                  validate=lambda prm: med_err(gv, qv, rv, 1, prm, seeds=(7,)))
+    assert hist[0][1] >= min(v for _, v in hist)                      # selection keeps the best
+    assert med_err(gv, qv, rv, 1, best, seeds=(7,)) <= hist[0][1]      # never worse than untrained
+    e_uni = med_err(gh, qh, rh, 0)
+    e_score = med_err(gh, qh, rh, 2)
+    e_net = med_err(gh, qh, rh, 1, best)
+    print(dict(validation=hist, uniform=e_uni, score=e_score, trained=e_net))
+    assert e_net <= 1.1 * e_score, (e_net, e_score)
+    assert e_score < e_uni and e_net < e_uni, (e_uni, e_score, e_net)
 
 
 @pytest.mark.parametrize("samples,group", [(1, 1), (4, 1), (2, 7)])
