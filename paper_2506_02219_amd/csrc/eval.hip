@@ -672,8 +672,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         return rr_eq5 ? p5 : rr_fixed;
     };
     int k = 0;
-    // internal nodes: the walk leaves the loop at a leaf, or when the roulette has
-    // stopped every lane (actm then 0); the loop has this one exit
+    // internal nodes: the walk leaves the loops below at a leaf, or when the roulette
+    // has stopped every lane (actm then 0); each loop's only exit is its condition
     // (leaf_size >= 1, so an internal node holds at least two points)
     bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
     const int lvl_int = tv.max_level - 1;   // a child below this level can be internal
