@@ -41,6 +41,7 @@ def lib():
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
         L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, i64, P, P, P, P, P, i32]
         L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32, P, i32]
+        L.orc_term_sens.argtypes = [i32, f64, f64, P, f64, P, P, P]
         L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
         L.orc_mlp_nparam.restype = i32
         L.orc_f16_round.argtypes = [C.c_float]
@@ -82,6 +83,14 @@ def brute(sources, weights, normals, queries, kernel, eps=1e-3, alpha=100.0, thr
     out = np.zeros(q.shape[0], dtype=np.float64)
     lib().orc_brute(_p(s), _p(w), _p(nrm), s.shape[0], _p(q), q.shape[0], kernel, eps, alpha, _p(out), threads)
     return out
+
+
+def term_sens(kernel, p, m, dip, q, eps=1e-3, alpha=100.0):
+    """One term f(p, q) (weight m, dipole dip) and its centre sensitivity |grad_p f| |p|."""
+    pp = np.ascontiguousarray(p, np.float64); dd = np.ascontiguousarray(dip, np.float64)
+    qq = np.ascontiguousarray(q, np.float64); out = np.zeros(2)
+    lib().orc_term_sens(kernel, eps, alpha, _p(pp), float(m), _p(dd), _p(qq), _p(out))
+    return float(out[0]), float(out[1])
 
 
 def smooth_distance(F, alpha=100.0):

@@ -415,18 +415,22 @@ static double point_term(const orc_tree* t, const kparams* kp, int64_t s, const 
     return term(kp, &t->pxyz[3 * s], t->pw[s], &t->pdip[3 * s], q);
 }
 
-/* Sensitivity of a node term to a relative perturbation of its centre of
- * mass of one unit (|df/dp| * |com|).  A float32 tree stores every centre
- * with an error of a few 2^-24 |com|, so this bounds how far a float32
- * evaluation of the same estimate can move for reasons other than rounding
- * in the evaluation itself.  Diagnostic only; it never enters an estimate. */
-static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+/* Sensitivity of a term to its centre: |grad_p f(p, q)| * |p|, where the
+ * gradient is taken with respect to the term's position p (a source point or
+ * a node's centre of mass).  A float32 tree stores every centre with an error
+ * of a few 2^-24 |p|, so this bounds how far a float32 evaluation of the same
+ * estimate can move for reasons other than rounding in the evaluation
+ * itself.  Potential and smooth distance: the exact gradient norm
+ * (m r / (r^2 + eps^2)^(3/2) and alpha m e^(-alpha r)).  Winding number: the
+ * gradient of dip.(p - q) / (4 pi r^3) is (dip - 3 (dip.u) u) / (4 pi r^3)
+ * with u the unit offset, whose norm lies between |dip| / (4 pi r^3) and
+ * 2 |dip| / (4 pi r^3); the bound 4 |dip| / (4 pi r^3) is used.
+ * Diagnostic only; it never enters an estimate. */
+static double sens_at(const kparams* kp, const double p[3], double m, const double dip[3], const double q[3])
 {
-    const double* p = &t->com[3 * i];
     double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
     double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
     double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-    double m = t->mass[i];
     switch (kp->kernel) {
     case ORC_POTENTIAL: {
         double s2 = r2 + kp->eps * kp->eps;
@@ -434,8 +438,7 @@ static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const d
     }
     case ORC_WINDING: {
         if (r2 == 0.0) return 0.0;
-        const double* d = &t->dip[3 * i];
-        double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double dn = sqrt(dip[0] * dip[0] + dip[1] * dip[1] + dip[2] * dip[2]);
         return dn / (ORC_PI * r2 * r) * pn;
     }
     case ORC_SMOOTHDIST:
@@ -443,6 +446,21 @@ static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const d
     default:
         return 0.0;
     }
+}
+
+static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+{
+    return sens_at(kp, &t->com[3 * i], t->mass[i], &t->dip[3 * i], q);
+}
+
+/* One term and its sensitivity at an arbitrary (p, m, dip, q): out = {f, sens}
+ * (for the tests that pin the sensitivity against finite differences of f). */
+void orc_term_sens(int kernel, double eps, double alpha, const double p[3], double m, const double dip[3],
+                   const double q[3], double out[2])
+{
+    kparams kp = {kernel, eps, alpha};
+    out[0] = term(&kp, p, m, dip, q);
+    out[1] = sens_at(&kp, p, m, dip, q);
 }
 
 static double dist2(const double a[3], const double q[3])
