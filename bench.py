@@ -45,6 +45,12 @@ FP32_PEAK_TFLOPS = 157.3
 # float32 operations per kernel term: differences, squared distance, the
 # kernel itself, the weight; transcendental calls counted as one operation
 TERM_FLOPS = {0: 11, 1: 17, 2: 14}
+# the roulette of one attempted step: offset and squared distance to the selected child (6), one
+# reciprocal square root, the max, two products and the min of Eq. (5)
+ROULETTE_FLOPS = 11
+# the weight update of one accepted step: the swap's difference, p product, 1 / (n_T prod p) and
+# the accumulation
+STEP_FLOPS = 6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -61,7 +67,7 @@ def parse():
     ap.add_argument("--err-sample", type=int, default=16384)
     ap.add_argument("--no-bh", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched evaluation")
@@ -124,6 +130,16 @@ def rel_errors(v, ref, kernel, alpha=100.0):
         scale = np.abs(ref)
     e = np.abs(v - ref) / scale
     return np.where(np.isnan(e), np.inf, e)
+
+
+def git_sha():
+    """HEAD of the repository when it is a git checkout (the benchmark box gets a copy without .git)."""
+    import subprocess
+    try:
+        return subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True,
+                              timeout=10).stdout.strip() or None
+    except Exception:
+        return None
 
 
 def csrc_hash():
@@ -246,7 +262,15 @@ def main():
     exp = tree.export()
 
     def work_of(group):
-        """Bytes and flops the estimator must read / compute for one launch (active lanes only)."""
+        """Algorithmic bytes and flops of one launch, from the kernel's own path records.
+
+        A path's attempted steps are its accepted ones, plus the step its roulette stopped (flag 0).
+        Every attempted step costs the roulette of Eq. (5): the selected child's distance and p
+        (ROULETTE_FLOPS), reading the child counts (d^3 + 1 words) and the selected child's
+        aggregate.  An accepted step at an internal node T adds the swap of Eq. (6): one term per
+        non-empty child of T and the weight update (STEP_FLOPS), reading the rest of T's child
+        block; an accepted step at a leaf adds one term per point of the leaf.  A roulette stop
+        does no swap.  Per query: the subdomain control variates and the final sums."""
         d3 = d ** 3
         paths = torch.empty((N, d3, S, 4), dtype=torch.int32, device=dev)
         P.sbh_eval(tree, qry, kernel, samples=S, seed=0, group=group, out=out, paths=paths)
@@ -260,64 +284,67 @@ def main():
         key_nodes = exp["level"].astype(np.int64) * (1 << 32) + exp["begin"].astype(np.int64)
         order = np.argsort(key_nodes)
         ks = key_nodes[order]
-        end_key = rec[:, 1].astype(np.int64) * (1 << 32) + rec[:, 0].astype(np.int64)
-        pos = np.minimum(np.searchsorted(ks, end_key), len(ks) - 1)
-        found = ks[pos] == end_key
-        end_count = np.where(found, exp["count"][order][pos], 1).astype(np.int64)
-        end_internal = found & (end_count > 8) & (rec[:, 1] < tree.max_level)
-        wind = kernel == 1
-        pt_bytes = 16 * (2 if wind else 1)
-        # accepted steps read child blocks, except the last one of a path that moved onto a virtual point
-        # (flag 2), which read its leaf's points; a roulette stop (flag 0) read the block or the leaf
-        # points of the node where it stopped
-        internal_att = (steps_acc - (flags == 2)) + ((flags == 0) & end_internal)
-        rr_leaf_pts = np.where((flags == 0) & ~end_internal & (end_count > 1), end_count, 0)
-        vp = flags == 2
-        leaf_key = (rec[vp, 1].astype(np.int64) - 1) * (1 << 32) + rec[vp, 0].astype(np.int64)
-        lpos = np.searchsorted(ks, leaf_key, side="right") - 1
-        vp_pts = exp["count"][order][lpos].astype(np.int64)
-        leaf_pts = rr_leaf_pts.sum() + vp_pts.sum()
-        leaf_att = int((rr_leaf_pts > 0).sum() + vp.sum())
-        n_int_att = int(internal_att.sum())
-        # only non-empty children are work: the number of children of every internal node a path
-        # scanned, from the per-node running sum of child counts along the ancestor chain
         parent = exp["parent"].astype(np.int64)
         nch = exp["nchild"].astype(np.int64)
         lev = exp["level"].astype(np.int64)
+        cnt = exp["count"].astype(np.int64)
+        # cumc[v]: non-empty children summed over v and its ancestors below the root
         cumc = np.zeros(len(nch), np.int64)
         for L in range(1, int(lev.max()) + 1):   # breadth-first: parents come first
             m = lev == L
             cumc[m] = nch[m] + cumc[parent[m]]
-        end_node = order[pos]
-        last = np.where((flags == 0) & end_internal, end_node, parent[end_node])   # last internal node scanned
-        if vp.any():
-            last[vp] = parent[order[lpos]]
-        last = np.where(found | vp, last, 0)
-        n_terms_int = int(np.where(lev[last] >= 1, cumc[last], 0).sum())
-        bytes_q = 12 + 4 + int(nch[0]) * 16 * (2 if wind else 1) + d3 * 4
-        alg_bytes = float(n_terms_int * 16 * (2 if wind else 1) + n_int_att * (d3 * 4 + 4) + leaf_pts * pt_bytes
-                          + N * bytes_q)
+        cumc[lev == 0] = 0
+        vp = flags == 2
+        # the node a path ended at (flags 0 and 1), or the leaf whose point it moved onto (flag 2)
+        end_lev = rec[:, 1].astype(np.int64) - vp
+        end_key = end_lev * (1 << 32) + rec[:, 0].astype(np.int64)
+        pos = np.searchsorted(ks, end_key, side="right") - 1   # flag 2: the leaf holding the point
+        end_node = order[np.clip(pos, 0, len(ks) - 1)]
+        assert np.all(lev[end_node] == end_lev) and np.all(exp["begin"][end_node] <= rec[:, 0])
+        # internal nodes whose swaps were taken: every ancestor of the end node below the root
+        # (a leaf's own swap, flag 2, is over its points)
+        par = parent[end_node]
+        swap_terms = np.where(par > 0, cumc[np.maximum(par, 0)], 0)
+        leaf_pts = np.where(vp, cnt[end_node], 0)
+        attempted = steps_acc + (flags == 0)
+        wind = kernel == 1
+        blk_row = 16 * (2 if wind else 1)
         tf = TERM_FLOPS[kernel]
-        alg_flops = float(n_terms_int * (tf + 1) + n_int_att * 25 + leaf_pts * (tf + 1) + leaf_att * 25
-                          + len(rec) * tf + N * (int(nch[0]) + 4))
+        n_terms = int(swap_terms.sum() + leaf_pts.sum())
+        n_att = int(attempted.sum())
+        n_acc = int(steps_acc.sum())
+        n_int_acc = int((steps_acc - vp).sum())
+        alg_flops = float(n_terms * (tf + 1) + n_acc * STEP_FLOPS + n_att * ROULETTE_FLOPS
+                          + N * (int(nch[0]) * (tf + 1) + 4))
+        alg_bytes = float(n_att * ((d3 + 1) * 4 + blk_row) + (n_terms - n_int_acc - int(vp.sum())) * blk_row
+                          + N * (12 + 4 + int(nch[0]) * blk_row + d3 * 4))
         return dict(alg_bytes=alg_bytes, alg_flops=alg_flops, mean_steps=float(steps_acc.mean()),
-                    attempted_steps_per_path=float((n_int_att + leaf_att) / len(rec)),
-                    children_per_internal_step=n_terms_int / max(n_int_att, 1))
+                    attempted_steps_per_path=float(n_att / len(rec)),
+                    children_per_accepted_internal_step=float(swap_terms.sum() / max(n_int_acc, 1)),
+                    paths=int(len(rec)), terms=n_terms, accepted=n_acc, attempted=n_att)
 
     wk = work_of(args.group)
     mean_steps = wk["mean_steps"]
+    derivation = {
+        "paths_per_launch": wk["paths"], "accepted_steps_per_path": wk["mean_steps"],
+        "attempted_steps_per_path": wk["attempted_steps_per_path"],
+        "children_per_accepted_internal_step": wk["children_per_accepted_internal_step"],
+        "terms_per_launch": wk["terms"], "term_flops": TERM_FLOPS[kernel] + 1, "roulette_flops": ROULETTE_FLOPS,
+        "step_flops": STEP_FLOPS,
+        "flops": "terms x term_flops + accepted x step_flops + attempted x roulette_flops "
+                 "+ queries x (subdomains x term_flops + 4)"}
     if args.group % 64 == 0:
         tflops = wk["alg_flops"] / (ms_per_step * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
                 "alg_flops_per_launch": wk["alg_flops"], "kernel": "k_sbh_wave",
                 # the build has no packed fp32 instructions: half the peak is what it can issue
-                "frac_of_non_packed_fp32": tflops / (FP32_PEAK_TFLOPS / 2)}
+                "frac_of_non_packed_fp32": tflops / (FP32_PEAK_TFLOPS / 2), "derivation": derivation}
     else:
         achieved_gbs = wk["alg_bytes"] / (ms_per_step * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                "alg_bytes_per_launch": wk["alg_bytes"], "kernel": "k_sbh_pool"}
+                "alg_bytes_per_launch": wk["alg_bytes"], "kernel": "k_sbh_pool", "derivation": derivation}
 
     # --- the other stream mode (per-query streams vs shared per wavefront), same tree and queries
     other = None
@@ -564,9 +591,16 @@ def main():
                    threads=threads)
         cpu_s = time.perf_counter() - tc
         nsamp_total = nsamp * reps
+        # the same oracle on one thread, on a prefix of the same queries (about a quarter of the time)
+        n1 = int(min(N, max(256, args.cpu_seconds / 4 / max(per_q * threads, 1e-9))))
+        tc = time.perf_counter()
+        ot.sbh(qry_np[:n1], kernel, samples=S, seed=0, group=args.group, index=np.arange(n1), threads=1)
+        one_s = time.perf_counter() - tc
         cpu = dict(value=nsamp_total / cpu_s, unit="queries/s", cores=threads, kind="oracle",
                    sample=f"first {nsamp} of {N} queries x {reps} repetitions, same tree, seed and streams, "
-                          f"{cpu_s:.1f} s")
+                          f"{cpu_s:.1f} s",
+                   single_thread=dict(value=n1 / one_s, unit="queries/s", cores=1,
+                                      sample=f"first {n1} of {N} queries, {one_s:.1f} s"))
 
     prof = os.path.join(ROOT, "profiles", f"pmc_sbh_eval_{args.config}_d{args.branching}_g{args.group}.json")
     if os.path.exists(prof):
@@ -610,6 +644,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "generate_s": gen_s,
+        "git_sha": git_sha(),
+        "csrc_sha256_16": csrc_hash(),
     }
     print(json.dumps(line))
 

@@ -107,6 +107,33 @@ typedef struct sbh_tree_desc {      /* host copy of a tree's sizes */
 #define SBH_MLP_NPARAM 1608
 #define SBH_MLP_GRAD_SIZE 1610
 
+/*
+ * Device memory.  Every device allocation of the library goes through one
+ * allocator pair: a tree's arrays and the temporaries of its build, the
+ * proposal network's workspaces and a batch plan's tables.
+ *   alloc(bytes, stream, ctx) returns device memory of at least `bytes`
+ *     bytes, 256-byte aligned, usable by work enqueued on `stream` from the
+ *     moment of the call on (stream order), or NULL when it cannot; the
+ *     library then releases what the failed call had taken, enqueues nothing
+ *     more and returns SBH_ENOMEM.
+ *   free(ptr, bytes, stream, ctx) returns an allocation; work that reads it
+ *     has been enqueued on `stream` before the call (or has completed when
+ *     `stream` is 0 and the library has waited for the device first).
+ * The default (both NULL) is hipMallocAsync / hipFreeAsync on the call's
+ * stream.  A PyTorch caller can pass its caching allocator here.
+ */
+typedef void* (*sbh_alloc_fn)(size_t bytes, hipStream_t stream, void* ctx);
+typedef void (*sbh_free_fn)(void* ptr, size_t bytes, hipStream_t stream, void* ctx);
+
+/*
+ * sbh_set_allocator - set the allocator of later allocations (process-wide).
+ * Objects keep the allocator they were created with and release through it,
+ * so a change does not affect trees or plans that exist.  Both NULL restores
+ * the default.  Call it while no other thread is inside the library.
+ * Errors: SBH_EINVAL (exactly one of alloc and free NULL).
+ */
+sbh_status sbh_set_allocator(sbh_alloc_fn alloc, sbh_free_fn free, void* ctx);
+
 /* Fill option structs with the defaults documented above. */
 void sbh_build_opts_default(sbh_build_opts* opts /*host*/);
 void sbh_eval_opts_default(sbh_eval_opts* opts /*host*/);
@@ -352,6 +379,14 @@ sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count,
 
 /* sbh_free - release a tree (waits for the device to finish using it). NULL is a no-op. */
 sbh_status sbh_free(sbh_tree* tree);
+
+/*
+ * sbh_free_async - release a tree in stream order, without waiting: its
+ * memory is handed back to its allocator on `stream`.  Every use of the tree
+ * must have been enqueued on `stream`, or ordered before it by the caller
+ * (events), before this call.  NULL is a no-op.
+ */
+sbh_status sbh_free_async(sbh_tree* tree, hipStream_t stream);
 
 /* Static text for a status code. */
 const char* sbh_status_string(sbh_status status);

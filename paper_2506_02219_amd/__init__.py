@@ -96,6 +96,10 @@ def lib():
         L.sbh_batch_free.restype = i32
         L.sbh_free.argtypes = [P]
         L.sbh_free.restype = i32
+        L.sbh_free_async.argtypes = [P, P]
+        L.sbh_free_async.restype = i32
+        L.sbh_set_allocator.argtypes = [P, P, P]
+        L.sbh_set_allocator.restype = i32
         L.sbh_status_string.argtypes = [i32]
         L.sbh_status_string.restype = C.c_char_p
         L.sbh_last_error.argtypes = []
@@ -173,11 +177,66 @@ class Tree:
             lib().sbh_free(self._h)
             self._h = None
 
+    def free_async(self, stream=None):
+        """Stream-ordered release (sbh_free_async) on `stream` (default: the current stream)."""
+        if self._h:
+            _check("sbh_free_async", lib().sbh_free_async(self._h, _stream(stream)))
+            self._h = None
+
     def __del__(self):
         try:
             self.free()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------- allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_alloc_keep = None   # the installed callbacks (kept alive while installed)
+
+
+def sbh_set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through alloc(bytes, stream) -> int pointer (0 on
+    failure) and free(ptr, bytes, stream) (sbh_set_allocator); both None restores the default.
+    `stream` is the raw hipStream_t handle as an int (0 for the null stream)."""
+    global _alloc_keep
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check("sbh_set_allocator", lib().sbh_set_allocator(None, None, None))
+        _alloc_keep = None
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0)) or 0)
+        except Exception:
+            return 0
+
+    def _f(ptr, nbytes, stream, ctx):
+        try:
+            free(int(ptr), int(nbytes), int(stream or 0))
+        except Exception:
+            pass
+
+    keep = (ALLOC_FN(_a), FREE_FN(_f))
+    _check("sbh_set_allocator", lib().sbh_set_allocator(C.cast(keep[0], C.c_void_p), C.cast(keep[1], C.c_void_p),
+                                                        None))
+    _alloc_keep = keep
+
+
+def use_torch_allocator():
+    """Take device memory from PyTorch's caching allocator (on the stream of each call)."""
+    import torch
+
+    def _alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream or None)
+
+    def _free(ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    sbh_set_allocator(_alloc, _free)
 
 
 def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_level=0, stream=None) -> Tree:

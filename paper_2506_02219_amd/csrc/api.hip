@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,11 +40,14 @@ sbh_status hip_fail(hipError_t e, const char* where)
     return fail(s, "%s: %s", where, hipGetErrorString(e));
 }
 
-void free_impl(sbh::sbh_tree_impl* t)
+void free_impl(sbh::sbh_tree_impl* t, hipStream_t s)
 {
-    for (void* p : t->slab)
-        if (p) (void)hipFree(p);
+    for (int i = 0; i < 3; ++i)
+        if (t->slab[i]) sbh::dev_free(t->mem, t->slab[i], t->slab_bytes[i], s);
 }
+
+std::mutex g_alloc_mu;
+sbh::Allocator g_alloc{nullptr, nullptr, nullptr};
 
 sbh_status check_kernel(int kernel)
 {
@@ -67,7 +71,43 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
 
 }  // namespace
 
+namespace sbh {
+
+Allocator allocator_current()
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+hipError_t dev_alloc(const Allocator& a, void** p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (!a.alloc) return hipMallocAsync(p, bytes, s);
+    *p = a.alloc(bytes, s, a.ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(const Allocator& a, void* p, size_t bytes, hipStream_t s)
+{
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    if (!a.alloc) (void)hipFreeAsync(p, s);
+    else a.free(p, bytes, s, a.ctx);
+}
+
+}  // namespace sbh
+
 extern "C" {
+
+sbh_status sbh_set_allocator(sbh_alloc_fn alloc, sbh_free_fn free, void* ctx)
+{
+    if ((alloc == nullptr) != (free == nullptr))
+        return fail(SBH_EINVAL, "sbh_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = sbh::Allocator{alloc, free, alloc ? ctx : nullptr};
+    return SBH_OK;
+}
 
 void sbh_build_opts_default(sbh_build_opts* o)
 {
@@ -126,12 +166,13 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     if (!t) return fail(SBH_ENOMEM, "sbh_build: host allocation failed");
     std::memset(&t->impl, 0, sizeof(t->impl));
     (void)hipGetDevice(&t->impl.device);
+    t->impl.mem = sbh::allocator_current();
     std::string msg;
     const sbh_status st =
         sbh::build_tree_impl(sources, weights, normals, n, o.branching, o.leaf_size, o.max_level, stream, &t->impl, &msg);
     if (st != SBH_OK) {
         (void)hipStreamSynchronize(stream);
-        free_impl(&t->impl);
+        free_impl(&t->impl, stream);
         delete t;
         return fail(st, "sbh_build: %s", msg.c_str());
     }
@@ -256,7 +297,15 @@ sbh_status sbh_free(sbh_tree* tree)
 {
     if (!tree) return SBH_OK;
     (void)hipDeviceSynchronize();
-    free_impl(&tree->impl);
+    free_impl(&tree->impl, 0);
+    delete tree;
+    return SBH_OK;
+}
+
+sbh_status sbh_free_async(sbh_tree* tree, hipStream_t stream)
+{
+    if (!tree) return SBH_OK;
+    free_impl(&tree->impl, stream);
     delete tree;
     return SBH_OK;
 }
@@ -312,12 +361,13 @@ sbh_status sbh_mlp_loss_grad(const float* params, const float* features, const f
     if (!params || !features || !targets || !counts || !grad)
         return fail(SBH_EINVAL, "sbh_mlp_loss_grad: NULL argument");
     float* partial = nullptr;
-    hipError_t e = hipMallocAsync((void**)&partial, sbh::mlp_partial_floats(n) * sizeof(float), stream);
+    const sbh::Allocator mem = sbh::allocator_current();
+    const size_t wbytes = sbh::mlp_partial_floats(n) * sizeof(float);
+    hipError_t e = sbh::dev_alloc(mem, (void**)&partial, wbytes, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_loss_grad: workspace");
     e = sbh::launch_mlp_grad(params, features, targets, counts, n, 0, n, partial, grad, stream);
-    const hipError_t f = hipFreeAsync(partial, stream);
+    sbh::dev_free(mem, partial, wbytes, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_loss_grad: kernel launch");
-    if (f != hipSuccess) return hip_fail(f, "sbh_mlp_loss_grad: workspace release");
     return SBH_OK;
 }
 
@@ -335,7 +385,9 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
     const int64_t b = batch_rows < n ? batch_rows : n;
     float* work = nullptr;
     const size_t pf = sbh::mlp_partial_floats(b);
-    hipError_t e = hipMallocAsync((void**)&work, (pf + 1616) * sizeof(float), stream);
+    const sbh::Allocator mem = sbh::allocator_current();
+    const size_t wbytes = (pf + 1616) * sizeof(float);
+    hipError_t e = sbh::dev_alloc(mem, (void**)&work, wbytes, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: workspace");
     float* grad = work + pf;
     for (int32_t s = 0; s < steps && e == hipSuccess; ++s) {
@@ -345,9 +397,8 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
         if (e == hipSuccess)
             e = sbh::launch_mlp_adam(params, adam_state, grad, lr, step0 + s, losses ? losses + s : nullptr, stream);
     }
-    const hipError_t f = hipFreeAsync(work, stream);
+    sbh::dev_free(mem, work, wbytes, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: kernel launch");
-    if (f != hipSuccess) return hip_fail(f, "sbh_mlp_train: workspace release");
     return SBH_OK;
 }
 
@@ -358,6 +409,7 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
 // ---------------------------------------------------------------------------
 struct sbh_batch {
     int device = 0;
+    sbh::Allocator mem{};                 // the allocator of the plan's tables
     int samples = 1;
     sbh_eval_opts opts{};
     std::vector<sbh::BatchItem> clouds;   // as given
@@ -380,16 +432,17 @@ struct sbh_batch {
 
 namespace {
 
+// (the caller has waited for the device)
 void batch_release(sbh_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (int g = 0; g < sbh::kBatchLaunchGroups; ++g) {
-        if (b->d_items[g]) (void)hipFree(b->d_items[g]);
-        if (b->d_wg[g]) (void)hipFree(b->d_wg[g]);
+        sbh::dev_free(b->mem, b->d_items[g], b->clouds.size() * sizeof(sbh::BatchItem), 0);
+        sbh::dev_free(b->mem, b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2), 0);
     }
-    if (b->d_state) (void)hipFree(b->d_state);
+    sbh::dev_free(b->mem, b->d_state, sbh::kBatchGroups * sizeof(sbh::BatchState), 0);
 }
 
 // Device descriptors and workgroup tables for a configuration: clouds split by
@@ -498,6 +551,7 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     if (!b) return fail(SBH_ENOMEM, "sbh_batch_create: host allocation");
     b->samples = samples;
     b->opts = o;
+    b->mem = sbh::allocator_current();
     (void)hipGetDevice(&b->device);
     for (int32_t i = 0; i < count; ++i) {
         const sbh::sbh_tree_impl* t = &items[i].tree->impl;
@@ -519,12 +573,17 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         e = hipDeviceGetAttribute(&b->lds_per_wg_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);
     if (e == hipSuccess) e = sbh::batch_static_lds(&b->lds_static);
     for (int g = 0; g < sbh::kBatchLaunchGroups && e == hipSuccess; ++g) {
-        e = hipMalloc((void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem));
-        if (e == hipSuccess && b->tiles[g] > 0) e = hipMalloc((void**)&b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2));
+        e = sbh::dev_alloc(b->mem, (void**)&b->d_items[g], (size_t)count * sizeof(sbh::BatchItem), stream);
+        if (e == hipSuccess && b->tiles[g] > 0)
+            e = sbh::dev_alloc(b->mem, (void**)&b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2), stream);
     }
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, sbh::kBatchGroups * sizeof(sbh::BatchState));
+    if (e == hipSuccess)
+        e = sbh::dev_alloc(b->mem, (void**)&b->d_state, sbh::kBatchGroups * sizeof(sbh::BatchState), stream);
+    // the tables are written by synchronous copies and read on other streams (graph replays)
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        (void)hipDeviceSynchronize();
         batch_release(b);
         delete b;
         return hip_fail(e, "sbh_batch_create: allocation");
@@ -589,7 +648,7 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
         if (e == hipSuccess && !b->begin_node) e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) {
-        (void)hipStreamSynchronize(stream);
+        (void)hipDeviceSynchronize();
         batch_release(b);
         delete b;
         return hip_fail(e, "sbh_batch_create: tuning or graph capture");

@@ -90,8 +90,11 @@ __global__ void __launch_bounds__(kBruteThreads) k_brute(const float* __restrict
         __syncthreads();
     }
     if (valid) {
-        if constexpr (K == SBH_SMOOTHDIST) out[j] = rmin - log(total) / alpha;
-        else out[j] = total;
+        R v = total;
+        if constexpr (K == SBH_SMOOTHDIST) v = rmin - log(total) / alpha;
+        // a query with a non-finite coordinate has no defined value
+        const bool fin = __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
+        out[j] = fin ? v : R(NAN);
     }
 }
 

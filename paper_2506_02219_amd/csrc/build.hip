@@ -570,14 +570,19 @@ struct Carver {
 };
 
 // Temporaries of one build: a bump allocator over a few large chunks.  A
-// build takes some two hundred temporaries, and one hipMalloc / hipFree pair
-// each (hipFree waits for the device) cost several times the build's kernels.
+// build takes some two hundred temporaries, and one allocation each cost
+// several times the build's kernels.  Chunks come from the library's
+// allocator on the build's stream and go back to it, in stream order, when
+// the build ends.
 struct DevPool {
     static constexpr size_t kChunk = (size_t)64 << 20;
-    std::vector<void*> chunks;
+    Allocator mem;
+    hipStream_t s;
+    std::vector<std::pair<void*, size_t>> chunks;
     char* cur = nullptr;
     size_t left = 0;
     hipError_t err = hipSuccess;
+    DevPool(const Allocator& a, hipStream_t st) : mem(a), s(st) {}
     template <class T>
     T* alloc(int64_t count)
     {
@@ -586,9 +591,9 @@ struct DevPool {
         if (bytes > left) {
             void* p = nullptr;
             const size_t sz = bytes > kChunk ? bytes : kChunk;
-            err = hipMalloc(&p, sz);
+            err = dev_alloc(mem, &p, sz, s);
             if (err != hipSuccess) return nullptr;
-            chunks.push_back(p);
+            chunks.push_back({p, sz});
             cur = (char*)p;
             left = sz;
         }
@@ -599,8 +604,7 @@ struct DevPool {
     }
     ~DevPool()
     {
-        for (void* p : chunks)
-            if (p) (void)hipFree(p);
+        for (auto& c : chunks) dev_free(mem, c.first, c.second, s);
     }
 };
 
@@ -618,7 +622,7 @@ struct LevelBufs {
 sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, int64_t n, int d, int leaf_size,
                            int max_level, hipStream_t s, sbh_tree_impl* t, std::string* msg)
 {
-    DevPool tmp;
+    DevPool tmp(t->mem, s);
     auto fail_hip = [&](hipError_t e, const char* where) {
         *msg = std::string(where) + ": " + hipGetErrorString(e);
         return e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? SBH_ENOMEM : SBH_EHIP;
@@ -670,9 +674,8 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     SBH_TRY(radix_sort_pairs(keys, vals, keys2, vals2, n, 0, 64, hist, stmp, s), "radix sort");
 
     // sorted points (owned by the tree)
-    SBH_TRY(hipMalloc(&t->slab[0], carve_bytes<float4>(n) * (nrm ? 2 : 1) + carve_bytes<uint32_t>(n) +
-                                        carve_bytes<uint64_t>(n)),
-            "allocating points");
+    t->slab_bytes[0] = carve_bytes<float4>(n) * (nrm ? 2 : 1) + carve_bytes<uint32_t>(n) + carve_bytes<uint64_t>(n);
+    SBH_TRY(dev_alloc(t->mem, &t->slab[0], t->slab_bytes[0], s), "allocating points");
     {
         Carver c{(char*)t->slab[0]};
         t->pts = c.take<float4>(n);
@@ -790,9 +793,9 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     }
 
     // concatenate level arrays into node arrays
-    SBH_TRY(hipMalloc(&t->slab[1], carve_bytes<int32_t>(n_nodes) * 7 + carve_bytes<float4>(n_nodes) * (nrm ? 2 : 1) +
-                                        carve_bytes<float>(n_nodes)),
-            "allocating nodes");
+    t->slab_bytes[1] =
+        carve_bytes<int32_t>(n_nodes) * 7 + carve_bytes<float4>(n_nodes) * (nrm ? 2 : 1) + carve_bytes<float>(n_nodes);
+    SBH_TRY(dev_alloc(t->mem, &t->slab[1], t->slab_bytes[1], s), "allocating nodes");
     {
         Carver c{(char*)t->slab[1]};
         t->nbegin = c.take<int32_t>(n_nodes);
@@ -830,7 +833,8 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     {
         const size_t bytes = carve_bytes<uint32_t>(nbk * ts) + carve_bytes<float4>(nbk * d3) * (nrm ? 2 : 1) +
                              carve_bytes<float>(nbk * d3);
-        SBH_TRY(hipMalloc(&t->slab[2], bytes), "allocating blocks");
+        t->slab_bytes[2] = bytes;
+        SBH_TRY(dev_alloc(t->mem, &t->slab[2], bytes, s), "allocating blocks");
         SBH_TRY(hipMemsetAsync(t->slab[2], 0, bytes, s), "blocks clear");
         Carver c{(char*)t->slab[2]};
         t->btopo = c.take<uint32_t>(nbk * ts);

@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
         smooth_setup(tv, kp.wscale, logwbar);
-        r0 = cube_distance(tv, qx, qy, qz);
+        r0 = smooth_shift<D>(tv, qx, qy, qz, a.alpha);
     }
     const uint32_t* __restrict__ rt = tv.btopo;  // root block
     const uint32_t n_a = valid ? rt[slot] : 0u;
@@ -276,10 +276,7 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
     // with the same bits because float addition is commutative)
 #pragma unroll
     for (int o = 1; o < D3; o <<= 1) val += __shfl_xor(val, o);
-    if (valid && slot == 0) {
-        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(val) + logwbar) / a.alpha;
-        else out[j] = val;
-    }
+    if (valid && slot == 0) out[j] = query_value<K>(val, r0, logwbar, a.alpha, qx, qy, qz);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,6 +309,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
     __shared__ float4 root_agg[D3];        // the subdomains' aggregates (and dipoles), for every path start
     __shared__ float4 root_dip[K == SBH_WINDING ? D3 : 1];
     __shared__ float qpos[4][kPoolPaths / 8 * 3];   // the wavefront's query positions (Q <= kPoolPaths / d^3)
+    __shared__ float qr0[K == SBH_SMOOTHDIST ? 4 : 1][kPoolPaths / 8];   // their smooth-distance shifts
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int S = a.samples;
@@ -345,6 +343,14 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
         }
         for (int i = lane; i < 3 * Q; i += 64)   // the wavefront's queries (past the end: zero)
             qpos[wv][i] = q0 * 3 + i < 3 * nq ? gld(queries + 3 * q0 + i) : 0.0f;
+        if constexpr (K == SBH_SMOOTHDIST) {
+            if (lane < Q) {
+                const int64_t jq = q0 + lane;
+                qr0[wv][lane] = jq < nq ? smooth_shift<D>(tv, gld(queries + 3 * jq), gld(queries + 3 * jq + 1),
+                                                          gld(queries + 3 * jq + 2), a.alpha)
+                                        : 0.0f;
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -374,7 +380,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
         qx = qpos[wv][3 * qi];
         qy = qpos[wv][3 * qi + 1];
         qz = qpos[wv][3 * qi + 2];
-        if constexpr (K == SBH_SMOOTHDIST) r0 = cube_distance(tv, qx, qy, qz);
+        if constexpr (K == SBH_SMOOTHDIST) r0 = qr0[wv][qi];
         const uint32_t n_a = tab[wv][slot][0];
         if (n_a == 0u) {   // empty subdomain
             if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(-1, 0, 0, 0);
@@ -527,12 +533,9 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
             for (int t = 0; t < S; ++t) fa += res[wv][(lane * D3 + c) * S + t];
             val += cvs[wv][lane * D3 + c] + fa / (float)S;
         }
-        if constexpr (K == SBH_SMOOTHDIST) {
-            const float rq = cube_distance(tv, gld(queries + 3 * jq), gld(queries + 3 * jq + 1), gld(queries + 3 * jq + 2));
-            gst(out + jq, rq - (logf(val) + logwbar) / a.alpha);
-        } else {
-            gst(out + jq, val);
-        }
+        const float rq = (K == SBH_SMOOTHDIST) ? qr0[wv][lane] : 0.0f;
+        gst(out + jq, query_value<K>(val, rq, logwbar, a.alpha, qpos[wv][3 * lane], qpos[wv][3 * lane + 1],
+                                     qpos[wv][3 * lane + 2]));
     }
 }
 
@@ -1106,7 +1109,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
         smooth_setup(tv, kp.wscale, logwbar);
-        r0 = cube_distance(tv, qx, qy, qz);
+        r0 = smooth_shift<D>(tv, qx, qy, qz, a.alpha);
     }
     const uint32_t stream = (uint32_t)(j0 / a.group);   // a.group is a multiple of 64
     const float inv_valid = 1.0f / (float)__popcll(__ballot(valid));
@@ -1169,10 +1172,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
 #pragma unroll
         for (int q = 1; q < P; ++q) F += part_f[tl * P + q][lane];
     }
-    if (valid) {
-        if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(F) + logwbar) / a.alpha);
-        else gst(out + j, F);
-    }
+    if (valid) gst(out + j, query_value<K>(F, r0, logwbar, a.alpha, qx, qy, qz));
 }
 
 template <int D, int K, bool TRACE, bool O64>
@@ -1231,7 +1231,10 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
     constexpr int TS = topo_stride(D3);
     using Off = typename TreeOff<O64>::T;   // byte offsets into the tree's arrays, as in the walks
     constexpr int MAXS = bh_stack_depth<D>();
+    // an entry is a child block to open: {block id, first point} and, apart, the level of its
+    // node (block ids take all 32 bits; levels are below 64)
     __shared__ int2 stack[256 / 64][MAXS];
+    __shared__ uint8_t stack_lvl[256 / 64][MAXS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (((int64_t)blockIdx.x * blockDim.x + wv * 64) >= nq) return;
@@ -1246,7 +1249,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
         smooth_setup(tv, kp.wscale, logwbar);
-        r0 = cube_distance(tv, qx, qy, qz);
+        r0 = smooth_shift<D>(tv, qx, qy, qz, a.alpha);
     }
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float acc = 0.0f;
@@ -1263,7 +1266,10 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             for (int i = 0; i < tv.n_points; ++i)
                 acc = term_acc<K>(tv.pts[i], (K == SBH_WINDING) ? tv.pdip[i] : zero4, qx, qy, qz, kp, r0, acc);
         } else {
-            if (lane == 0) stack[wv][0] = make_int2(0, 0);  // block 0, level 0 (packed), begin 0
+            if (lane == 0) {
+                stack[wv][0] = make_int2(0, 0);   // block 0, first point 0
+                stack_lvl[wv][0] = 0;             // the root's level
+            }
             sp = 1;
         }
     }
@@ -1271,8 +1277,8 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
     while (sp > 0) {
         --sp;
         const int2 e = stack[wv][sp];
-        const int32_t blk = __builtin_amdgcn_readfirstlane(e.x & 0x07FFFFFF);
-        const int level = __builtin_amdgcn_readfirstlane((int)((uint32_t)e.x >> 27));
+        const int32_t blk = __builtin_amdgcn_readfirstlane(e.x);
+        const int level = __builtin_amdgcn_readfirstlane((int)stack_lvl[wv][sp]);
         uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
         __builtin_amdgcn_wave_barrier();
         const float diamC = ldexpf(tv.diam0, -(level + 1) * (D == 2 ? 1 : 2));
@@ -1294,7 +1300,10 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             if (__ballot(near) == 0ull) {
                 acc = term_r2_acc<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, dx, dy, dz, r2, kp, r0, acc);
             } else if (internal_c) {
-                if (lane == 0) stack[wv][sp] = make_int2((int32_t)(((uint32_t)(level + 1) << 27) | (uint32_t)(base + nint)), (int32_t)pre);
+                if (lane == 0) {
+                    stack[wv][sp] = make_int2(base + nint, (int32_t)pre);
+                    stack_lvl[wv][sp] = (uint8_t)(level + 1);
+                }
                 ++sp;
             } else {
                 for (uint32_t i = pre; i < pre + cnt; ++i) {
@@ -1308,10 +1317,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (valid) {
-        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(acc) + logwbar) / a.alpha;
-        else out[j] = acc;
-    }
+    if (valid) out[j] = query_value<K>(acc, r0, logwbar, a.alpha, qx, qy, qz);
 }
 
 // A tree whose root is a leaf: every query is summed exactly over its points.
@@ -1325,14 +1331,13 @@ __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
         smooth_setup(tv, kp.wscale, logwbar);
-        r0 = cube_distance(tv, qx, qy, qz);
+        r0 = smooth_shift<2>(tv, qx, qy, qz, alpha);   // the root is a leaf: every point is examined
     }
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float acc = 0.0f;
     for (int i = 0; i < tv.n_points; ++i)
         acc = term_acc<K>(gld4(tv.pts + i), (K == SBH_WINDING) ? gld4(tv.pdip + i) : zero4, qx, qy, qz, kp, r0, acc);
-    if constexpr (K == SBH_SMOOTHDIST) gst(out + j, r0 - (logf(acc) + logwbar) / alpha);
-    else gst(out + j, acc);
+    gst(out + j, query_value<K>(acc, r0, logwbar, alpha, qx, qy, qz));
 }
 
 template <int K>

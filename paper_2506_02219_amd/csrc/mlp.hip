@@ -395,18 +395,37 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ prm, 
     }
 }
 
-// Means over the rows that count, sums over blocks in block order:
-// grad[0..1607] gradient, grad[1608] loss, grad[1609] number of rows.
-__global__ void k_mlp_reduce(const float* __restrict__ partial, int nblocks, float* __restrict__ grad)
+// Means over the rows that count, sums over blocks in a fixed order:
+// grad[0..1607] gradient, grad[1608] loss, grad[1609] number of rows.  A
+// workgroup takes 64 consecutive entries; its kReduceParts wavefronts each sum
+// one run of consecutive blocks in block order, and the runs' sums are added
+// in run order (independent loads in flight instead of one serial chain).
+constexpr int kReduceParts = 8;
+__global__ void __launch_bounds__(64 * kReduceParts) k_mlp_reduce(const float* __restrict__ partial, int nblocks,
+                                                                  float* __restrict__ grad)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > 1609) return;
+    __shared__ float ps[kReduceParts][64];
+    __shared__ float pc[kReduceParts];
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + l;
+    const int per = (nblocks + kReduceParts - 1) / kReduceParts;
+    const int b0 = g * per, b1 = min(nblocks, b0 + per);
     float s = 0.0f, cnt = 0.0f;
-    for (int b = 0; b < nblocks; ++b) {
-        s += partial[(int64_t)b * kGradStride + p];
+    for (int b = b0; b < b1; ++b) {
+        if (p <= 1609) s += partial[(int64_t)b * kGradStride + p];
         cnt += partial[(int64_t)b * kGradStride + 1609];
     }
-    grad[p] = p == 1609 ? cnt : s / fmaxf(cnt, 1.0f);
+    ps[g][l] = s;
+    if (l == 0) pc[g] = cnt;
+    __syncthreads();
+    if (g == 0 && p <= 1609) {
+        float t = ps[0][l], c = pc[0];
+        for (int k = 1; k < kReduceParts; ++k) {
+            t += ps[k][l];
+            c += pc[k];
+        }
+        grad[p] = p == 1609 ? c : t / fmaxf(c, 1.0f);
+    }
 }
 
 // Adam (Kingma and Ba): state m[1608], v[1608]
@@ -618,7 +637,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
         const float wbar = tv.nagg[0].w / (float)tv.n_points;
         kp.wscale = 1.0f / wbar;
         logwbar = logf(wbar);
-        r0 = cube_distance(tv, qx, qy, qz);
+        r0 = smooth_shift<2>(tv, qx, qy, qz, a.alpha);
     }
     const uint32_t* __restrict__ rt = tv.btopo;
     const uint32_t n_a = valid ? rt[slot] : 0u;
@@ -801,10 +820,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned(TreeView tv, const float* _
     float val = n_a ? cv + fa / (float)a.samples : 0.0f;
 #pragma unroll
     for (int o = 1; o < D3; o <<= 1) val += __shfl_xor(val, o);
-    if (valid && slot == 0) {
-        if constexpr (K == SBH_SMOOTHDIST) out[j] = r0 - (logf(val) + logwbar) / a.alpha;
-        else out[j] = val;
-    }
+    if (valid && slot == 0) out[j] = query_value<K>(val, r0, logwbar, a.alpha, qx, qy, qz);
 }
 
 // The same estimator with lane refill: a wavefront owns a pool of kLearnPool
@@ -829,6 +845,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const flo
     __shared__ float4 root_agg[D3];
     __shared__ float4 root_dip[K == SBH_WINDING ? D3 : 1];
     __shared__ float qpos[4][kLearnPool / D3 * 3];
+    __shared__ float qr0[K == SBH_SMOOTHDIST ? 4 : 1][kLearnPool / D3];   // the queries' smooth-distance shifts
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -874,6 +891,14 @@ __global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const flo
             nint += ((int)n > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
         }
         for (int i = lane; i < 3 * Q; i += 64) qpos[wv][i] = q0 * 3 + i < 3 * nq ? queries[3 * q0 + i] : 0.0f;
+        if constexpr (K == SBH_SMOOTHDIST) {
+            if (lane < Q) {
+                const int64_t jq = q0 + lane;
+                qr0[wv][lane] = jq < nq ? smooth_shift<2>(tv, queries[3 * jq], queries[3 * jq + 1], queries[3 * jq + 2],
+                                                          a.alpha)
+                                        : 0.0f;
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -902,7 +927,7 @@ __global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const flo
         qx = qpos[wv][3 * qi];
         qy = qpos[wv][3 * qi + 1];
         qz = qpos[wv][3 * qi + 2];
-        if constexpr (K == SBH_SMOOTHDIST) r0 = cube_distance(tv, qx, qy, qz);
+        if constexpr (K == SBH_SMOOTHDIST) r0 = qr0[wv][qi];
         const uint32_t n_a = tab[wv][slot][0];
         if (n_a == 0u) {   // empty subdomain
             if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)S + smp] = make_int4(-1, 0, 0, 0);
@@ -1102,12 +1127,8 @@ __global__ void __launch_bounds__(256) k_sbh_learned_pool(TreeView tv, const flo
             for (int t = 0; t < S; ++t) fa += res[wv][(lane * D3 + c) * S + t];
             val += cvs[wv][lane * D3 + c] + fa / (float)S;
         }
-        if constexpr (K == SBH_SMOOTHDIST) {
-            const float rq = cube_distance(tv, queries[3 * jq], queries[3 * jq + 1], queries[3 * jq + 2]);
-            out[jq] = rq - (logf(val) + logwbar) / a.alpha;
-        } else {
-            out[jq] = val;
-        }
+        const float rq = (K == SBH_SMOOTHDIST) ? qr0[wv][lane] : 0.0f;
+        out[jq] = query_value<K>(val, rq, logwbar, a.alpha, queries[3 * jq], queries[3 * jq + 1], queries[3 * jq + 2]);
     }
 }
 
@@ -1128,7 +1149,7 @@ hipError_t launch_mlp_grad(const float* prm, const float* X, const float* Tg, co
 {
     const int nb = (int)((rows + 63) / 64);
     k_mlp_grad<<<nb, 64, 0, s>>>(prm, X, Tg, Cn, n, row_begin, rows, partial);
-    k_mlp_reduce<<<(1610 + 255) / 256, 256, 0, s>>>(partial, nb, grad);
+    k_mlp_reduce<<<(1610 + 63) / 64, 64 * kReduceParts, 0, s>>>(partial, nb, grad);
     return hipGetLastError();
 }
 

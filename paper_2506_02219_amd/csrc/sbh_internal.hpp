@@ -69,8 +69,21 @@ __device__ __forceinline__ float gld(const float* p) { return *(const SBH_GLOBAL
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const SBH_GLOBAL uint32_t*)p; }
 __device__ __forceinline__ void gst(float* p, float v) { *(SBH_GLOBAL float*)p = v; }
 
+// Device memory of the library: one allocator pair (sbh_set_allocator), or
+// the default, the stream-ordered hipMallocAsync / hipFreeAsync.  Objects keep
+// the pair they were allocated with and release through it.
+struct Allocator {
+    sbh_alloc_fn alloc;   // nullptr: the default
+    sbh_free_fn free;
+    void* ctx;
+};
+Allocator allocator_current();
+hipError_t dev_alloc(const Allocator& a, void** p, size_t bytes, hipStream_t s);
+void dev_free(const Allocator& a, void* p, size_t bytes, hipStream_t s);
+
 struct sbh_tree_impl {
     int device;
+    Allocator mem;    // the allocator the tree's slabs came from
     int d, d3, bits, leaf_size, max_level, depth, has_normals;
     int64_t n_points, n_nodes, n_blocks;
     float lo[3], side, inv_side;
@@ -85,6 +98,7 @@ struct sbh_tree_impl {
     float* bspr;
     uint32_t* btopo;
     void* slab[3];   // the allocations the arrays above are carved from: points, nodes, blocks
+    size_t slab_bytes[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -201,16 +215,111 @@ __device__ __forceinline__ float term_acc(float4 a, float4 dp, float qx, float q
     }
 }
 
-// Lower bound on the distance from q to any source (distance to the root
-// cube); used as the shift of the smooth-distance sum so that no term
-// overflows: with it every exp(-alpha (r - r0)) of a point or of a centre of
-// mass is at most 1.
+// Lower bound on the distance from q to any source: its distance to the
+// root cube.
 __device__ __forceinline__ float cube_distance(const TreeView& tv, float qx, float qy, float qz)
 {
     const float ex = fmaxf(fmaxf(tv.lo[0] - qx, qx - (tv.lo[0] + tv.side)), 0.0f);
     const float ey = fmaxf(fmaxf(tv.lo[1] - qy, qy - (tv.lo[1] + tv.side)), 0.0f);
     const float ez = fmaxf(fmaxf(tv.lo[2] - qz, qz - (tv.lo[2] + tv.side)), 0.0f);
     return __builtin_sqrtf(norm2(ex, ey, ez));
+}
+
+// Margin of the smooth-distance shift: the shift lies this many 1/alpha below
+// the distance to the source that the descent below finds, so that source's
+// term is at least e^-30 of its weight share (far from float32 underflow).
+constexpr float kSmoothShiftMargin = 30.0f;
+
+// Shift r0 of the smooth-distance sum for query q.  Float32 cannot hold
+// w exp(-alpha r) once alpha r exceeds about 87, so the kernels evaluate
+// (w / wbar) exp(-alpha (r - r0)) and report r0 - (log F + log wbar) / alpha.
+// r0 comes from a greedy descent: from the root, into the non-empty child
+// whose cell is nearest to q, down to a leaf; r_up is the distance from q to
+// the nearest point of that leaf (an upper bound on the distance to the
+// nearest source), and
+//   r0 = max(r_up - kSmoothShiftMargin / alpha, distance to the root cube),
+// so the sum is at least e^-30 times that point's weight share and no term
+// of a point nearer than r0 can exceed the float32 range unless the descent
+// missed the nearest source by more than about 100 / alpha.  The shift is a
+// common factor of every term: the estimate of the scaled sum stays
+// unbiased.  Cells follow the tree's quantisation (a level-l cell of side
+// side / d^l); d = 4 digits hold two octree digits, the higher one in bits
+// 3..5.
+template <int D>
+__device__ __forceinline__ float smooth_shift(const TreeView& tv, float qx, float qy, float qz, float alpha)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    const float q[3] = {qx, qy, qz};
+    float cl[3] = {tv.lo[0], tv.lo[1], tv.lo[2]};
+    float cs = tv.side;
+    uint32_t n = (uint32_t)tv.n_points, begin = 0u;
+    uint32_t blk = 0u;
+    for (int level = 0; (int)n > tv.leaf_size && level < tv.max_level; ++level) {
+        const float hs = cs * (1.0f / (float)D);
+        float dd[3][D];   // squared distance from q to each slab of the cell along each axis
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const float lo = cl[a] + (float)i * hs, hi = lo + hs;
+                const float e = fmaxf(fmaxf(lo - q[a], q[a] - hi), 0.0f);
+                dd[a][i] = e * e;
+            }
+        const uint32_t* bt = tv.btopo + (uint64_t)blk * TS;
+        float best = INFINITY;
+        uint32_t pre = 0u, pre_b = 0u, n_b = 0u;
+        int c_b = 0, nint = 0, nint_b = 0;
+        for (int c = 0; c < D3; ++c) {
+            const uint32_t cnt = gld(bt + c);
+            const int ix = D == 2 ? (c & 1) : ((c >> 2) & 2) | (c & 1);
+            const int iy = D == 2 ? ((c >> 1) & 1) : ((c >> 3) & 2) | ((c >> 1) & 1);
+            const int iz = D == 2 ? ((c >> 2) & 1) : ((c >> 4) & 2) | ((c >> 2) & 1);
+            const float d2 = dd[0][ix] + dd[1][iy] + dd[2][iz];
+            if (cnt != 0u && d2 < best) {
+                best = d2;
+                c_b = c;
+                pre_b = pre;
+                n_b = cnt;
+                nint_b = nint;
+            }
+            nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
+            pre += cnt;
+        }
+        const int ix = D == 2 ? (c_b & 1) : ((c_b >> 2) & 2) | (c_b & 1);
+        const int iy = D == 2 ? ((c_b >> 1) & 1) : ((c_b >> 3) & 2) | ((c_b >> 1) & 1);
+        const int iz = D == 2 ? ((c_b >> 2) & 1) : ((c_b >> 4) & 2) | ((c_b >> 2) & 1);
+        cl[0] += (float)ix * hs;
+        cl[1] += (float)iy * hs;
+        cl[2] += (float)iz * hs;
+        cs = hs;
+        blk = gld(bt + D3) + (uint32_t)nint_b;
+        begin += pre_b;
+        n = n_b;
+    }
+    float r2 = INFINITY;
+    for (uint32_t i = 0; i < n; ++i) {
+        const float4 p = gld4(tv.pts + (uint64_t)(begin + i));
+        r2 = fminf(r2, norm2(p.x - qx, p.y - qy, p.z - qz));
+    }
+    return fmaxf(__builtin_sqrtf(r2) - kSmoothShiftMargin / alpha, cube_distance(tv, qx, qy, qz));
+}
+
+// A query with a non-finite coordinate has no defined value: NaN.
+__device__ __forceinline__ float nan_unless_finite(float v, float qx, float qy, float qz)
+{
+    return (__builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz)) ? v : __builtin_nanf("");
+}
+
+// The value written for query q from the estimated (or summed) F: the smooth
+// distance r0 - (log F + log wbar) / alpha, or F itself.
+template <int K>
+__device__ __forceinline__ float query_value(float F, float r0, float logwbar, float alpha, float qx, float qy,
+                                             float qz)
+{
+    const float v = (K == SBH_SMOOTHDIST) ? r0 - (logf(F) + logwbar) / alpha : F;
+    return nan_unless_finite(v, qx, qy, qz);
 }
 
 // ---------------------------------------------------------------------------

@@ -103,3 +103,32 @@ def test_argument_errors_before_any_device_work():
     assert b"no tree" in L.sbh_last_error()
     assert L.sbh_batch_launch(None, 0, 0, None) == -1
     assert L.sbh_batch_free(None) == 0
+
+
+def test_allocator_failure_is_reported_and_leaks_nothing():
+    """An allocator that refuses: the build and the training workspace report SBH_ENOMEM before
+    any kernel runs, and every allocation the library obtained has been returned."""
+    import paper_2506_02219_amd as P
+    L = P.lib()
+    calls = {"alloc": 0, "live": 0}
+
+    def alloc(nbytes, stream, ctx):
+        calls["alloc"] += 1
+        return None
+
+    def free(ptr, nbytes, stream, ctx):
+        calls["live"] -= 1
+
+    fa, ff = P.ALLOC_FN(alloc), P.FREE_FN(free)
+    assert L.sbh_set_allocator(ctypes.cast(fa, ctypes.c_void_p), None, None) == -1   # one of the two
+    assert L.sbh_set_allocator(ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p), None) == 0
+    try:
+        fake = ctypes.c_void_p(4096)   # never dereferenced: the first allocation fails first
+        h = ctypes.c_void_p()
+        assert L.sbh_build(fake, fake, None, 100, None, None, ctypes.byref(h)) == -2
+        assert h.value is None
+        assert b"alloc" in L.sbh_last_error()
+        assert L.sbh_mlp_loss_grad(fake, fake, fake, fake, 64, None, fake) == -2
+        assert calls["alloc"] == 2 and calls["live"] == 0
+    finally:
+        assert L.sbh_set_allocator(None, None, None) == 0

@@ -224,3 +224,41 @@ def test_bh_infinite_beta_is_exact():
         g = host(P.sbh_eval(gt, T(q), kernel, beta=math.inf, samples=0))
         ref = fp64_reference(src, w, nrm, q, kernel)
         assert np.all(np.abs(g - ref) <= 1e-4 * value_scale(ref, kernel, 100.0))
+
+
+# ----------------------------------------------------------------------------- deep trees
+def geometric_cluster(n, seed=12):
+    """Half of the points uniform in the unit cube, half at distances 2^-u (u uniform in [2, 19])
+    from the point c = (0.3, 0.6, 0.45): the tree reaches level 18 and more around c."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = n // 2
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    c = np.array([0.3, 0.6, 0.45])
+    cl = c + d * (2.0 ** -rng.uniform(2, 19, m))[:, None]
+    src = np.concatenate([rng.uniform(0, 1, (n - m, 3)), cl]).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    q = (c + rng.normal(size=(1024, 3)) * (2.0 ** -rng.uniform(3, 14, 1024))[:, None]).astype(np.float32)
+    return src, w, q
+
+
+@pytest.mark.parametrize("G,rr,proposal", [(64, 1, None), (64, 2, None), (1, 1, None), (1, 2, None),
+                                            (64, 0, None), (64, 1, 3), (1, 1, 2)])
+def test_deep_tree_paths_beyond_sixteen_steps(G, rr, proposal):
+    """Leaf size 1 on a geometric cluster: paths without roulette (rr = 1) and with p = 1/2 run
+    past step 16, where the coherent walk computes its random words again instead of taking the
+    ones it holds; every path record must still match the oracle bit for bit."""
+    src, w, q = geometric_cluster(6000)
+    gt, ot = build_both(src, w, leaf_size=1)
+    assert gt.depth >= 18, gt.depth
+    paths = torch.full((q.shape[0], 8, 1, 4), -7, dtype=torch.int32, device=DEV)
+    out = host(P.sbh_eval(gt, T(q), P.POTENTIAL, samples=1, seed=4, group=G, rr_mode=rr, paths=paths,
+                          proposal=proposal))
+    pth = host(paths)
+    st = check_sbh(gt, ot, q, P.POTENTIAL, samples=1, seed=4, group=G, rr_mode=rr, gpu_out=out, gpu_paths=pth,
+                   index=np.arange(q.shape[0]), proposal=proposal,
+                   max_divergent=3e-3 if proposal else 1e-5)
+    deep = int((pth[..., 2] >= 17).sum())
+    print(st, "paths with >= 17 accepted steps:", deep)
+    if rr == 1:   # no roulette: every path into the cluster runs to a one-point leaf
+        assert deep > 0
