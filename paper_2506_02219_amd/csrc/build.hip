@@ -477,54 +477,67 @@ __global__ void k_set_base(const uint32_t* __restrict__ cscan_prev, int n_int_pr
 // ---------------------------------------------------------------------------
 // 5. Aggregates and packing
 // ---------------------------------------------------------------------------
+// Aggregates of one level's nodes (offset off, n of them), in float64: from
+// the points of a leaf, from the children's float64 aggregates for an
+// internal node (mass, w-weighted centre of mass, summed w n, and the second
+// moment about the centre of mass by the parallel-axis rule, a sum of
+// non-negative terms).  The tree stores each as the float32 nearest to its
+// float64 value: one rounding, so a one-point leaf's centre of mass is its
+// point and its second moment exactly 0, as the definitions give.
 __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ nbegin,
                             const int32_t* __restrict__ ncount, const int32_t* __restrict__ nfirst,
                             const int32_t* __restrict__ nnchild, const float4* __restrict__ pts,
-                            const float4* __restrict__ pdip, float4* __restrict__ nagg, float4* __restrict__ ndip,
+                            const float4* __restrict__ pdip, double4* __restrict__ agg64, double4* __restrict__ dip64,
+                            double* __restrict__ spr64, float4* __restrict__ nagg, float4* __restrict__ ndip,
                             float* __restrict__ nspr)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t g = off + i;
-    float m = 0.f, sx = 0.f, sy = 0.f, sz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
+    double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
     const int32_t f = nfirst[g];
     if (f < 0) {
         const int32_t b = nbegin[g], e = b + ncount[g];
         for (int32_t s = b; s < e; ++s) {
             const float4 p = pts[s];
-            m += p.w; sx += p.w * p.x; sy += p.w * p.y; sz += p.w * p.z;
+            const double w = p.w;
+            m += w; sx += w * (double)p.x; sy += w * (double)p.y; sz += w * (double)p.z;
             if (pdip) { const float4 q = pdip[s]; dx += q.x; dy += q.y; dz += q.z; }
         }
     } else {
         const int32_t e = f + nnchild[g];
         for (int32_t c = f; c < e; ++c) {
-            const float4 a = nagg[c];
+            const double4 a = agg64[c];
             m += a.w; sx += a.w * a.x; sy += a.w * a.y; sz += a.w * a.z;
-            if (ndip) { const float4 q = ndip[c]; dx += q.x; dy += q.y; dz += q.z; }
+            if (pdip) { const double4 q = dip64[c]; dx += q.x; dy += q.y; dz += q.z; }
         }
     }
-    const float cx = sx / m, cy = sy / m, cz = sz / m;
-    nagg[g] = make_float4(cx, cy, cz, m);
-    if (ndip) ndip[g] = make_float4(dx, dy, dz, 0.0f);
-    // second moment about the centre of mass: from the points of a leaf, from
-    // the children of an internal node (parallel axes: every term >= 0)
-    float s2 = 0.f;
+    const double cx = sx / m, cy = sy / m, cz = sz / m;
+    double s2 = 0.0;
     if (f < 0) {
         const int32_t b = nbegin[g], e = b + ncount[g];
         for (int32_t s = b; s < e; ++s) {
             const float4 p = pts[s];
-            const float ex = p.x - cx, ey = p.y - cy, ez = p.z - cz;
-            s2 += p.w * (ex * ex + ey * ey + ez * ez);
+            const double ex = (double)p.x - cx, ey = (double)p.y - cy, ez = (double)p.z - cz;
+            s2 += (double)p.w * (ex * ex + ey * ey + ez * ez);
         }
     } else {
         const int32_t e = f + nnchild[g];
         for (int32_t c = f; c < e; ++c) {
-            const float4 a = nagg[c];
-            const float ex = a.x - cx, ey = a.y - cy, ez = a.z - cz;
-            s2 += a.w * (nspr[c] + (ex * ex + ey * ey + ez * ez));
+            const double4 a = agg64[c];
+            const double ex = a.x - cx, ey = a.y - cy, ez = a.z - cz;
+            s2 += a.w * (spr64[c] + (ex * ex + ey * ey + ez * ez));
         }
     }
-    nspr[g] = s2 / m;
+    s2 /= m;
+    agg64[g] = make_double4(cx, cy, cz, m);
+    spr64[g] = s2;
+    nagg[g] = make_float4((float)cx, (float)cy, (float)cz, (float)m);
+    nspr[g] = (float)s2;
+    if (pdip) {
+        dip64[g] = make_double4(dx, dy, dz, 0.0);
+        ndip[g] = make_float4((float)dx, (float)dy, (float)dz, 0.0f);
+    }
 }
 
 __global__ void k_pack(int32_t n_nodes, const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
@@ -853,9 +866,14 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     {
         std::vector<int64_t> off(n_levels + 1, 0);
         for (int l = 0; l < n_levels; ++l) off[l + 1] = off[l] + lv[l].n;
+        double4* agg64 = tmp.alloc<double4>(n_nodes);
+        double4* dip64 = nrm ? tmp.alloc<double4>(n_nodes) : nullptr;
+        double* spr64 = tmp.alloc<double>(n_nodes);
+        SBH_ALLOC_OK("allocating float64 aggregates");
         for (int l = n_levels - 1; l >= 0; --l) {
             k_aggregate<<<nblk(lv[l].n), 256, 0, s>>>((int32_t)off[l], lv[l].n, t->nbegin, t->ncount, t->nfirst,
-                                                      t->nnchild, t->pts, t->pdip, t->nagg, t->ndip, t->nspr);
+                                                      t->nnchild, t->pts, t->pdip, agg64, dip64, spr64, t->nagg,
+                                                      t->ndip, t->nspr);
             SBH_TRY(hipGetLastError(), "aggregate kernel");
         }
     }

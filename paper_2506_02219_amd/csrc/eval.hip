@@ -1245,6 +1245,9 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         qy = queries[3 * j + 1];
         qz = queries[3 * j + 2];
     }
+    // a query with a non-finite coordinate has no value (NaN) and takes no part in the vote, so
+    // the cut its wavefront neighbours get is the one they would get without it
+    const bool votes = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     KParams kp{a.eps2, a.alpha, 1.0f};
     float logwbar = 0.f, r0 = 0.f;
     if constexpr (K == SBH_SMOOTHDIST) {
@@ -1259,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
         const float4 g = tv.nagg[0];
         const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
         const float lim = a.beta * tv.diam0;   // |q - com| / |B| >= beta, squared
-        const bool near = valid && !(norm2(dx, dy, dz) >= lim * lim);
+        const bool near = votes && !(norm2(dx, dy, dz) >= lim * lim);
         if (__ballot(near) == 0ull) {
             acc = term<K>(g, (K == SBH_WINDING) ? tv.ndip[0] : zero4, qx, qy, qz, kp, r0);
         } else if (!tv.root_internal) {
@@ -1296,7 +1299,7 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
             const float4 g = ba[c];
             const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
             const float r2 = norm2(dx, dy, dz);
-            const bool near = valid && !(r2 >= limC * limC);
+            const bool near = votes && !(r2 >= limC * limC);
             if (__ballot(near) == 0ull) {
                 acc = term_r2_acc<K>(g, (K == SBH_WINDING) ? bd[c] : zero4, dx, dy, dz, r2, kp, r0, acc);
             } else if (internal_c) {

@@ -16,8 +16,11 @@ Tolerances (stated once, used by every parity test):
     query.  At most 1% of the queries may need this allowance;
   - sampled paths (end node, depth, accepted steps, stop reason): bit-exact,
     except queries whose smallest Russian-roulette margin |u - p| is below
-    1e-5 (a float32 / float64 near-tie); at most 1e-5 of the queries may
-    diverge, and every divergent query must be such a near-tie.
+    1e-5 (a float32 / float64 near-tie); every divergent query must be such a
+    near-tie, and the number of them must be consistent with a divergence
+    rate of at most 1e-5 of the queries: a one-sided Poisson test at level
+    1e-3 (allowed_divergent) - one divergent query among a few thousand is
+    what a rate near 1e-5 produces now and then, two are not.
 """
 import math
 
@@ -31,6 +34,19 @@ DEV = "cuda"
 U32 = 2.0 ** -24
 NEAR_TIE = 1e-5
 REL_TOL = 1e-4
+
+
+def allowed_divergent(n, rate=1e-5, level=1e-3):
+    """The largest count of divergent queries among n that a divergence rate of `rate` explains:
+    the smallest k with P(X > k) < level for X ~ Poisson(rate n)."""
+    lam = rate * n
+    k, term = 0, math.exp(-lam)
+    cdf = term
+    while 1.0 - cdf >= level:
+        k += 1
+        term *= lam / k
+        cdf += term
+    return k
 
 
 def T(a, dtype=None):
@@ -86,9 +102,25 @@ def value_scale(ref, kernel, alpha):
     return ref
 
 
+# constants of the float32 error bound 2^-24 (C_EVAL absum + C_AGG sens) of an estimate
+C_EVAL, C_AGG = 64, 16
+
+
+def fp32_bound_ratio(gpu, F, absum, kernel, alpha=100.0, sens=None):
+    """|GPU - oracle| over the float32 bound of each estimate (in the units of the sum F: the smooth
+    distance's error is taken back through d(-log F / alpha) = -dF / (alpha F))."""
+    dF = U32 * (C_EVAL * absum + (0 if sens is None else C_AGG * sens))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        if kernel == P.SMOOTHDIST:
+            r = np.abs(gpu + np.log(F) / alpha) * alpha * np.abs(F) / dF
+        else:
+            r = np.abs(gpu - F) / dF
+    return np.where(np.isfinite(r), r, 0.0)
+
+
 def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
     """Return (ok mask, relative error, used-fp32-bound mask) for GPU values vs oracle sums F."""
-    dF = U32 * (64 * absum + (0 if sens is None else 16 * sens))
+    dF = U32 * (C_EVAL * absum + (0 if sens is None else C_AGG * sens))
     if kernel == P.SMOOTHDIST:
         with np.errstate(invalid="ignore", divide="ignore"):
             ref = -np.log(F) / alpha
@@ -112,7 +144,7 @@ def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
 
 def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, eps=1e-3, alpha=100.0,
               index=None, gpu_out=None, gpu_paths=None, batch=0, mlp=None, near_tie=NEAR_TIE,
-              max_divergent=1e-5, proposal=None, tile_all=None):
+              max_divergent=1e-5, proposal=None, tile_all=None, max_fp32_share=0.01):
     """Run (or take) the GPU estimator and compare with the oracle, query by query.
     With `index`, `queries` are a subset of a larger set evaluated on the GPU
     (gpu_out/gpu_paths are the full-set outputs).  mlp: float32 network
@@ -143,12 +175,17 @@ def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, ep
     stats = dict(n=n, path_mismatch=int(path_bad.sum()), value_mismatch=int((~ok).sum()),
                  near_ties=int(near.sum()), fp32_bound_used=int(used_bound.sum()),
                  max_rel_err=float(np.nanmax(np.where(ok, err, np.nan))) if ok.any() else float("nan"),
-                 median_rel_err=float(np.nanmedian(err)))
+                 median_rel_err=float(np.nanmedian(err)),
+                 max_err_over_fp32_bound=float(np.max(np.where(path_bad, 0.0, fp32_bound_ratio(
+                     g, r["F"], r["absum"], kernel, alpha, r["sens"])))))
     worst = np.nonzero(bad & ~near)[0][:5]
+    # the first differing path records of the worst queries: (slot, sample, gpu record, oracle record)
+    recs = [(int(i), [(int(a), int(b), gp[i, a, b].tolist(), r["paths"][i, a, b].tolist())
+                      for a, b in zip(*np.nonzero(np.any(gp[i] != r["paths"][i], axis=-1)))][:2]) for i in worst]
     assert not np.any(bad & ~near), (stats, [(int(i), float(g[i]), float(r["F"][i]), float(r["absum"][i]),
-                                              float(r["sens"][i])) for i in worst])
-    assert bad.sum() <= max_divergent * n, stats
-    assert used_bound.sum() <= 0.01 * n, stats
+                                              float(r["sens"][i])) for i in worst], recs)
+    assert bad.sum() <= allowed_divergent(n, max_divergent), stats
+    assert used_bound.sum() <= max_fp32_share * n, stats
     return stats
 
 
@@ -171,7 +208,7 @@ def check_bh(gt, ot, queries, kernel, beta, eps=1e-3, alpha=100.0, gpu_out=None,
     near = margin < NEAR_TIE
     bad = ~(err <= REL_TOL)
     assert not np.any(bad & ~near), (np.nonzero(bad & ~near)[0][:10], float(np.nanmax(err)))
-    assert bad.sum() <= max(1e-5 * queries.shape[0], 0), int(bad.sum())
+    assert bad.sum() <= allowed_divergent(queries.shape[0]), int(bad.sum())
     return dict(max_rel_err=float(np.nanmax(err)), near=int(near.sum()))
 
 

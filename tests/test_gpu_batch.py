@@ -29,7 +29,7 @@ SPECS = [  # (m, n, kernel, seed, branching): uneven sizes, every kernel, both b
     (2500, 777, 2, 19, 4),
     (6000, 3001, 1, 20, 2),
 ]
-ALPHA = 20.0
+ALPHA = 100.0
 
 
 def make_batch(specs=SPECS):

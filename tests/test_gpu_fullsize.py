@@ -33,8 +33,7 @@ def run_full(cl, group, samples, alpha=100.0, d=2, proposal=None, trees=None):
     idx = np.sort(np.random.Generator(np.random.PCG64(17)).choice(cl.n, NSAMPLE, replace=False))
     st = check_sbh(gt, ot, cl.queries[idx], cl.kernel, samples=samples, seed=0, group=group, alpha=alpha,
                    index=idx, gpu_out=out, gpu_paths=pth, proposal=proposal,
-                   tile_all=cl.queries if proposal == 3 else None,
-                   max_divergent=3e-3 if proposal else 1e-5)
+                   tile_all=cl.queries if proposal == 3 else None)
     return gt, ot, st
 
 

@@ -262,16 +262,14 @@ def test_estimator_exact_network_strict_parity(samples, group):
     cl = W.c1()
     gt, ot = build_both(cl.sources, cl.weights)
     prm = dyadic_constant_params(41)
-    print(check_sbh(gt, ot, cl.queries[:1500], P.POTENTIAL, samples=samples, seed=5, group=group, mlp=prm,
-                    max_divergent=3e-3))
+    print(check_sbh(gt, ot, cl.queries[:1500], P.POTENTIAL, samples=samples, seed=5, group=group, mlp=prm))
 
 
 @pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST])
 def test_estimator_exact_network_surface_kernels(kernel):
     pts, nrm, w, q = surface_cloud()
     gt, ot = build_both(pts, w, nrm)
-    print(check_sbh(gt, ot, q[:1000], kernel, samples=2, seed=6, alpha=20.0, mlp=dyadic_constant_params(42),
-                    max_divergent=3e-3))
+    print(check_sbh(gt, ot, q[:1000], kernel, samples=2, seed=6, alpha=100.0, mlp=dyadic_constant_params(42)))
 
 
 @pytest.mark.parametrize("rr_mode", [1, 2])
@@ -279,7 +277,7 @@ def test_estimator_exact_network_roulette_ablations(rr_mode):
     cl = W.c1()
     gt, ot = build_both(cl.sources, cl.weights)
     check_sbh(gt, ot, cl.queries[:800], P.POTENTIAL, samples=1, seed=7, rr_mode=rr_mode,
-              mlp=dyadic_constant_params(43), max_divergent=3e-3)
+              mlp=dyadic_constant_params(43))
 
 
 @pytest.mark.parametrize("kernel", [P.POTENTIAL, P.WINDING])
@@ -292,7 +290,7 @@ def test_score_proposal_parity(kernel, samples, group):
     else:
         src, nrm, w, q = surface_cloud()
     gt, ot = build_both(src, w, nrm)
-    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=9, group=group, proposal=2, max_divergent=3e-3))
+    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=9, group=group, proposal=2, ))
 
 
 @pytest.mark.parametrize("kind", ["cube", "surface"])
@@ -354,16 +352,14 @@ def test_tile_proposal_parity(kernel, samples, group):
     pts, nrm, w, _ = surface_cloud()
     q = grid_rows(1000)   # 15 full tiles and a ragged one
     gt, ot = build_both(pts, w, nrm)
-    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=11, group=group, alpha=20.0, proposal=3,
-                    max_divergent=3e-3))
+    print(check_sbh(gt, ot, q, kernel, samples=samples, seed=11, group=group, alpha=100.0, proposal=3))
 
 
 def test_tile_proposal_random_queries_and_roulette_modes():
     cl = W.c1()
     gt, ot = build_both(cl.sources, cl.weights)
     for rr in (0, 1, 2):
-        check_sbh(gt, ot, cl.queries[:1300], P.POTENTIAL, samples=1, seed=12, group=64, rr_mode=rr, proposal=3,
-                  max_divergent=3e-3)
+        check_sbh(gt, ot, cl.queries[:1300], P.POTENTIAL, samples=1, seed=12, group=64, rr_mode=rr, proposal=3)
 
 
 def test_tile_proposal_argument_errors():
