@@ -290,6 +290,25 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
                          const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr, int32_t step0,
                          hipStream_t stream, float* losses);
 
+/*
+ * sbh_mlp_train_noalloc - sbh_mlp_train without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * or training loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results (bit for bit) as sbh_mlp_train.  The workspace is a
+ * static array in device memory of (SBH_NOALLOC_MAX_BATCH_ROWS / 64 + 1)
+ * * 1616 floats (about 3.2 MiB), one copy per GPU, held until the process
+ * ends; its address is looked up on the first call on each device.  The
+ * workspace holds no state between calls (every word a call reads it has
+ * written first), but it is shared: calls that overlap in time on one GPU
+ * (on different streams, or from different threads) race and give wrong
+ * results.  Errors: as sbh_mlp_train, and SBH_EINVAL for batch_rows above
+ * SBH_NOALLOC_MAX_BATCH_ROWS; never SBH_ENOMEM.
+ */
+#define SBH_NOALLOC_MAX_BATCH_ROWS 32768
+sbh_status sbh_mlp_train_noalloc(float* params, float* adam_state, const float* features, const float* targets,
+                                 const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr,
+                                 int32_t step0, hipStream_t stream, float* losses);
+
 /* ------------------------------------------------------------------------
  * Batched evaluation: many trees and query sets (of uneven sizes) evaluated
  * by one launch per (branching factor, kernel) group present, replayed from

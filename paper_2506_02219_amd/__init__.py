@@ -86,6 +86,8 @@ def lib():
         L.sbh_mlp_loss_grad.restype = i32
         L.sbh_mlp_train.argtypes = [P, P, P, P, P, i64, i32, i32, f32, i32, P, P]
         L.sbh_mlp_train.restype = i32
+        L.sbh_mlp_train_noalloc.argtypes = [P, P, P, P, P, i64, i32, i32, f32, i32, P, P]
+        L.sbh_mlp_train_noalloc.restype = i32
         L.sbh_batch_create.argtypes = [P, i32, i32, P, P, P, P]
         L.sbh_batch_create.restype = i32
         L.sbh_batch_launch.argtypes = [P, u64, u32, P]
@@ -375,6 +377,32 @@ def sbh_mlp_train(params, adam_state, features, targets, counts, steps, batch_ro
     _check("sbh_mlp_train", lib().sbh_mlp_train(_ptr(params), _ptr(adam_state), _ptr(features), _ptr(targets),
                                                 _ptr(counts), n, int(steps), int(batch_rows), float(lr), int(step0),
                                                 _stream(stream), _ptr(losses)))
+    return losses
+
+
+MLP_NOALLOC_MAX_BATCH_ROWS = 32768
+
+
+def sbh_mlp_train_noalloc(params, adam_state, features, targets, counts, steps, batch_rows=4096, lr=1e-3,
+                          step0=0, losses=None, stream=None):
+    """sbh_mlp_train on the library's static device workspace (sbh_mlp_train_noalloc): no allocation;
+    batch_rows <= MLP_NOALLOC_MAX_BATCH_ROWS; calls overlapping on one GPU race."""
+    _params(params, "params"); _dev(adam_state, "adam_state")
+    if tuple(adam_state.shape) != (2 * MLP_NPARAM,):
+        raise ValueError("adam_state must have shape [2 * MLP_NPARAM]")
+    for t, nm in ((features, "features"), (targets, "targets"), (counts, "counts")):
+        _dev(t, nm, (8,))
+    n = features.shape[0]
+    if targets.shape[0] != n or counts.shape[0] != n:
+        raise ValueError("features, targets and counts must have the same number of rows")
+    if losses is not None:
+        _dev(losses, "losses")
+        if losses.numel() < steps:
+            raise ValueError("losses must hold `steps` values")
+    _check("sbh_mlp_train_noalloc",
+           lib().sbh_mlp_train_noalloc(_ptr(params), _ptr(adam_state), _ptr(features), _ptr(targets), _ptr(counts),
+                                       n, int(steps), int(batch_rows), float(lr), int(step0), _stream(stream),
+                                       _ptr(losses)))
     return losses
 
 

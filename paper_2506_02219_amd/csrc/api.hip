@@ -49,6 +49,36 @@ void free_impl(sbh::sbh_tree_impl* t, hipStream_t s)
 std::mutex g_alloc_mu;
 sbh::Allocator g_alloc{nullptr, nullptr, nullptr};
 
+// The static workspace of sbh_mlp_train_noalloc: the partial gradients of one batch (one row of
+// 1616 floats per 64 rows) and the summed gradient (1616 floats).  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels get the per-device address that hipGetSymbolAddress returns.
+constexpr size_t kScratchFloats = (size_t)(SBH_NOALLOC_MAX_BATCH_ROWS / 64 + 1) * 1616;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device (with that device current).
+hipError_t scratch_ptr(float** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 sbh_status check_kernel(int kernel)
 {
     if (kernel != SBH_POTENTIAL && kernel != SBH_WINDING && kernel != SBH_SMOOTHDIST)
@@ -399,6 +429,37 @@ sbh_status sbh_mlp_train(float* params, float* adam_state, const float* features
     }
     sbh::dev_free(mem, work, wbytes, stream);
     if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train: kernel launch");
+    return SBH_OK;
+}
+
+sbh_status sbh_mlp_train_noalloc(float* params, float* adam_state, const float* features, const float* targets,
+                                 const float* counts, int64_t n, int32_t steps, int32_t batch_rows, float lr,
+                                 int32_t step0, hipStream_t stream, float* losses)
+{
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(SBH_EINVAL, "sbh_mlp_train_noalloc: n must be in [1, 2^31)");
+    if (!params || !adam_state || !features || !targets || !counts)
+        return fail(SBH_EINVAL, "sbh_mlp_train_noalloc: NULL argument");
+    if (steps < 0 || step0 < 0) return fail(SBH_EINVAL, "sbh_mlp_train_noalloc: steps and step0 must be >= 0");
+    if (batch_rows < 1 || batch_rows > SBH_NOALLOC_MAX_BATCH_ROWS)
+        return fail(SBH_EINVAL, "sbh_mlp_train_noalloc: batch_rows must be in [1, %d] (the static workspace)",
+                    SBH_NOALLOC_MAX_BATCH_ROWS);
+    if (!(lr > 0.0f) || !std::isfinite(lr))
+        return fail(SBH_EINVAL, "sbh_mlp_train_noalloc: lr must be finite and > 0");
+    if (steps == 0) return SBH_OK;
+    float* work = nullptr;
+    const hipError_t e0 = scratch_ptr(&work);
+    if (e0 != hipSuccess) return hip_fail(e0, "sbh_mlp_train_noalloc: address of the static workspace");
+    const int64_t b = batch_rows < n ? batch_rows : n;
+    float* grad = work + sbh::mlp_partial_floats(b);
+    hipError_t e = hipSuccess;
+    for (int32_t s = 0; s < steps && e == hipSuccess; ++s) {
+        const int64_t row_begin = ((int64_t)(step0 + s) * b) % n;
+        const int64_t rows = (n - row_begin) < b ? (n - row_begin) : b;
+        e = sbh::launch_mlp_grad(params, features, targets, counts, n, row_begin, rows, work, grad, stream);
+        if (e == hipSuccess)
+            e = sbh::launch_mlp_adam(params, adam_state, grad, lr, step0 + s, losses ? losses + s : nullptr, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "sbh_mlp_train_noalloc: kernel launch");
     return SBH_OK;
 }
 
