@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--train-batch", type=int, default=8192)
     ap.add_argument("--train-lr", type=float, default=2e-3)
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the roulette / branching ablation on c1-c3 (one JSON line of its own)")
     return ap.parse_args()
 
 
@@ -151,8 +153,78 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
+ABLATION_RR = {0: "eq5", 1: "p=1", 2: "p=1/2"}
+
+
+def ablation(args):
+    """The paper's roulette study (Appendix C) and the branching factor (Section 3.3): the estimator
+    with Eq. (5), with p = 1 (no roulette) and with p = 1/2, on trees of branching 2 and 4, on the
+    potential (c1), winding (c2, shuffled plane) and smooth-distance (c3) workloads; one sample per
+    subdomain, G = 64 (the coherent walk).  Time per evaluation of every query (HIP events, median
+    of rounds of K launches) and median relative error against float64 brute force on a fixed
+    sample; accepted steps per path from the kernel's own path records."""
+    import torch
+    import workloads as W
+    import paper_2506_02219_amd as P
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for name in ("c1", "c2", "c3"):
+        cl = getattr(W, name)()
+        kernel = CONFIGS[name]["kernel"]
+        q_np = W.shuffle_queries(cl.queries, 4242)[0] if name == "c2" else cl.queries
+        src = torch.from_numpy(cl.sources).to(dev)
+        wts = torch.from_numpy(cl.weights).to(dev)
+        nrm = None if cl.normals is None else torch.from_numpy(cl.normals).to(dev)
+        qry = torch.from_numpy(q_np).to(dev)
+        N = qry.shape[0]
+        ns = min(N, 8192)
+        sidx = np.sort(np.random.Generator(np.random.PCG64(99)).choice(N, size=ns, replace=False))
+        sidx_t = torch.from_numpy(sidx).to(dev)
+        ref = P.sbh_brute(src, wts, nrm, qry[sidx_t].contiguous(), kernel, fp64=True).cpu().numpy()
+        out = torch.empty(N, dtype=torch.float32, device=dev)
+        for d in (2, 4):
+            tree = P.sbh_build(src, wts, nrm, branching=d, leaf_size=8)
+            for rr in (0, 1, 2):
+                def run(rr=rr):
+                    P.sbh_eval(tree, qry, kernel, samples=1, seed=0, group=64, rr_mode=rr, out=out)
+                for _ in range(2):
+                    run()
+                times = []
+                for _ in range(5):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(args.steps):
+                        run()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1) / args.steps)
+                run()
+                torch.cuda.synchronize()
+                err = float(np.median(rel_errors(out[sidx_t].cpu().numpy(), ref, kernel)))
+                paths = torch.empty((N, d ** 3, 1, 4), dtype=torch.int32, device=dev)
+                P.sbh_eval(tree, qry, kernel, samples=1, seed=0, group=64, rr_mode=rr, out=out, paths=paths)
+                rec = paths.cpu().numpy().reshape(-1, 4)
+                del paths
+                rec = rec[rec[:, 0] >= 0]
+                rows.append(dict(workload=cl.name, kernel=["potential", "winding", "smoothdist"][kernel], queries=N,
+                                 branching=d, roulette=ABLATION_RR[rr], ms=float(np.median(times)),
+                                 median_rel_err=err, accepted_steps_per_path=float(rec[:, 2].mean()),
+                                 # time x error^2: the cost of reaching a fixed error (variance ~ 1/S)
+                                 work_at_unit_variance=float(np.median(times)) * err * err))
+            tree.free()
+    print(json.dumps({"ablation": rows, "samples_per_subdomain": 1, "group": 64, "steps": args.steps,
+                      "git_sha": git_sha(), "csrc_sha256_16": csrc_hash()}))
+
+
 def main():
     args = parse()
+    if args.ablation:
+        if args.gpus != 1:
+            sys.exit(2)
+        ablation(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "queries are independent, so several GPUs would each evaluate a share of them", file=sys.stderr)

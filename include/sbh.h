@@ -62,9 +62,9 @@ typedef enum sbh_proposal {
 } sbh_proposal;
 
 typedef struct sbh_build_opts {
-    int32_t branching;   /* per-dimension branching d: 2 (octree) or 4 (64-way); default 2 */
+    int32_t branching;   /* per-dimension branching d: 2 (octree), 4 (64-way) or 8 (512-way); default 2 */
     int32_t leaf_size;   /* a node is split iff it holds more points than this; 1..64, default 8 */
-    int32_t max_level;   /* deepest level; 0 = 60/(3 log2 d), i.e. 20 for d=2, 10 for d=4 */
+    int32_t max_level;   /* deepest level; 0 = 60/(3 log2 d): 20 for d=2, 10 for d=4, 6 for d=8 */
 } sbh_build_opts;
 
 typedef struct sbh_eval_opts {
@@ -178,7 +178,8 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
  *   eps < 0, alpha <= 0, SBH_WINDING on a tree without normals, proposal
  *   not 0..3, proposal 1 without opts->mlp, proposal 3 with a group that is
  *   not a multiple of 64), SBH_EUNSUPPORTED (proposals 1-3 on a tree with
- *   branching 4), SBH_EHIP.
+ *   branching 4 or 8; on a tree with branching 8, Barnes-Hut and groups
+ *   that are not a multiple of 64), SBH_EHIP.
  *
  *   Learned and score proposals (opts->proposal = 1, 2).  Section 3.3 draws
  *   the path index uniformly and leaves importance sampling open; Theorem 1

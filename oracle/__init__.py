@@ -34,6 +34,8 @@ def lib():
         L.orc_tree_build.argtypes = [P, P, P, i64, i32, i32, i32]
         L.orc_tree_build.restype = P
         L.orc_tree_free.argtypes = [P]
+        L.orc_tree_set_diam_mode.argtypes = [P, i32]
+        L.orc_tree_set_diam_mode.restype = i32
         L.orc_tree_num_nodes.argtypes = [P]
         L.orc_tree_num_nodes.restype = i64
         L.orc_tree_meta.argtypes = [P, P]
@@ -132,6 +134,13 @@ class Tree:
         if h is not None and _lib is not None:
             _lib.orc_tree_free(h)
             self._h = None
+
+    def set_diam_mode(self, mode):
+        """The reading of |B| for a study of the paper's wording (0, the default and the one the
+        GPU implements: the cell diagonal; 1: the cell side; 2: the diagonal of the axis-aligned
+        box of the node's own points, 0 for a single point)."""
+        if lib().orc_tree_set_diam_mode(self._h, int(mode)) != 0:
+            raise ValueError("diam mode must be 0, 1 or 2")
 
     @property
     def internal(self):

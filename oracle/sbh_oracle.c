@@ -169,6 +169,12 @@ typedef struct orc_tree {
     double *mass, *com, *dip; /* com, dip: [n][3] */
     double* spr;              /* second moment sum w |p - com|^2 / mass */
     double diam[64];          /* |B| per level */
+    /* The reading of |B| (a study of the paper's wording; 0 is the one both
+     * sides implement): 0 the cell diagonal, 1 the cell side, 2 the diagonal
+     * of the axis-aligned box of the node's own points (bdiag), under which
+     * a point (a one-point node, or a leaf's virtual child) has |B| = 0. */
+    int diam_mode;
+    double* bdiag;            /* [n] tight-box diagonals, mode 2 only */
 } orc_tree;
 
 static uint64_t spread3(uint32_t v)
@@ -223,7 +229,7 @@ void orc_tree_free(orc_tree* t)
     free(t->pxyz); free(t->pw); free(t->pdip); free(t->perm); free(t->codes);
     free(t->begin); free(t->count); free(t->first_child); free(t->parent);
     free(t->level); free(t->nchild); free(t->digit);
-    free(t->mass); free(t->com); free(t->dip); free(t->spr);
+    free(t->mass); free(t->com); free(t->dip); free(t->spr); free(t->bdiag);
     free(t);
 }
 
@@ -471,6 +477,45 @@ static double dist2(const double a[3], const double q[3])
 
 static double dist3(const double a[3], const double q[3]) { return sqrt(dist2(a, q)); }
 
+/* |B| of node i, and of a virtual child (one point) of leaf i, under the
+ * tree's diameter reading. */
+static double node_diam(const orc_tree* t, int64_t i)
+{
+    if (t->diam_mode == 2) return t->bdiag[i];
+    double c = t->diam[t->level[i]];
+    return t->diam_mode == 1 ? c / sqrt(3.0) : c;
+}
+
+static double point_diam(const orc_tree* t, int64_t leaf)
+{
+    if (t->diam_mode == 2) return 0.0;
+    double c = t->diam[t->level[leaf] + 1];
+    return t->diam_mode == 1 ? c / sqrt(3.0) : c;
+}
+
+/* Switch the tree's reading of |B| (mode as in orc_tree); returns 0 on success. */
+int orc_tree_set_diam_mode(orc_tree* t, int mode)
+{
+    if (mode < 0 || mode > 2) return -1;
+    if (mode == 2 && !t->bdiag) {
+        t->bdiag = malloc(t->n_nodes * sizeof(double));
+        for (int64_t i = 0; i < t->n_nodes; ++i) {
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t s = t->begin[i]; s < t->begin[i] + t->count[i]; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    double x = t->pxyz[3 * s + a];
+                    if (x < lo[a]) lo[a] = x;
+                    if (x > hi[a]) hi[a] = x;
+                }
+            double e2 = 0.0;
+            for (int a = 0; a < 3; ++a) e2 += (hi[a] - lo[a]) * (hi[a] - lo[a]);
+            t->bdiag[i] = sqrt(e2);
+        }
+    }
+    t->diam_mode = mode;
+    return 0;
+}
+
 static double leaf_exact(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
 {
     double s = 0.0;
@@ -491,7 +536,7 @@ static void bh_group(const orc_tree* t, const kparams* kp, int64_t node, const d
     int open = 0;
     *visited += 1;
     for (int g = 0; g < gn; ++g) {
-        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / t->diam[t->level[node]];
+        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / node_diam(t, node);
         double mg = fabs(bt - beta) / beta;
         if (mg < margin[g]) margin[g] = mg;
         if (!(bt >= beta)) open = 1;
@@ -806,8 +851,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         /* uniform path index inside T: offset r in [0, nT) */
         int64_t r = (int64_t)(((uint64_t)x_sel * (uint64_t)nT) >> 32);
         int64_t target = t->begin[T] + r;
-        double diam_c = t->diam[t->level[T] + 1];
-        double bT = dist3(&t->com[3 * T], q) / t->diam[t->level[T]];
+        double bT = dist3(&t->com[3 * T], q) / node_diam(t, T);
         double sum_children = 0.0, abs_children = 0.0, sens_step = node_sens(t, kp, T, q);
         double bc, tc, q_c;
         int64_t c_node = -1;
@@ -837,7 +881,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 q_c = qv[ci];
             }
             c_node = c;
-            bc = dist3(&t->com[3 * c], q) / diam_c;
+            bc = dist3(&t->com[3 * c], q) / node_diam(t, c);
             tc = node_term(t, kp, c, q);
         } else {
             /* leaf with several points: the points are virtual children */
@@ -846,7 +890,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 sum_children += v;
                 abs_children += fabs(v);
             }
-            bc = dist3(&t->pxyz[3 * target], q) / diam_c;
+            bc = dist3(&t->pxyz[3 * target], q) / point_diam(t, T);
             tc = point_term(t, kp, target, q);
             q_c = 1.0 / (double)nT;
         }
@@ -954,8 +998,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
 {
     int64_t nT = t->count[T];
     if (nT == 1) return 0.0;
-    double bT = dist3(&t->com[3 * T], q) / t->diam[t->level[T]];
-    double diam_c = t->diam[t->level[T] + 1];
+    double bT = dist3(&t->com[3 * T], q) / node_diam(t, T);
     double total = 0.0;
     if (is_internal(t, T)) {
         double sum = 0.0;
@@ -967,7 +1010,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         int nonuni = proposal_q(t, prop, T, q, qv, slots, &nk);
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
             double qc = nonuni ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
-            double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / diam_c);
+            double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / node_diam(t, ch));
             double tc = node_term(t, kp, ch, q);
             total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prop));
         }
@@ -977,7 +1020,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         double delta = sum - tT;
         for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) {
             double qc = 1.0 / (double)nT;
-            double pc = rr_prob(rr_mode, bT, dist3(&t->pxyz[3 * s], q) / diam_c);
+            double pc = rr_prob(rr_mode, bT, dist3(&t->pxyz[3 * s], q) / point_diam(t, T));
             total += qc * pc * (delta / (ps * pr * pc));
         }
     }

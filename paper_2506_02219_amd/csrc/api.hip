@@ -185,9 +185,10 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     sbh_build_opts o;
     sbh_build_opts_default(&o);
     if (opts) o = *opts;
-    if (o.branching != 2 && o.branching != 4) return fail(SBH_EINVAL, "sbh_build: branching must be 2 or 4");
+    if (o.branching != 2 && o.branching != 4 && o.branching != 8)
+        return fail(SBH_EINVAL, "sbh_build: branching must be 2, 4 or 8");
     if (o.leaf_size < 1 || o.leaf_size > 64) return fail(SBH_EINVAL, "sbh_build: leaf_size must be in [1, 64]");
-    const int bits = o.branching == 2 ? 3 : 6;
+    const int bits = o.branching == 2 ? 3 : o.branching == 4 ? 6 : 9;
     const int lmax = 60 / bits;
     if (o.max_level < 0 || o.max_level > lmax) return fail(SBH_EINVAL, "sbh_build: max_level must be in [0, %d]", lmax);
     if (o.max_level == 0) o.max_level = lmax;
@@ -243,6 +244,11 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     const bool learned = samples > 0 && (o.proposal == 1 || o.proposal == 2);
     if (samples > 0 && o.proposal != 0 && t->d != 2)
         return fail(SBH_EUNSUPPORTED, "sbh_eval: proposals 1, 2 and 3 need branching 2");
+    // branching 8 (512 children per node): the estimator's coherent walk only
+    if (t->d == 8 && samples == 0)
+        return fail(SBH_EUNSUPPORTED, "sbh_eval: Barnes-Hut needs branching 2 or 4");
+    if (t->d == 8 && o.group % 64 != 0)
+        return fail(SBH_EUNSUPPORTED, "sbh_eval: branching 8 needs group a multiple of 64");
     e.tile_score = (samples > 0 && o.proposal == 3) ? 1 : 0;
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;

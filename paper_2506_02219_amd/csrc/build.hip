@@ -650,7 +650,7 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         if (tmp.err != hipSuccess) return fail_hip(tmp.err, where); \
     } while (0)
 
-    const int lg = d == 2 ? 1 : 2;
+    const int lg = d == 2 ? 1 : d == 4 ? 2 : 3;
     const int bits = 3 * lg;
     const int d3 = d * d * d;
     const int ts = topo_stride(d3);

@@ -775,12 +775,12 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
                 }
             } else {
-#pragma unroll 8
+                // only the other non-empty slots, behind wavefront-uniform branches (a surface
+                // fills a few of a node's 64 or 512 slots)
                 for (int c = 0; c < D3; ++c) {
-                    const uint32_t cnt = gld(bt + c);
+                    if (gld(bt + c) == 0u || c == csel) continue;
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
-                    sumc = (cnt && c != csel) ? v : sumc;
+                    sumc = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
                 }
             }
             // the lanes the roulette keeps take the step (selects, not a branch)
@@ -1434,7 +1434,7 @@ template <int D, int K>
 static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
                                 hipStream_t s)
 {
-    constexpr int QPW = 64 / (D * D * D);
+    constexpr int QPW = D == 8 ? 1 : 64 / (D * D * D);
     SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
               e.eps * e.eps, e.alpha, e.paths};
     if (e.group % 64 == 0) {
@@ -1462,7 +1462,9 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
         }
         return hipGetLastError();
     }
-    if ((int64_t)D * D * D * e.samples <= kPoolPaths) {
+    if constexpr (D == 8) {
+        return hipErrorInvalidValue;   // branching 8: the coherent walk only (the API checks G)
+    } else if ((int64_t)D * D * D * e.samples <= kPoolPaths) {
         // per-lane walks with lane refill: Q queries per wavefront, four wavefronts per block
         const int64_t qpw = kPoolPaths / (D * D * D * e.samples);
         const int64_t waves = (nq + qpw - 1) / qpw;
@@ -1470,12 +1472,13 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
         if (e.paths) k_sbh_pool<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
         else k_sbh_pool<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
         return hipGetLastError();
+    } else {
+        const int64_t waves = (nq + QPW - 1) / QPW;
+        const unsigned blocks = (unsigned)((waves + 3) / 4);
+        if (e.paths) k_sbh<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        else k_sbh<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
+        return hipGetLastError();
     }
-    const int64_t waves = (nq + QPW - 1) / QPW;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    if (e.paths) k_sbh<D, K, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
-    else k_sbh<D, K, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out);
-    return hipGetLastError();
 }
 
 template <int D, int K>
@@ -1509,6 +1512,11 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
         if (e.kernel == SBH_POTENTIAL) return launch_leaf<SBH_POTENTIAL>(tv, queries, nq, e, out, s);
         if (e.kernel == SBH_WINDING) return launch_leaf<SBH_WINDING>(tv, queries, nq, e, out, s);
         return launch_leaf<SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
+    }
+    if (t->d == 8) {
+        if (e.kernel == SBH_POTENTIAL) return launch_sbh_dk<8, SBH_POTENTIAL>(tv, queries, nq, e, out, s);
+        if (e.kernel == SBH_WINDING) return launch_sbh_dk<8, SBH_WINDING>(tv, queries, nq, e, out, s);
+        return launch_sbh_dk<8, SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
     }
     SBH_DISPATCH(launch_sbh_dk, t, tv, queries, nq, e, out, s);
 }

@@ -245,6 +245,14 @@ constexpr float kSmoothShiftMargin = 30.0f;
 // unbiased.  Cells follow the tree's quantisation (a level-l cell of side
 // side / d^l); d = 4 digits hold two octree digits, the higher one in bits
 // 3..5.
+// The cell index along axis a (0 = x) of the child in slot c: a slot of a
+// d = 2^g tree holds g octree digits (3 bits each, the coarser ones higher),
+// whose bit a is that axis' bit at that level.
+__device__ __forceinline__ int digit_axis(int c, int a)
+{
+    return ((c >> a) & 1) | ((c >> (a + 2)) & 2) | ((c >> (a + 4)) & 4);
+}
+
 template <int D>
 __device__ __forceinline__ float smooth_shift(const TreeView& tv, float qx, float qy, float qz, float alpha)
 {
@@ -273,9 +281,7 @@ __device__ __forceinline__ float smooth_shift(const TreeView& tv, float qx, floa
         int c_b = 0, nint = 0, nint_b = 0;
         for (int c = 0; c < D3; ++c) {
             const uint32_t cnt = gld(bt + c);
-            const int ix = D == 2 ? (c & 1) : ((c >> 2) & 2) | (c & 1);
-            const int iy = D == 2 ? ((c >> 1) & 1) : ((c >> 3) & 2) | ((c >> 1) & 1);
-            const int iz = D == 2 ? ((c >> 2) & 1) : ((c >> 4) & 2) | ((c >> 2) & 1);
+            const int ix = digit_axis(c, 0), iy = digit_axis(c, 1), iz = digit_axis(c, 2);
             const float d2 = dd[0][ix] + dd[1][iy] + dd[2][iz];
             if (cnt != 0u && d2 < best) {
                 best = d2;
@@ -287,9 +293,7 @@ __device__ __forceinline__ float smooth_shift(const TreeView& tv, float qx, floa
             nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
             pre += cnt;
         }
-        const int ix = D == 2 ? (c_b & 1) : ((c_b >> 2) & 2) | (c_b & 1);
-        const int iy = D == 2 ? ((c_b >> 1) & 1) : ((c_b >> 3) & 2) | ((c_b >> 1) & 1);
-        const int iz = D == 2 ? ((c_b >> 2) & 1) : ((c_b >> 4) & 2) | ((c_b >> 2) & 1);
+        const int ix = digit_axis(c_b, 0), iy = digit_axis(c_b, 1), iz = digit_axis(c_b, 2);
         cl[0] += (float)ix * hs;
         cl[1] += (float)iy * hs;
         cl[2] += (float)iz * hs;

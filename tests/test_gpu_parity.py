@@ -42,14 +42,14 @@ def test_brute_matches_oracle(kernel):
 
 
 # ----------------------------------------------------------------------------- tree
-@pytest.mark.parametrize("d", [2, 4])
+@pytest.mark.parametrize("d", [2, 4, 8])
 def test_tree_bit_exact_c1(d):
     c = W.c1()
     gt, ot = build_both(c.sources, c.weights, d=d)
     compare_trees(gt, ot)
 
 
-@pytest.mark.parametrize("d,leaf", [(2, 8), (4, 8), (2, 1)])
+@pytest.mark.parametrize("d,leaf", [(2, 8), (4, 8), (2, 1), (8, 8)])
 def test_tree_bit_exact_surface(d, leaf):
     src, nrm, w = surface(50000, 5)
     gt, ot = build_both(src, w, nrm, d=d, leaf_size=leaf)
@@ -59,7 +59,7 @@ def test_tree_bit_exact_surface(d, leaf):
 def test_tree_duplicates_and_max_level():
     src = np.array([[0.3, 0.3, 0.3]] * 40 + [[0, 0, 0], [1, 1, 1]] + [[0.7, 0.2, 0.9]] * 3, np.float32)
     w = np.linspace(0.5, 1.5, len(src)).astype(np.float32)
-    for d, ml in ((2, 0), (2, 5), (4, 3)):
+    for d, ml in ((2, 0), (2, 5), (4, 3), (8, 0), (8, 2)):
         gt, ot = build_both(src, w, d=d, leaf_size=4, max_level=ml)
         compare_trees(gt, ot)
 
@@ -176,6 +176,36 @@ def test_duplicate_points_estimator():
     q = box_queries(500, 8, -0.5, 1.5)
     gt, ot = build_both(src, w, d=2, leaf_size=4, max_level=6)
     check_sbh(gt, ot, q, P.POTENTIAL, samples=2)
+
+
+# ----------------------------------------------------------------------------- branching 8
+@pytest.mark.parametrize("S,rr", [(1, 0), (2, 0), (1, 1), (1, 2)])
+def test_sbh_parity_branching8_c1(S, rr):
+    """Branching 8 (512 children per node, the largest factor of the paper's branching study): the
+    coherent walk (G a multiple of 64) against the oracle."""
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights, d=8)
+    print(check_sbh(gt, ot, c.queries[:2000], P.POTENTIAL, samples=S, seed=3, group=64, rr_mode=rr))
+
+
+@pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST])
+def test_sbh_parity_branching8_surface(kernel):
+    src, nrm, w = surface(30000, 9)
+    q = box_queries(1000, 4)
+    gt, ot = build_both(src, w, nrm, d=8)
+    print(check_sbh(gt, ot, q, kernel, samples=1, seed=123, alpha=100.0, group=128))
+
+
+def test_branching8_limits():
+    c = W.c1()
+    gt = P.sbh_build(T(c.sources), T(c.weights), branching=8)
+    q = T(c.queries[:100])
+    with pytest.raises(P.SbhError, match="EUNSUPPORTED"):
+        P.sbh_eval(gt, q, P.POTENTIAL, samples=1, group=1)         # per-query streams: branching 2 and 4
+    with pytest.raises(P.SbhError, match="EUNSUPPORTED"):
+        P.sbh_eval(gt, q, P.POTENTIAL, samples=0, beta=2.0)       # Barnes-Hut: branching 2 and 4
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_build(T(c.sources), T(c.weights), branching=3)
 
 
 def test_argument_errors():
