@@ -571,6 +571,12 @@ __device__ __forceinline__ const T* at_off(const T* base, O byte_off)
     return (const T*)((const char*)base + byte_off);
 }
 
+// the value lane c holds, as a wavefront-uniform scalar
+__device__ __forceinline__ float rdlane(float v, int c)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
+}
+
 __device__ __forceinline__ float vmax(float a, float b)
 {
     float r;
@@ -698,6 +704,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         int32_t blkC = 0;
         int csel = 0;
         uint32_t nonempty = 0u;   // d = 2: slots with points (wavefront-uniform)
+        uint64_t nonempty64 = 0ull;   // d = 4
         if constexpr (D == 2) {
             // child selection across lanes 0..7 (one slot each): an exclusive scan of the
             // counts by DPP row shifts, then ballots give the slot whose range holds r, the
@@ -720,6 +727,32 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
             nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
             const int32_t nintC = __popc(im & ((1u << csel) - 1u));
+            aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
+            if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
+            beginC = beginT + preC;
+            blkC = (int32_t)gld(bt + D3) + nintC;
+        } else if constexpr (D == 4) {
+            // 64 slots, one per lane: an inclusive scan of the counts across the wavefront
+            // (row shifts within rows of 16 lanes, then the row broadcasts of lanes 15 and 31),
+            // and ballots give the slot whose range holds r, the internal slots before it and
+            // the non-empty slots
+            const int ln = threadIdx.x & 63;
+            const uint32_t cl = gld(bt + ln);
+            uint32_t inc = cl;
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x118, 0xF, 0xF, false);   // row_shr:8
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x142, 0xA, 0xF, false);   // row_bcast:15
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x143, 0xC, 0xF, false);   // row_bcast:31
+            const uint32_t excl = inc - cl;
+            const uint64_t hm = __ballot((r - excl) < cl);
+            const uint64_t im = level < lvl_int ? __ballot((int)cl > tv.leaf_size) : 0ull;
+            nonempty64 = __ballot(cl != 0u);
+            csel = (int)__builtin_ctzll(hm);
+            const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+            nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+            const int32_t nintC = (int32_t)__popcll(im & ((1ull << csel) - 1ull));
             aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
             if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
             beginC = beginT + preC;
@@ -774,9 +807,27 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                     sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
                 }
+            } else if constexpr (D == 4) {
+                // the block in one coalesced load (lane c holds slot c), then the other non-empty
+                // slots (a surface fills a few of the 64) in turn, each broadcast from its lane
+                const int ln = threadIdx.x & 63;
+                const float4 gl = gld4(ba + ln);
+                const float4 gdl = (K == SBH_WINDING) ? gld4(bd + ln) : zero4;
+                uint64_t rest = nonempty64 & ~(1ull << csel);
+                while (rest) {
+                    const int c = (int)__builtin_ctzll(rest);
+                    rest &= rest - 1ull;
+                    const float4 g = make_float4(rdlane(gl.x, c), rdlane(gl.y, c),
+                                                 rdlane(gl.z, c), rdlane(gl.w, c));
+                    float4 gd = zero4;
+                    if constexpr (K == SBH_WINDING)
+                        gd = make_float4(rdlane(gdl.x, c), rdlane(gdl.y, c),
+                                         rdlane(gdl.z, c), 0.0f);
+                    sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
+                }
             } else {
                 // only the other non-empty slots, behind wavefront-uniform branches (a surface
-                // fills a few of a node's 64 or 512 slots)
+                // fills a few of a node's 512 slots)
                 for (int c = 0; c < D3; ++c) {
                     if (gld(bt + c) == 0u || c == csel) continue;
                     const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
@@ -932,7 +983,6 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
         if (internal) {
             const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);
             const float4* __restrict__ ba = at_off(tv.bagg, boff);
-            const float4* __restrict__ bd = at_off(tv.bdip, boff);
             const float* __restrict__ bs = at_off(tv.bspr, (Off)(uint32_t)blk * (Off)(D3 * 4));
             const uint32_t* __restrict__ bt = at_off(tv.btopo, (Off)(uint32_t)blk * (Off)(TS * 4));
             // counts in lanes 0..7 (lanes 8..63 read the row's zero padding word)
