@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched evaluation")
     ap.add_argument("--no-grid", action="store_true", help="skip the estimator on the plane's original order")
+    ap.add_argument("--no-cut", action="store_true", help="skip the Barnes-Hut-cut subdomains")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -460,6 +461,15 @@ def main():
             ms_s = timed(lambda: run_sbh(tree, sv), 3, 1)
             sweep.append(dict(samples=sv, ms=ms_s, median_rel_err=err_of(lambda: run_sbh(tree, sv))))
 
+    # --- subdomains from the Barnes-Hut cut D(q, beta_low) (Section 3.3.1), on the headline's queries
+    cut = None
+    if not args.no_cut and args.group % 64 == 0 and args.branching in (2, 4):
+        cut = dict(group=args.group, sweep=[])
+        for bl in (0.3, 0.5, 0.8):
+            def run_cut(bl=bl):
+                P.sbh_eval(tree, qry, kernel, beta=bl, samples=S, seed=0, group=args.group, out=out, subdomains=1)
+            cut["sweep"].append(dict(beta_low=bl, ms=timed(run_cut, 5, 1), median_rel_err=err_of(run_cut)))
+
     # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
     # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
     # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
@@ -467,6 +477,9 @@ def main():
     bh = None
     if not args.no_bh:
         bh_tree = tree if args.bh_branching == args.branching else build(args.bh_branching)[0]
+
+        # sweep until Barnes-Hut is well below every error it is compared at
+        e_floor = min([err_star] + ([c_["median_rel_err"] for c_ in cut["sweep"]] if cut else []))
 
         def bh_sweep(qset, idx_t):
             pts = []
@@ -476,7 +489,7 @@ def main():
                 ms = timed(run, 3, 1)
                 e = err_of(run, idx_t)
                 pts.append((beta, ms, e))
-                if e < err_star / 4 and len(pts) > 2:
+                if e < e_floor / 4 and len(pts) > 2:
                     break
             return pts
 
@@ -505,6 +518,11 @@ def main():
             tb = at_error(pts_g, e1)[0]
             tile_grid["bh_ms_at_this_error"] = tb
             tile_grid["speedup_vs_bh_at_this_error"] = None if tb is None else tb / tile_grid["sweep"][0]["ms"]
+        if cut is not None:
+            for c_ in cut["sweep"]:
+                tb = at_error(pts_s, c_["median_rel_err"])[0]
+                c_["bh_ms_at_this_error"] = tb
+                c_["speedup_vs_bh_at_this_error"] = None if tb is None else tb / c_["ms"]
         if grid_order is not None:
             tb = at_error(pts_g, grid_order["median_rel_err"])[0]
             grid_order["bh_ms_at_this_error"] = tb
@@ -709,6 +727,7 @@ def main():
         "other_stream_mode": other,
         "grid_order": grid_order,
         "tile_score_grid_order": tile_grid,
+        "cut_subdomains": cut,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

@@ -88,6 +88,15 @@ typedef struct sbh_eval_opts {
     const float* mlp;    /* DEVICE [SBH_MLP_NPARAM] network parameters for proposal 1; default NULL.
                             Parameters that are not all finite are ignored: the kernel then
                             uses the score proposal (the zero network). */
+    int32_t subdomains;  /* path roots (Section 3.3.1): 0 = the root's children (default);
+                            1 = the Barnes-Hut cut D(q, beta) with beta = sbh_eval's beta:
+                            walking from the root, a node that every query of the wavefront
+                            (64 consecutive queries) sees as far (|q - com| / |B| >= beta) is
+                            a subdomain; a node that is not far is opened, a leaf summed
+                            exactly.  1 needs group a multiple of 64, the uniform proposal and
+                            branching 2 or 4; paths, if given, is then [nq][4] int32: {subdomains,
+                            leaves summed exactly, accepted steps of all paths, sum of their
+                            end levels}. */
 } sbh_eval_opts;
 
 typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */

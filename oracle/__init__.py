@@ -43,6 +43,8 @@ def lib():
         L.orc_bh.argtypes = [P, P, i64, i32, f64, f64, f64, i32, P, P, P, i32]
         L.orc_sbh.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, i32, P, P, P, i64, P, P, P, P, P, i32]
         L.orc_sbh_expect.argtypes = [P, P, i64, i32, f64, f64, i32, P, i32, P, i32]
+        L.orc_sbh_cut.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, i32, u32, i32, f64, P, i32, P, P, P, P,
+                                  P, i32]
         L.orc_term_sens.argtypes = [i32, f64, f64, P, f64, P, P, P]
         L.orc_refine_all.argtypes = [P, P, i64, i32, f64, f64, P]
         L.orc_mlp_nparam.restype = i32
@@ -172,6 +174,21 @@ class Tree:
         if paths:
             r["paths"] = pth
         return r
+
+    def sbh_cut(self, queries, kernel, beta_low, samples=1, seed=0, group=64, vote=64, batch=0, rr_mode=0,
+                eps=1e-3, alpha=100.0, index=None, expect=False, threads=0):
+        """The estimator stratified by the Barnes-Hut cut D(q, beta_low), voted over groups of `vote`
+        consecutive queries (Section 3.3.1); returns dict(F, margin, absum, sens, digest [n, 4]:
+        subdomains, leaves summed exactly, accepted steps, sum of end levels).  expect: the exact
+        expectation (Theorem 1) instead of a sample."""
+        q = _f32(queries, (-1, 3)); n = q.shape[0]
+        idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
+        out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n); sn = np.zeros(n)
+        dg = np.zeros((n, 4), np.int32)
+        lib().orc_sbh_cut(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, vote, batch, rr_mode,
+                          float(beta_low), _p(idx), int(bool(expect)), _p(out), _p(mg), _p(ab), _p(sn), _p(dg),
+                          threads)
+        return dict(F=out, margin=mg, absum=ab, sens=sn, digest=dg)
 
     def expect(self, queries, kernel, rr_mode=0, eps=1e-3, alpha=100.0, params=None, tiles=False, threads=0):
         """Exact expectation of the one-sample estimator (Theorem 1), optionally with the learned

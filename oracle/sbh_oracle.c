@@ -830,8 +830,8 @@ typedef struct {
 /* One path sample rooted at subdomain node `a` (Algorithm 2, inner loop).
  * counter = (sigma, a_slot*S + s, step/2, batch), key = (seed lo, seed hi). */
 static path_out sample_path(const orc_tree* t, const kparams* kp, const double q[3], int64_t a,
-                            uint32_t sigma, uint32_t stream2, uint32_t batch, uint64_t seed, int rr_mode,
-                            const proposal* prop)
+                            uint32_t sigma, uint32_t stream2, uint32_t ctr2_base, uint32_t batch, uint64_t seed,
+                            int rr_mode, const proposal* prop)
 {
     path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
@@ -844,7 +844,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         po.end_begin = (int32_t)t->begin[T];
         po.end_level = t->level[T];
         if (nT == 1) { po.flags = 1; break; }   /* a one-point leaf: nothing left to refine */
-        uint32_t ctr[4] = {sigma, stream2, (uint32_t)(k >> 1), batch}, rnd[4];
+        uint32_t ctr[4] = {sigma, stream2, ctr2_base + (uint32_t)(k >> 1), batch}, rnd[4];
         orc_philox4x32_10(ctr, key, rnd);
         uint32_t x_sel = rnd[2 * (k & 1)], x_rr = rnd[2 * (k & 1) + 1];
         double u_rr = (double)(x_rr >> 8) * (1.0 / 16777216.0);
@@ -962,7 +962,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
                 double cv = node_term(t, &kp, a, q);     /* control variate CV_a */
                 double Fa = 0.0, Aa = 0.0, Sa = 0.0;
                 for (int s = 0; s < S; ++s) {
-                    path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), batch, seed, rr_mode,
+                    path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), 0u, batch, seed, rr_mode,
                                               &prop);
                     Fa += po.value;
                     Aa += po.absum;
@@ -982,6 +982,131 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
         if (min_margin) min_margin[j] = mg;
         if (absum) absum[j] = A;
         if (sens) sens[j] = SN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stratification by a Barnes-Hut cut (Section 3.3.1 names the contribution */
+/* nodes D(q, beta) of a low beta as an alternative to the root's children   */
+/* as path roots).  The cut is voted over groups of `vote` consecutive       */
+/* queries, as Barnes-Hut's is: walking from the root, a node is a subdomain */
+/* when every query of the group has far-field ratio >= beta_low; otherwise  */
+/* an internal node is opened and a leaf is summed exactly.  Each subdomain a */
+/* contributes its control variate m_a f(p_a, q) plus the mean of S path     */
+/* samples rooted at a (Algorithm 2's inner loop).  The subdomains cover     */
+/* every point once, so Theorem 1 applies to each and the sum is unbiased.   */
+/* Random numbers: the path from subdomain a (first point b_a, level l_a),   */
+/* sample s, step k draws from the Philox block with counter                 */
+/* (stream id, b_a, l_a 2^24 + s 2^16 + floor(k/2), batch).                  */
+/* Digest per query: {subdomains, leaves summed exactly, accepted steps over */
+/* all paths, sum of the paths' end levels}.                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double F, A, SN, mg;
+    int32_t dig[4];
+} cut_acc;
+
+static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3], int64_t T, double tT,
+                         double ps, double pr, int rr_mode, const proposal* prop);
+
+static void cut_group(const orc_tree* t, const kparams* kp, int64_t node, const double* qs, const uint32_t* sig,
+                      int gn, double beta_low, int S, uint64_t seed, uint32_t batch, int rr_mode, int expect,
+                      cut_acc* acc)
+{
+    int open = 0;
+    for (int g = 0; g < gn; ++g) {
+        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / node_diam(t, node);
+        if (!(bt >= beta_low)) open = 1;
+    }
+    if (!open) {
+        for (int g = 0; g < gn; ++g) {
+            const double* q = &qs[3 * g];
+            double cv = node_term(t, kp, node, q);
+            cut_acc* A = &acc[g];
+            A->dig[0] += 1;
+            if (expect) {   /* the exact expectation of the subdomain's paths (Theorem 1) */
+                A->F += cv + (t->count[node] > 1 ? expect_rec(t, kp, q, node, cv, 1.0, 1.0, rr_mode, NULL) : 0.0);
+                continue;
+            }
+            double Fa = 0.0, Aa = 0.0, Sa = 0.0;
+            for (int s = 0; s < S; ++s) {
+                uint32_t c2 = ((uint32_t)t->level[node] << 24) | ((uint32_t)s << 16);
+                path_out po = sample_path(t, kp, q, node, sig[g], (uint32_t)t->begin[node], c2, batch, seed, rr_mode,
+                                          NULL);
+                Fa += po.value;
+                Aa += po.absum;
+                Sa += po.sens;
+                if (po.margin < A->mg) A->mg = po.margin;
+                A->dig[2] += po.steps;
+                A->dig[3] += po.end_level;
+            }
+            A->F += cv + Fa / S;
+            A->A += fabs(cv) + Aa / S;
+            A->SN += node_sens(t, kp, node, q) + Sa / S;
+        }
+        return;
+    }
+    if (!is_internal(t, node)) {
+        for (int g = 0; g < gn; ++g) {
+            double v = leaf_exact(t, kp, node, &qs[3 * g]);
+            acc[g].F += v;
+            acc[g].A += fabs(v);
+            acc[g].dig[1] += 1;
+        }
+        return;
+    }
+    for (int c = 0; c < t->nchild[node]; ++c)
+        cut_group(t, kp, t->first_child[node] + c, qs, sig, gn, beta_low, S, seed, batch, rr_mode, expect, acc);
+}
+
+/* The cut-stratified estimator for n queries; stream id of query j is
+ * floor(qindex[j] / G) (qindex NULL: j); votes over groups of `vote`
+ * consecutive queries of the given set.  expect != 0: the exact expectation
+ * instead of a sample. */
+void orc_sbh_cut(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha, int S,
+                 uint64_t seed, int G, int vote, uint32_t batch, int rr_mode, double beta_low, const int64_t* qindex,
+                 int expect, double* out, double* min_margin, double* absum, double* sens, int32_t* digest,
+                 int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+    if (G < 1) G = 1;
+    if (vote < 1) vote = 1;
+    int64_t ng = (n + vote - 1) / vote;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t gi = 0; gi < ng; ++gi) {
+        int64_t j0 = gi * vote;
+        int gn = (int)((n - j0 < vote) ? (n - j0) : vote);
+        double* qs = malloc(3 * gn * sizeof(double));
+        uint32_t* sig = malloc(gn * sizeof(uint32_t));
+        cut_acc* acc = calloc(gn, sizeof(cut_acc));
+        for (int g = 0; g < gn; ++g) {
+            for (int a = 0; a < 3; ++a) qs[3 * g + a] = qry[3 * (j0 + g) + a];
+            int64_t jj = qindex ? qindex[j0 + g] : j0 + g;
+            sig[g] = (uint32_t)(jj / G);
+            acc[g].mg = INFINITY;
+        }
+        if (!is_internal(t, 0)) {
+            for (int g = 0; g < gn; ++g) {
+                acc[g].F = leaf_exact(t, &kp, 0, &qs[3 * g]);
+                acc[g].A = fabs(acc[g].F);
+                acc[g].dig[1] = 1;
+            }
+        } else {
+            for (int c = 0; c < t->nchild[0]; ++c)
+                cut_group(t, &kp, t->first_child[0] + c, qs, sig, gn, beta_low, S, seed, batch, rr_mode, expect, acc);
+        }
+        for (int g = 0; g < gn; ++g) {
+            out[j0 + g] = acc[g].F;
+            if (min_margin) min_margin[j0 + g] = acc[g].mg;
+            if (absum) absum[j0 + g] = acc[g].A;
+            if (sens) sens[j0 + g] = acc[g].SN;
+            if (digest)
+                for (int k = 0; k < 4; ++k) digest[4 * (j0 + g) + k] = acc[g].dig[k];
+        }
+        free(qs); free(sig); free(acc);
     }
 }
 

@@ -27,7 +27,8 @@ class BuildOpts(C.Structure):
 
 class EvalOpts(C.Structure):
     _fields_ = [("eps", C.c_float), ("alpha", C.c_float), ("group", C.c_int32), ("rr_mode", C.c_int32),
-                ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p)]
+                ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p),
+                ("subdomains", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -255,9 +256,11 @@ def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_leve
 
 
 def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
-             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None):
+             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None, subdomains=0):
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
-    paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records;
+    subdomains: 0 the root's children, 1 the Barnes-Hut cut at beta (group a multiple of 64);
+    paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records ([nq, 4]
+    digests with subdomains = 1);
     mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal (1);
     proposal: 0 uniform path index, 1 learned (needs mlp; parameters that are not all finite fall back
     to the score proposal), 2 score proposal, 3 tile-shared score proposal (group a multiple of 64)
@@ -270,8 +273,9 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
     _dev(out, "out")
     if paths is not None:
         _dev(paths, "paths", dtype=torch.int32)
-        if tuple(paths.shape) != (nq, tree.branching ** 3, max(samples, 1), 4):
-            raise ValueError("paths must have shape [nq, d^3, samples, 4]")
+        want = (nq, 4) if subdomains == 1 else (nq, tree.branching ** 3, max(samples, 1), 4)
+        if tuple(paths.shape) != want:
+            raise ValueError(f"paths must have shape {list(want)}")
     if mlp is not None:
         _dev(mlp, "mlp")
         if tuple(mlp.shape) != (MLP_NPARAM,):
@@ -279,7 +283,8 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
     if proposal is None:
         proposal = 0 if mlp is None else 1
     o = EvalOpts(eps, alpha, group, rr_mode, int(proposal), batch,
-                 None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr())
+                 None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr(),
+                 int(subdomains))
     _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
                                       C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
     return out

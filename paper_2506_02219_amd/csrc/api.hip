@@ -96,6 +96,9 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (o.proposal == 3 && o.group % 64 != 0)
         return fail(SBH_EINVAL, "the tile-shared score proposal needs group a multiple of 64");
     if (o.proposal == 1 && !o.mlp) return fail(SBH_EINVAL, "the learned proposal needs opts->mlp");
+    if (o.subdomains < 0 || o.subdomains > 1) return fail(SBH_EINVAL, "subdomains must be 0 or 1");
+    if (o.subdomains == 1 && (o.group % 64 != 0 || o.proposal != 0))
+        return fail(SBH_EINVAL, "Barnes-Hut-cut subdomains need group a multiple of 64 and the uniform proposal");
     return SBH_OK;
 }
 
@@ -158,6 +161,7 @@ void sbh_eval_opts_default(sbh_eval_opts* o)
     o->batch = 0;
     o->paths = nullptr;
     o->mlp = nullptr;
+    o->subdomains = 0;
 }
 
 const char* sbh_status_string(sbh_status s)
@@ -250,6 +254,10 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     if (t->d == 8 && o.group % 64 != 0)
         return fail(SBH_EUNSUPPORTED, "sbh_eval: branching 8 needs group a multiple of 64");
     e.tile_score = (samples > 0 && o.proposal == 3) ? 1 : 0;
+    e.cut = (samples > 0 && o.subdomains == 1) ? 1 : 0;
+    if (e.cut && !(beta > 0.0f && std::isfinite(beta)))
+        return fail(SBH_EINVAL, "sbh_eval: Barnes-Hut-cut subdomains need a finite beta > 0");
+    if (e.cut && t->d == 8) return fail(SBH_EUNSUPPORTED, "sbh_eval: Barnes-Hut-cut subdomains need branching 2 or 4");
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;
     if (samples == 0) err = sbh::launch_bh_eval(t, queries, nq, e, out, stream);
@@ -590,6 +598,7 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     o.group = 64;
     if (opts) o = *opts;
     if (check_eval_opts(o) != SBH_OK) return SBH_EINVAL;
+    if (o.subdomains != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: batches take the root's children as subdomains");
     if (o.group % 64 != 0) return fail(SBH_EINVAL, "sbh_batch_create: group must be a multiple of 64");
     if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: only the uniform proposal is batched");
     if (o.paths) return fail(SBH_EINVAL, "sbh_batch_create: path records are not available in a batch");

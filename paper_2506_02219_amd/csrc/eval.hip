@@ -637,12 +637,45 @@ struct PathWords {
     }
 };
 
-template <int D, int K, bool TRACE, bool O64>
+// The words of one path only (the Barnes-Hut-cut subdomains, which are found
+// one at a time): lane l holds the block of step pair l, for steps 0..127
+// (deeper than any tree), its roulette words converted.
+struct PathWordsOne {
+    u32x4 vr;
+    __device__ __forceinline__ void compute(uint32_t ctr0, uint32_t ctr1, uint32_t ctr2_base, uint32_t ctr3,
+                                            uint32_t key0, uint32_t key1)
+    {
+        vr = philox4x32_10(ctr0, ctr1, ctr2_base + (threadIdx.x & 63u), ctr3, key0, key1);
+        vr.y = __float_as_uint(unit24(vr.y));
+        vr.w = __float_as_uint(unit24(vr.w));
+    }
+    __device__ __forceinline__ void step(int k, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t& xsel,
+                                         float& u) const
+    {
+        xsel = __builtin_amdgcn_readlane((k & 1) ? vr.z : vr.x, k >> 1);
+        u = __uint_as_float(__builtin_amdgcn_readlane((k & 1) ? vr.w : vr.y, k >> 1));
+    }
+    template <bool ODD>
+    __device__ __forceinline__ void step_held(int k, uint32_t, uint32_t& xsel, float& u) const
+    {
+        xsel = __builtin_amdgcn_readlane(ODD ? vr.z : vr.x, k >> 1);
+        u = __uint_as_float(__builtin_amdgcn_readlane(ODD ? vr.w : vr.y, k >> 1));
+    }
+    __device__ __forceinline__ void step_late(int k, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t& xsel,
+                                              float& u) const
+    {
+        step(k, 0u, 0u, 0u, 0u, 0u, xsel, u);
+    }
+};
+
+// One path of the coherent walk from subdomain node a (n_a points from begin_a, at
+// level level_a; blk_a its child block when internal), for the wavefront's 64 queries.
+template <int D, int K, bool TRACE, bool O64, class PW = PathWords>
 __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
                                            const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
-                                           int32_t blk_a, float4 agg_a, float t_a, const PathWords& pw,
+                                           int32_t blk_a, float4 agg_a, float t_a, const PW& pw,
                                            uint32_t ctr0, uint32_t ctr1, uint32_t ctr3, uint32_t key0,
-                                           uint32_t key1, int rr_mode, int4* rec)
+                                           uint32_t key1, int rr_mode, int4* rec, int level_a = 1)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
@@ -653,8 +686,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // wavefront-uniform walk state
     uint32_t nT = n_a, beginT = begin_a;
     int32_t blk = blk_a;
-    int level = 1;
-    float diamT = tv.diam0 * kInvD;
+    int level = level_a;
+    float diamT = ldexpf(tv.diam0, -level_a * (D == 2 ? 1 : D == 4 ? 2 : 3));
     const float fna = (float)n_a;
     // per-lane state; actm holds the lanes still walking (wavefront-uniform): a lane's own
     // flag is its bit, so that the votes below are single compares and no per-lane flag is
@@ -1373,6 +1406,129 @@ __global__ void __launch_bounds__(256) k_bh(TreeView tv, const float* __restrict
     if (valid) out[j] = query_value<K>(acc, r0, logwbar, a.alpha, qx, qy, qz);
 }
 
+// Stratification by a Barnes-Hut cut (Section 3.3.1 names the contribution
+// nodes D(q, beta) of a low beta as path roots in place of the root's
+// children).  One wavefront per 64 consecutive queries walks the tree
+// depth-first as Barnes-Hut does (uniform LDS stack, scalar block loads): a
+// child that every valid query of the wavefront sees as far (far-field ratio
+// >= beta_low) is a subdomain, whose control variate and S coherent path
+// samples (wave_path from that node) are added at once; a child that is not
+// far is opened when internal and summed exactly when a leaf.  Random words of
+// the path from subdomain a (first point b_a, level l_a), sample s: the Philox
+// blocks with counter (stream id, b_a, l_a 2^24 + s 2^16 + step pair, batch).
+// With TRACE, paths[j] receives {subdomains, leaves summed exactly, accepted
+// steps, sum of end levels} of query j.
+template <int D, int K, bool TRACE, bool O64>
+__global__ void __launch_bounds__(256) k_sbh_cut(TreeView tv, const float* __restrict__ queries, int64_t nq,
+                                                 SbhArgs a, float beta_low, float* __restrict__ out)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = D * D * D;
+    constexpr int TS = topo_stride(D3);
+    constexpr int LG = D == 2 ? 1 : D == 4 ? 2 : 3;
+    using Off = typename TreeOff<O64>::T;
+    constexpr int MAXS = bh_stack_depth<D>();
+    __shared__ int2 stack[256 / 64][MAXS];
+    __shared__ uint8_t stack_lvl[256 / 64][MAXS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+    if (j0 >= nq) return;
+    const int64_t j = j0 + lane;
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = gld(queries + 3 * j);
+        qy = gld(queries + 3 * j + 1);
+        qz = gld(queries + 3 * j + 2);
+    }
+    // a query with a non-finite coordinate has no value and takes no part in the vote
+    const bool votes = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = smooth_shift<D>(tv, qx, qy, qz, a.alpha);
+    }
+    const uint32_t stream = (uint32_t)(j0 / a.group);   // a.group is a multiple of 64
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float F = 0.0f;
+    int n_sub = 0, n_leaf = 0, steps = 0, end_levels = 0;
+    int sp = 0;
+    if (lane == 0) {
+        stack[wv][0] = make_int2(0, 0);   // the root's children: block 0, first point 0
+        stack_lvl[wv][0] = 0;
+    }
+    sp = 1;
+    __builtin_amdgcn_wave_barrier();
+    while (sp > 0) {
+        --sp;
+        const int2 e = stack[wv][sp];
+        const int32_t blk = __builtin_amdgcn_readfirstlane(e.x);
+        const int level = __builtin_amdgcn_readfirstlane((int)stack_lvl[wv][sp]);
+        uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
+        __builtin_amdgcn_wave_barrier();
+        const float diamC = ldexpf(tv.diam0, -(level + 1) * LG);
+        const float lim = beta_low * diamC;
+        const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);
+        const float4* __restrict__ ba = at_off(tv.bagg, boff);
+        const float4* __restrict__ bd = at_off(tv.bdip, boff);
+        const uint32_t* __restrict__ bt = at_off(tv.btopo, (Off)(uint32_t)blk * (Off)(TS * 4));
+        const int32_t base = (int32_t)gld(bt + D3);
+        int32_t nint = 0;
+        for (int c = 0; c < D3; ++c) {
+            const uint32_t cnt = gld(bt + c);
+            if (cnt == 0u) continue;
+            const bool internal_c = (int)cnt > tv.leaf_size && level + 1 < tv.max_level;
+            const float4 g = gld4(ba + c);
+            const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+            const float dx = g.x - qx, dy = g.y - qy, dz = g.z - qz;
+            const float r2 = norm2(dx, dy, dz);
+            const bool near = votes && !(r2 >= lim * lim);
+            if (__ballot(near) == 0ull) {
+                // a subdomain: its control variate and S paths rooted at it
+                const float cv = term_r2<K>(g, gd, dx, dy, dz, r2, kp, r0);
+                const int32_t blk_c = internal_c ? base + nint : 0;
+                float fa = 0.0f;
+                for (int s2 = 0; s2 < a.samples; ++s2) {
+                    PathWordsOne pw;
+                    pw.compute(stream, pre, ((uint32_t)(level + 1) << 24) | ((uint32_t)s2 << 16), a.batch, a.key0,
+                               a.key1);
+                    int4 rec;
+                    fa += wave_path<D, K, TRACE, O64, PathWordsOne>(tv, qx, qy, qz, r0, kp, valid, cnt, pre, blk_c, g,
+                                                                    cv, pw, stream, 0u, a.batch, a.key0, a.key1,
+                                                                    a.rr_mode, &rec, level + 1);
+                    if constexpr (TRACE) {
+                        steps += rec.z;
+                        end_levels += rec.y;
+                    }
+                }
+                F += cv + fa / (float)a.samples;
+                ++n_sub;
+            } else if (internal_c) {
+                if (lane == 0) {
+                    stack[wv][sp] = make_int2(base + nint, (int32_t)pre);
+                    stack_lvl[wv][sp] = (uint8_t)(level + 1);
+                }
+                ++sp;
+            } else {
+                for (uint32_t i = pre; i < pre + cnt; ++i) {
+                    const Off po = (Off)i * (Off)16;
+                    F = term_acc<K>(*at_off(tv.pts, po), (K == SBH_WINDING) ? *at_off(tv.pdip, po) : zero4, qx, qy, qz,
+                                    kp, r0, F);
+                }
+                ++n_leaf;
+            }
+            nint += internal_c ? 1 : 0;
+            pre += cnt;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (valid) {
+        gst(out + j, query_value<K>(F, r0, logwbar, a.alpha, qx, qy, qz));
+        if constexpr (TRACE) reinterpret_cast<int4*>(a.paths)[j] = make_int4(n_sub, n_leaf, steps, end_levels);
+    }
+}
+
 // A tree whose root is a leaf: every query is summed exactly over its points.
 template <int K>
 __device__ __forceinline__ void leaf_exact_query(const TreeView& tv, const float* __restrict__ queries, int64_t j,
@@ -1532,6 +1688,23 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
 }
 
 template <int D, int K>
+static hipError_t launch_cut_dk(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
+                                hipStream_t s)
+{
+    SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
+              e.eps * e.eps, e.alpha, e.paths};
+    const unsigned blocks = (unsigned)(((nq + 63) / 64 + 3) / 4);
+    if (tv.wide) {
+        if (e.paths) k_sbh_cut<D, K, true, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, e.beta, out);
+        else k_sbh_cut<D, K, false, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, e.beta, out);
+    } else {
+        if (e.paths) k_sbh_cut<D, K, true, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, e.beta, out);
+        else k_sbh_cut<D, K, false, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, e.beta, out);
+    }
+    return hipGetLastError();
+}
+
+template <int D, int K>
 static hipError_t launch_bh_dk(const TreeView& tv, const float* q, int64_t nq, const EvalLaunch& e, float* out,
                                hipStream_t s)
 {
@@ -1562,6 +1735,9 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
         if (e.kernel == SBH_POTENTIAL) return launch_leaf<SBH_POTENTIAL>(tv, queries, nq, e, out, s);
         if (e.kernel == SBH_WINDING) return launch_leaf<SBH_WINDING>(tv, queries, nq, e, out, s);
         return launch_leaf<SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
+    }
+    if (e.cut) {   // subdomains: the Barnes-Hut cut (branching 2 and 4)
+        SBH_DISPATCH(launch_cut_dk, t, tv, queries, nq, e, out, s);
     }
     if (t->d == 8) {
         if (e.kernel == SBH_POTENTIAL) return launch_sbh_dk<8, SBH_POTENTIAL>(tv, queries, nq, e, out, s);

@@ -353,6 +353,7 @@ struct EvalLaunch {
     float eps, alpha;
     int32_t* paths;
     int tile_score;     // coherent walk with the tile-shared score proposal (d = 2, group % 64 == 0)
+    int cut;            // subdomains: the Barnes-Hut cut at beta (group % 64 == 0, d = 2 or 4)
 };
 
 hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,

@@ -215,3 +215,37 @@ def check_bh(gt, ot, queries, kernel, beta, eps=1e-3, alpha=100.0, gpu_out=None,
 def fp64_reference(src, w, nrm, queries, kernel, eps=1e-3, alpha=100.0):
     return host(P.sbh_brute(T(src), T(w), None if nrm is None else T(nrm), T(queries), kernel, eps=eps,
                             alpha=alpha, fp64=True))
+
+
+def check_cut(gt, ot, queries, kernel, beta_low, samples=1, seed=0, group=64, rr_mode=0, eps=1e-3, alpha=100.0,
+              index=None, gpu_out=None, gpu_digest=None, max_divergent=1e-5):
+    """The Barnes-Hut-cut stratified estimator (subdomains = 1) against the oracle's, query by query:
+    values to the estimator's bar, and each query's digest {subdomains, leaves summed exactly,
+    accepted steps, sum of end levels} bit-exact except near-ties.  `queries` must be whole groups of
+    64 consecutive queries (the vote); with `index` they are those groups taken from a larger set
+    evaluated on the GPU (gpu_out / gpu_digest hold the full-set outputs)."""
+    if gpu_out is None:
+        dig = torch.full((queries.shape[0], 4), -7, dtype=torch.int32, device=DEV)
+        g = host(P.sbh_eval(gt, T(queries), kernel, beta=beta_low, samples=samples, seed=seed, eps=eps, alpha=alpha,
+                            group=group, rr_mode=rr_mode, paths=dig, subdomains=1))
+        gd = host(dig)
+    else:
+        g, gd = gpu_out[index], gpu_digest[index]
+    r = ot.sbh_cut(queries, kernel, beta_low, samples=samples, seed=seed, group=group, vote=64, rr_mode=rr_mode,
+                   eps=eps, alpha=alpha, index=index)
+    near = r["margin"] < NEAR_TIE
+    dig_bad = np.any(gd != r["digest"], axis=1)
+    ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha, r["sens"])
+    bad = dig_bad | ~ok
+    n = queries.shape[0]
+    stats = dict(n=n, digest_mismatch=int(dig_bad.sum()), value_mismatch=int((~ok).sum()),
+                 near_ties=int(near.sum()), fp32_bound_used=int(used_bound.sum()),
+                 max_rel_err=float(np.nanmax(np.where(ok, err, np.nan))) if ok.any() else float("nan"),
+                 median_rel_err=float(np.nanmedian(err)), subdomains_mean=float(r["digest"][:, 0].mean()),
+                 leaves_mean=float(r["digest"][:, 1].mean()))
+    worst = np.nonzero(bad & ~near)[0][:5]
+    assert not np.any(bad & ~near), (stats, [(int(i), float(g[i]), float(r["F"][i]), gd[i].tolist(),
+                                              r["digest"][i].tolist()) for i in worst])
+    assert bad.sum() <= allowed_divergent(n, max_divergent), stats
+    assert used_bound.sum() <= 0.01 * n, stats
+    return stats

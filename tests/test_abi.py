@@ -56,7 +56,8 @@ def test_struct_layouts_match_header(tmp_path):
     import paper_2506_02219_amd as P
     src = tmp_path / "layout.c"
     fields = [("sbh_build_opts", None), ("sbh_eval_opts", None), ("sbh_eval_opts", "paths"),
-              ("sbh_eval_opts", "mlp"), ("sbh_eval_opts", "batch"), ("sbh_tree_desc", None),
+              ("sbh_eval_opts", "mlp"), ("sbh_eval_opts", "batch"), ("sbh_eval_opts", "subdomains"),
+              ("sbh_tree_desc", None),
               ("sbh_tree_desc", "lo"), ("sbh_tree_desc", "inv_side"), ("sbh_batch_item", None),
               ("sbh_batch_item", "nq"), ("sbh_batch_item", "kernel"), ("sbh_batch_config", None),
               ("sbh_batch_config", "ms")]
@@ -69,7 +70,7 @@ def test_struct_layouts_match_header(tmp_path):
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(P.BuildOpts), ctypes.sizeof(P.EvalOpts), P.EvalOpts.paths.offset, P.EvalOpts.mlp.offset,
-            P.EvalOpts.batch.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset,
+            P.EvalOpts.batch.offset, P.EvalOpts.subdomains.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset,
             ctypes.sizeof(P.BatchItem), P.BatchItem.nq.offset, P.BatchItem.kernel.offset, ctypes.sizeof(P.BatchConfig),
             P.BatchConfig.ms.offset]
     assert got == want

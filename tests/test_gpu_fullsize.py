@@ -11,7 +11,7 @@ import torch
 import oracle
 import workloads as W
 import paper_2506_02219_amd as P
-from gpu_helpers import DEV, T, host, compare_trees, check_sbh, check_bh
+from gpu_helpers import DEV, T, host, compare_trees, check_sbh, check_bh, check_cut
 
 pytestmark = pytest.mark.gpu
 
@@ -110,3 +110,16 @@ def test_c3_smooth_fullsize(c3, samples):
     cl = W.Cloud(c3.sources, c3.weights, c3.normals, c3.queries, c3.kernel)
     gt, ot, st = run_full(cl, 64, samples)
     print(st)
+
+
+def test_c5_potential_fullsize_cut_subdomains(c5):
+    """Subdomains from the Barnes-Hut cut at beta = 0.5 on the 2^22-source potential workload (the
+    shuffled plane, G = 64): 24 sampled groups of 64 queries (whole groups, for the vote)."""
+    q, _ = W.shuffle_queries(c5.queries, 4242)
+    gt = P.sbh_build(T(c5.sources), T(c5.weights))
+    ot = oracle.Tree(c5.sources, c5.weights, None, d=2, leaf_size=8)
+    dig = torch.empty((q.shape[0], 4), dtype=torch.int32, device=DEV)
+    out = host(P.sbh_eval(gt, T(q), P.POTENTIAL, beta=0.5, samples=1, seed=0, group=64, paths=dig, subdomains=1))
+    g = np.random.Generator(np.random.PCG64(5)).choice(q.shape[0] // 64, 24, replace=False)
+    idx = (np.sort(g)[:, None] * 64 + np.arange(64)[None, :]).ravel()
+    print(check_cut(gt, ot, q[idx], P.POTENTIAL, 0.5, index=idx, gpu_out=out, gpu_digest=host(dig)))

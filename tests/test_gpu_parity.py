@@ -13,7 +13,7 @@ import torch
 import oracle
 import workloads as W
 import paper_2506_02219_amd as P
-from gpu_helpers import (DEV, T, host, build_both, compare_trees, check_sbh, check_bh, fp64_reference,
+from gpu_helpers import (check_cut, DEV, T, host, build_both, compare_trees, check_sbh, check_bh, fp64_reference,
                          value_scale)
 
 pytestmark = pytest.mark.gpu
@@ -176,6 +176,39 @@ def test_duplicate_points_estimator():
     q = box_queries(500, 8, -0.5, 1.5)
     gt, ot = build_both(src, w, d=2, leaf_size=4, max_level=6)
     check_sbh(gt, ot, q, P.POTENTIAL, samples=2)
+
+
+# ----------------------------------------------------------------------------- Barnes-Hut-cut subdomains
+@pytest.mark.parametrize("d,S,G,rr,beta_low", [(2, 1, 64, 0, 0.4), (2, 2, 64, 0, 1.0), (2, 1, 128, 1, 0.6),
+                                               (2, 1, 64, 2, 2.0), (4, 1, 64, 0, 0.5), (4, 2, 64, 0, 1.2)])
+def test_sbh_cut_parity_c1(d, S, G, rr, beta_low):
+    c = W.c1()
+    gt, ot = build_both(c.sources, c.weights, d=d)
+    print(check_cut(gt, ot, c.queries[:2000], P.POTENTIAL, beta_low, samples=S, seed=2, group=G, rr_mode=rr))
+
+
+@pytest.mark.parametrize("kernel", [P.WINDING, P.SMOOTHDIST, P.POTENTIAL])
+def test_sbh_cut_parity_surface(kernel):
+    src, nrm, w = surface(30000, 9)
+    q = box_queries(1000, 4)   # ragged: 15 full groups and 40 queries
+    gt, ot = build_both(src, w, nrm)
+    print(check_cut(gt, ot, q, kernel, 0.5, samples=1, seed=7, alpha=100.0))
+
+
+def test_sbh_cut_limits_and_errors():
+    c = W.c1()
+    gt = P.sbh_build(T(c.sources), T(c.weights))
+    q = T(c.queries[:640])
+    F = oracle.brute(c.sources, c.weights, None, c.queries[:640], P.POTENTIAL)
+    # no node far: every leaf summed exactly
+    v = host(P.sbh_eval(gt, q, P.POTENTIAL, beta=1e9, samples=1, group=64, subdomains=1))
+    assert np.max(np.abs(v - F) / np.abs(F)) < 1e-5
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.POTENTIAL, beta=0.5, samples=1, group=1, subdomains=1)     # needs G % 64 == 0
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.POTENTIAL, beta=float("inf"), samples=1, group=64, subdomains=1)
+    with pytest.raises(P.SbhError, match="EINVAL"):
+        P.sbh_eval(gt, q, P.POTENTIAL, beta=0.5, samples=1, group=64, subdomains=1, proposal=3)
 
 
 # ----------------------------------------------------------------------------- branching 8
