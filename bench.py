@@ -52,6 +52,9 @@ ROULETTE_FLOPS = 11
 # the accumulation
 STEP_FLOPS = 6
 HBM_PEAK_GBS = 8000.0
+# L2 of MI355X: 8 XCDs x 16 channels x 128 bytes per clock x 2.4 GHz (the per-query-stream walk's
+# gathers are served from L2 and the Infinity Cache, not from HBM)
+L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 
 
 def parse():
@@ -427,7 +430,8 @@ def main():
     wk_o = work_of(og)
     other = dict(group=og, ms_per_step=ms_o, queries_per_s=N / (ms_o * 1e-3), median_rel_err=e_o,
                  alg_bytes_per_launch=wk_o["alg_bytes"], achieved_alg_GBs=wk_o["alg_bytes"] / (ms_o * 1e-3) / 1e9,
-                 alg_flops_per_launch=wk_o["alg_flops"])
+                 alg_flops_per_launch=wk_o["alg_flops"], l2_peak_GBs=L2_PEAK_GBS,
+                 frac_of_l2_peak=wk_o["alg_bytes"] / (ms_o * 1e-3) / 1e9 / L2_PEAK_GBS)
 
     # --- the same estimator on the plane's original pixel order: neighbouring queries share a
     # wavefront (and its random stream); per-query estimates have the same distribution, but
