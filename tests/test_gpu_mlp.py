@@ -213,13 +213,11 @@ def test_training_lowers_the_loss_on_real_rows():
     assert np.all(np.isfinite(host(losses)))
 
 
-def test_trained_network_against_the_score_proposal():
-    """What training buys: a network trained on rows from three surfaces, kept at the
-    chunk with the lowest validation error on a fourth (the untrained network, which is
-    the score proposal, included), evaluated on a fifth.  Model selection may never
-    return a network that validates worse than the score proposal; on the held-out
-    surface it stays within 10% of the score proposal's error, and both importance
-    proposals beat the uniform path index.  The measured errors are printed."""
+@pytest.fixture(scope="module")
+def trained_vs_score():
+    """A network trained on rows from three surfaces, kept at the chunk with the lowest validation
+    error on a fourth (the untrained network, which is the score proposal, included), and the median
+    errors of the uniform path index, the score proposal and that network on a fifth."""
     import paper_2506_02219_amd.learned as L
 
     def surface_case(seed):
@@ -247,14 +245,30 @@ def test_trained_network_against_the_score_proposal():
     p0 = L.init_params(0)
     best, hist = L.train_selected(p0.clone(), X, Tg, Cn, steps=400, chunks=4, batch_rows=2048, lr=2e-3,
                                   validate=lambda prm: med_err(gv, qv, rv, 1, prm, seeds=(7,)))
-    assert hist[0][1] >= min(v for _, v in hist)                      # selection keeps the best
-    assert med_err(gv, qv, rv, 1, best, seeds=(7,)) <= hist[0][1]      # never worse than untrained
-    e_uni = med_err(gh, qh, rh, 0)
-    e_score = med_err(gh, qh, rh, 2)
-    e_net = med_err(gh, qh, rh, 1, best)
-    print(dict(validation=hist, uniform=e_uni, score=e_score, trained=e_net))
-    assert e_net <= 1.1 * e_score, (e_net, e_score)
-    assert e_score < e_uni and e_net < e_uni, (e_uni, e_score, e_net)
+    r = dict(hist=hist, best_validation=med_err(gv, qv, rv, 1, best, seeds=(7,)), uniform=med_err(gh, qh, rh, 0),
+             score=med_err(gh, qh, rh, 2), trained=med_err(gh, qh, rh, 1, best))
+    print(r)
+    return r
+
+
+def test_trained_network_selection_and_importance(trained_vs_score):
+    """Model selection never returns a network that validates worse than the untrained one (the score
+    proposal), and both importance proposals beat the uniform path index on a held-out surface."""
+    r = trained_vs_score
+    assert r["hist"][0][1] >= min(v for _, v in r["hist"])        # selection keeps the best
+    assert r["best_validation"] <= r["hist"][0][1]                 # never worse than untrained
+    assert r["score"] < r["uniform"] and r["trained"] < r["uniform"], r
+
+
+@pytest.mark.xfail(reason="measured: training lowers the cross-entropy but not the estimator's error; on the "
+                          "held-out surface the selected network is the score proposal or within a few per cent of "
+                          "it (GPU: score 9.3e-3, trained 9.3e-3 to 9.6e-3; CPU study with a variance objective: "
+                          "score 9.35e-3, cross-entropy 9.55e-3, variance 9.43e-3)", strict=False)
+def test_trained_network_beats_the_score_proposal(trained_vs_score):
+    """What the trained network gains over the method without it: a strictly lower held-out error than
+    the score proposal it starts from."""
+    r = trained_vs_score
+    assert r["trained"] < 0.97 * r["score"], r
 
 
 @pytest.mark.parametrize("samples,group", [(1, 1), (4, 1), (2, 7)])
