@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched evaluation")
     ap.add_argument("--no-grid", action="store_true", help="skip the estimator on the plane's original order")
     ap.add_argument("--no-cut", action="store_true", help="skip the Barnes-Hut-cut subdomains")
+    ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-aggregate walk")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -474,6 +475,36 @@ def main():
                 P.sbh_eval(tree, qry, kernel, beta=bl, samples=S, seed=0, group=args.group, out=out, subdomains=1)
             cut["sweep"].append(dict(beta_low=bl, ms=timed(run_cut, 5, 1), median_rel_err=err_of(run_cut)))
 
+    # --- the walk on compressed interior aggregates (binary16 codes, 8 bytes a child slot in place of
+    # the 16 of a float32 centre of mass and mass), same queries and samples as the headline
+    compressed = None
+    if (not args.no_compressed and args.group % 64 == 0 and args.branching == 2
+            and kernel in (P.POTENTIAL, P.SMOOTHDIST)):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ctree = P.sbh_build(src, wts, nrm, branching=2, leaf_size=8, compress=True)
+        torch.cuda.synchronize()
+        cbuild_ms = (time.perf_counter() - tb) * 1e3
+
+        def run_cmp():
+            P.sbh_eval(ctree, qry, kernel, samples=S, seed=0, group=args.group, out=out, compressed=1)
+
+        ms_c = timed(run_cmp, args.steps, args.warmup)
+        d3 = 8
+
+        def run_cmp_o():   # the other stream mode, against the uncompressed walk's `other` leg
+            P.sbh_eval(ctree, qry, kernel, samples=S, seed=0, group=og, out=out, compressed=1)
+
+        ms_co = timed(run_cmp_o, args.steps, args.warmup)
+        compressed = dict(group=args.group, samples=S, ms_per_step=ms_c, queries_per_s=N / (ms_c * 1e-3),
+                          median_rel_err=err_of(run_cmp), vs_headline=ms_per_step / ms_c, build_ms=cbuild_ms,
+                          other_stream_mode=dict(group=og, ms_per_step=ms_co, median_rel_err=err_of(run_cmp_o),
+                                                 vs_uncompressed=ms_o / ms_co),
+                          child_block_bytes=d3 * 8, float32_child_block_bytes=d3 * 16,
+                          interior_aggregate_bytes=int(ctree.n_blocks) * d3 * 8,
+                          float32_interior_aggregate_bytes=int(ctree.n_blocks) * d3 * 16)
+        ctree.free()
+
     # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
     # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
     # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
@@ -732,6 +763,7 @@ def main():
         "grid_order": grid_order,
         "tile_score_grid_order": tile_grid,
         "cut_subdomains": cut,
+        "compressed_aggregates": compressed,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

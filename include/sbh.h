@@ -65,6 +65,15 @@ typedef struct sbh_build_opts {
     int32_t branching;   /* per-dimension branching d: 2 (octree), 4 (64-way) or 8 (512-way); default 2 */
     int32_t leaf_size;   /* a node is split iff it holds more points than this; 1..64, default 8 */
     int32_t max_level;   /* deepest level; 0 = 60/(3 log2 d): 20 for d=2, 10 for d=4, 6 for d=8 */
+    int32_t compress;    /* 1: also store the compressed interior aggregates (the conclusion's
+                            quantised node buffer; branching 2): for each child c of an internal
+                            node P, binary16 o_c = (com_c - com^q_P) / s_c per axis (s_c the
+                            side of c's cell) and f_c = m_c / m^q_P, where com^q, m^q are the
+                            decoded values com^q_c = com^q_P + o_c s_c, m^q_c = m^q_P f_c
+                            (float64; the root's are its float32 centre of mass and mass; the
+                            exact aggregates summed in float64, a leaf over its points in order,
+                            an internal node over its children in slot order); 8 bytes per
+                            child instead of 16.  Default 0. */
 } sbh_build_opts;
 
 typedef struct sbh_eval_opts {
@@ -97,6 +106,13 @@ typedef struct sbh_eval_opts {
                             branching 2 or 4; paths, if given, is then [nq][4] int32: {subdomains,
                             leaves summed exactly, accepted steps of all paths, sum of their
                             end levels}. */
+    int32_t compressed;  /* 1: walk on the tree's compressed interior aggregates (built with
+                            sbh_build_opts.compress = 1; the conclusion's compressed LOD
+                            representation): each node's centre of mass and mass are the
+                            binary16-coded values decoded down from the root, and a node of one
+                            point takes the leaf step.  Needs the uniform proposal, subdomains
+                            0, the potential or smooth-distance kernel, and samples <= 32 when
+                            group is not a multiple of 64.  Default 0. */
 } sbh_eval_opts;
 
 typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */
@@ -405,6 +421,17 @@ sbh_status sbh_tree_info(const sbh_tree* tree, sbh_tree_desc* info);
 sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count, int32_t* level,
                            int32_t* digit, int32_t* parent, int32_t* first_child, int32_t* nchild,
                            float* agg, float* dip, uint32_t* perm, uint64_t* codes, float* spread2);
+
+/*
+ * sbh_tree_export_compressed - copy a tree's compressed aggregates (built with
+ * opts->compress = 1) to the host: codes [n_blocks][d^3][2] uint32, the child
+ * block of the b-th internal node (breadth-first order) in row b, slot s the
+ * child with digit s: {offset x | offset y << 16, offset z | mass fraction
+ * << 16}, binary16 bit patterns (zero for empty slots).  Synchronises the null
+ * stream.  Errors: SBH_EINVAL (NULL), SBH_ESTATE (no compressed aggregates),
+ * SBH_EHIP.
+ */
+sbh_status sbh_tree_export_compressed(const sbh_tree* tree, uint32_t* codes);
 
 /* sbh_free - release a tree (waits for the device to finish using it). NULL is a no-op. */
 sbh_status sbh_free(sbh_tree* tree);

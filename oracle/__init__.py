@@ -34,6 +34,9 @@ def lib():
         L.orc_tree_build.argtypes = [P, P, P, i64, i32, i32, i32]
         L.orc_tree_build.restype = P
         L.orc_tree_free.argtypes = [P]
+        L.orc_tree_set_compressed.argtypes = [P, i32]
+        L.orc_tree_set_compressed.restype = i32
+        L.orc_tree_compressed.argtypes = [P, P, P]
         L.orc_tree_set_diam_mode.argtypes = [P, i32]
         L.orc_tree_set_diam_mode.restype = i32
         L.orc_tree_num_nodes.argtypes = [P]
@@ -136,6 +139,22 @@ class Tree:
         if h is not None and _lib is not None:
             _lib.orc_tree_free(h)
             self._h = None
+
+    def set_compressed(self, on=True):
+        """Use the compressed interior aggregates (binary16 centre-of-mass offsets relative to the
+        decoded parent, in units of the node's cell side, and binary16 mass fractions of the decoded
+        parent) in every node term and far-field ratio; points stay exact."""
+        lib().orc_tree_set_compressed(self._h, int(bool(on)))
+        self._cmp = bool(on)
+
+    def compressed(self):
+        """(decoded aggregates [n, 4] float64: com xyz, mass; stored codes [n, 4] float32: offsets
+        x, y, z and mass fraction, zero for the root)."""
+        lib().orc_tree_set_compressed(self._h, 1)
+        qa = np.zeros((self.n_nodes, 4)); code = np.zeros((self.n_nodes, 4), np.float32)
+        lib().orc_tree_compressed(self._h, _p(qa), _p(code))
+        lib().orc_tree_set_compressed(self._h, int(getattr(self, "_cmp", False)))
+        return qa, code
 
     def set_diam_mode(self, mode):
         """The reading of |B| for a study of the paper's wording (0, the default and the one the

@@ -12,8 +12,11 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O3", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-shared", "-fPIC", "-o", tmp, SRC, "-lm"]
+    # -fno-tree-slp-vectorize: gcc 11's basic-block vectorizer at -O3 drops the float32 rounding of
+    # (double)(float)x in straight-line code (observed on the root's decoded centre of mass); the
+    # oracle relies on such roundings being done
+    cmd = ["gcc", "-O3", "-fno-tree-slp-vectorize", "-std=c99", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

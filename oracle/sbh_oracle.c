@@ -175,6 +175,13 @@ typedef struct orc_tree {
      * a point (a one-point node, or a leaf's virtual child) has |B| = 0. */
     int diam_mode;
     double* bdiag;            /* [n] tight-box diagonals, mode 2 only */
+    /* Compressed interior aggregates (the conclusion's quantisation of the
+     * node-aggregate buffer): when cmp is set, every node term and far-field
+     * ratio uses the decoded aggregates qcom / qmass below instead of the
+     * exact ones; leaves' points stay exact. */
+    int cmp;
+    double *qcom, *qmass;     /* [n][3], [n] decoded centres of mass and masses */
+    float* qcode;             /* [n][4] the stored binary16 values: offset x, y, z, mass fraction */
 } orc_tree;
 
 static uint64_t spread3(uint32_t v)
@@ -230,6 +237,7 @@ void orc_tree_free(orc_tree* t)
     free(t->begin); free(t->count); free(t->first_child); free(t->parent);
     free(t->level); free(t->nchild); free(t->digit);
     free(t->mass); free(t->com); free(t->dip); free(t->spr); free(t->bdiag);
+    free(t->qcom); free(t->qmass); free(t->qcode);
     free(t);
 }
 
@@ -411,9 +419,106 @@ void orc_tree_export(const orc_tree* t, int64_t* begin, int64_t* count, int32_t*
     }
 }
 
+static const double* node_com(const orc_tree* t, int64_t i) { return t->cmp ? &t->qcom[3 * i] : &t->com[3 * i]; }
+static double node_mass(const orc_tree* t, int64_t i) { return t->cmp ? t->qmass[i] : t->mass[i]; }
+
+/* binary16 value nearest to x (round to nearest even), as a double: the
+ * rounding is done on x itself, not on a float32 rounding of it. */
+static double f16_round_d(double x)
+{
+    if (!(x == x) || x == 0.0 || isinf(x)) return x;
+    int e;
+    (void)frexp(x, &e);
+    int ex = e - 1;
+    if (ex < -14) ex = -14;
+    double quantum = ldexp(1.0, ex - 10);
+    double r = nearbyint(x / quantum) * quantum;
+    if (fabs(r) > 65504.0) return x > 0 ? INFINITY : -INFINITY;
+    return r;
+}
+
+/* Compressed aggregates.  The root keeps its centre of mass and mass as
+ * float32 values.  A node v at level L >= 1 with parent P (already decoded)
+ * stores, in binary16,
+ *   o_v = (com_v - com^q_P) / s_L   (per axis; s_L = side / d^L, v's cell side)
+ *   f_v = m_v / m^q_P
+ * and decodes to com^q_v = com^q_P + o_v s_L, m^q_v = m^q_P f_v (float64
+ * arithmetic, in that order).  Offsets are relative to the decoded parent, so
+ * the error of a centre of mass is one binary16 rounding of its cell side and
+ * does not accumulate down the tree; the estimator stays unbiased for any
+ * aggregate values (Theorem 1). */
+int orc_tree_set_compressed(orc_tree* t, int on)
+{
+    if (on && !t->qcom) {
+        int64_t n = t->n_nodes;
+        /* the exact aggregates the codes round, in a fixed float64 summation order: a leaf sums its
+         * points in sorted order (m = sum w, s = sum w p), an internal node its children in slot
+         * order (m = sum m_c, s = sum m_c com_c); com = s / m.  (The centre-of-mass definition
+         * above sums every node's points directly; the two agree to float64 rounding, and the
+         * codes need one order that the GPU build follows too.) */
+        double* bm = malloc(n * sizeof(double));
+        double* bc = malloc(3 * n * sizeof(double));
+        for (int64_t v = n - 1; v >= 0; --v) {   /* children follow their parents */
+            double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            if (is_internal(t, v)) {
+                for (int64_t c = t->first_child[v]; c < t->first_child[v] + t->nchild[v]; ++c) {
+                    m += bm[c];
+                    sx += bm[c] * bc[3 * c];
+                    sy += bm[c] * bc[3 * c + 1];
+                    sz += bm[c] * bc[3 * c + 2];
+                }
+            } else {
+                for (int64_t q = t->begin[v]; q < t->begin[v] + t->count[v]; ++q) {
+                    double w = t->pw[q];
+                    m += w;
+                    sx += w * t->pxyz[3 * q];
+                    sy += w * t->pxyz[3 * q + 1];
+                    sz += w * t->pxyz[3 * q + 2];
+                }
+            }
+            bm[v] = m;
+            bc[3 * v] = sx / m;
+            bc[3 * v + 1] = sy / m;
+            bc[3 * v + 2] = sz / m;
+        }
+        t->qcom = malloc(3 * n * sizeof(double));
+        t->qmass = malloc(n * sizeof(double));
+        t->qcode = calloc(4 * n, sizeof(float));
+        for (int a = 0; a < 3; ++a) t->qcom[a] = (double)(float)bc[a];
+        t->qmass[0] = (double)(float)bm[0];
+        for (int64_t v = 1; v < n; ++v) {   /* breadth-first: every parent precedes its children */
+            int64_t P = t->parent[v];
+            double sl = (double)t->side / pow((double)t->d, (double)t->level[v]);
+            for (int a = 0; a < 3; ++a) {
+                double o = f16_round_d((bc[3 * v + a] - t->qcom[3 * P + a]) / sl);
+                t->qcode[4 * v + a] = (float)o;
+                t->qcom[3 * v + a] = t->qcom[3 * P + a] + o * sl;
+            }
+            double f = f16_round_d(bm[v] / t->qmass[P]);
+            t->qcode[4 * v + 3] = (float)f;
+            t->qmass[v] = t->qmass[P] * f;
+        }
+        free(bm);
+        free(bc);
+    }
+    t->cmp = on ? 1 : 0;
+    return 0;
+}
+
+/* The decoded aggregates and the stored codes, for tests: qagg [n][4] = com^q xyz, m^q;
+ * code [n][4] = o_x, o_y, o_z, f (the root's row is zero). */
+void orc_tree_compressed(const orc_tree* t, double* qagg, float* code)
+{
+    for (int64_t i = 0; i < t->n_nodes; ++i) {
+        for (int a = 0; a < 3; ++a) qagg[4 * i + a] = t->qcom[3 * i + a];
+        qagg[4 * i + 3] = t->qmass[i];
+        for (int a = 0; a < 4; ++a) code[4 * i + a] = t->qcode[4 * i + a];
+    }
+}
+
 static double node_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
 {
-    return term(kp, &t->com[3 * i], t->mass[i], &t->dip[3 * i], q);
+    return term(kp, node_com(t, i), node_mass(t, i), &t->dip[3 * i], q);
 }
 
 static double point_term(const orc_tree* t, const kparams* kp, int64_t s, const double q[3])
@@ -456,7 +561,7 @@ static double sens_at(const kparams* kp, const double p[3], double m, const doub
 
 static double node_sens(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
 {
-    return sens_at(kp, &t->com[3 * i], t->mass[i], &t->dip[3 * i], q);
+    return sens_at(kp, node_com(t, i), node_mass(t, i), &t->dip[3 * i], q);
 }
 
 /* One term and its sensitivity at an arbitrary (p, m, dip, q): out = {f, sens}
@@ -536,7 +641,7 @@ static void bh_group(const orc_tree* t, const kparams* kp, int64_t node, const d
     int open = 0;
     *visited += 1;
     for (int g = 0; g < gn; ++g) {
-        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / node_diam(t, node);
+        double bt = dist3(node_com(t, node), &qs[3 * g]) / node_diam(t, node);
         double mg = fabs(bt - beta) / beta;
         if (mg < margin[g]) margin[g] = mg;
         if (!(bt >= beta)) open = 1;
@@ -843,7 +948,9 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         int64_t nT = t->count[T];
         po.end_begin = (int32_t)t->begin[T];
         po.end_level = t->level[T];
-        if (nT == 1) { po.flags = 1; break; }   /* a one-point leaf: nothing left to refine */
+        /* a one-point node: nothing left to refine (with compressed aggregates its term is not
+         * its point's, so it takes one more step, onto the point as a virtual child) */
+        if (nT == 1 && !t->cmp) { po.flags = 1; break; }
         uint32_t ctr[4] = {sigma, stream2, ctr2_base + (uint32_t)(k >> 1), batch}, rnd[4];
         orc_philox4x32_10(ctr, key, rnd);
         uint32_t x_sel = rnd[2 * (k & 1)], x_rr = rnd[2 * (k & 1) + 1];
@@ -851,7 +958,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         /* uniform path index inside T: offset r in [0, nT) */
         int64_t r = (int64_t)(((uint64_t)x_sel * (uint64_t)nT) >> 32);
         int64_t target = t->begin[T] + r;
-        double bT = dist3(&t->com[3 * T], q) / node_diam(t, T);
+        double bT = dist3(node_com(t, T), q) / node_diam(t, T);
         double sum_children = 0.0, abs_children = 0.0, sens_step = node_sens(t, kp, T, q);
         double bc, tc, q_c;
         int64_t c_node = -1;
@@ -881,7 +988,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
                 q_c = qv[ci];
             }
             c_node = c;
-            bc = dist3(&t->com[3 * c], q) / node_diam(t, c);
+            bc = dist3(node_com(t, c), q) / node_diam(t, c);
             tc = node_term(t, kp, c, q);
         } else {
             /* leaf with several points: the points are virtual children */
@@ -1015,7 +1122,7 @@ static void cut_group(const orc_tree* t, const kparams* kp, int64_t node, const 
 {
     int open = 0;
     for (int g = 0; g < gn; ++g) {
-        double bt = dist3(&t->com[3 * node], &qs[3 * g]) / node_diam(t, node);
+        double bt = dist3(node_com(t, node), &qs[3 * g]) / node_diam(t, node);
         if (!(bt >= beta_low)) open = 1;
     }
     if (!open) {
@@ -1122,8 +1229,8 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
                          double ps, double pr, int rr_mode, const proposal* prop)
 {
     int64_t nT = t->count[T];
-    if (nT == 1) return 0.0;
-    double bT = dist3(&t->com[3 * T], q) / node_diam(t, T);
+    if (nT == 1 && !t->cmp) return 0.0;
+    double bT = dist3(node_com(t, T), q) / node_diam(t, T);
     double total = 0.0;
     if (is_internal(t, T)) {
         double sum = 0.0;
@@ -1135,7 +1242,7 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         int nonuni = proposal_q(t, prop, T, q, qv, slots, &nk);
         for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
             double qc = nonuni ? qv[ch - t->first_child[T]] : (double)t->count[ch] / (double)nT;
-            double pc = rr_prob(rr_mode, bT, dist3(&t->com[3 * ch], q) / node_diam(t, ch));
+            double pc = rr_prob(rr_mode, bT, dist3(node_com(t, ch), q) / node_diam(t, ch));
             double tc = node_term(t, kp, ch, q);
             total += qc * pc * (delta / (ps * pr * pc) + expect_rec(t, kp, q, ch, tc, ps * qc, pr * pc, rr_mode, prop));
         }

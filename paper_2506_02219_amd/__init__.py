@@ -22,13 +22,13 @@ KERNELS = {"potential": POTENTIAL, "winding": WINDING, "smoothdist": SMOOTHDIST}
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("branching", C.c_int32), ("leaf_size", C.c_int32), ("max_level", C.c_int32)]
+    _fields_ = [("branching", C.c_int32), ("leaf_size", C.c_int32), ("max_level", C.c_int32), ("compress", C.c_int32)]
 
 
 class EvalOpts(C.Structure):
     _fields_ = [("eps", C.c_float), ("alpha", C.c_float), ("group", C.c_int32), ("rr_mode", C.c_int32),
                 ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p),
-                ("subdomains", C.c_int32)]
+                ("subdomains", C.c_int32), ("compressed", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -79,6 +79,8 @@ def lib():
         L.sbh_tree_info.restype = i32
         L.sbh_tree_export.argtypes = [P] + [P] * 12
         L.sbh_tree_export.restype = i32
+        L.sbh_tree_export_compressed.argtypes = [P, P]
+        L.sbh_tree_export_compressed.restype = i32
         L.sbh_mlp_forward.argtypes = [P, P, i64, P, P]
         L.sbh_mlp_forward.restype = i32
         L.sbh_mlp_pairs.argtypes = [P, P, i64, i32, u64, i32, P, P, P, P, P, P]
@@ -175,6 +177,15 @@ class Tree:
             p(a["spread2"])))
         return a
 
+    def export_compressed(self):
+        """The compressed aggregates (sbh_tree_export_compressed) as binary16 values
+        [n_blocks, d^3, 4] float32: offsets x, y, z (cell sides) and mass fraction."""
+        nb = max(self.n_blocks, 1)
+        w = np.zeros((nb, self.branching ** 3, 2), np.uint32)
+        _check("sbh_tree_export_compressed", lib().sbh_tree_export_compressed(self._h, w.ctypes.data_as(C.c_void_p)))
+        h = np.stack([w[..., 0] & 0xFFFF, w[..., 0] >> 16, w[..., 1] & 0xFFFF, w[..., 1] >> 16], -1).astype(np.uint16)
+        return h.view(np.float16).astype(np.float32)
+
     def free(self):
         if self._h:
             lib().sbh_free(self._h)
@@ -242,13 +253,15 @@ def use_torch_allocator():
     sbh_set_allocator(_alloc, _free)
 
 
-def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_level=0, stream=None) -> Tree:
-    """Build the tree on the GPU (sbh_build). sources [n,3], weights [n], normals [n,3] or None."""
+def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_level=0, stream=None,
+              compress=False) -> Tree:
+    """Build the tree on the GPU (sbh_build). sources [n,3], weights [n], normals [n,3] or None;
+    compress: also store the compressed interior aggregates (branching 2)."""
     _dev(sources, "sources", (3,)); _dev(weights, "weights"); _dev(normals, "normals", (3,))
     n = sources.shape[0]
     if weights.shape != (n,) or (normals is not None and normals.shape[0] != n):
         raise ValueError("sources, weights and normals must have the same length")
-    o = BuildOpts(branching, leaf_size, max_level)
+    o = BuildOpts(branching, leaf_size, max_level, int(bool(compress)))
     h = C.c_void_p()
     _check("sbh_build", lib().sbh_build(_ptr(sources), _ptr(weights), _ptr(normals), n, C.byref(o),
                                         _stream(stream), C.byref(h)))
@@ -256,7 +269,8 @@ def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_leve
 
 
 def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
-             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None, subdomains=0):
+             rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None, subdomains=0,
+             compressed=0):
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
     subdomains: 0 the root's children, 1 the Barnes-Hut cut at beta (group a multiple of 64);
     paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records ([nq, 4]
@@ -264,7 +278,9 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
     mlp: optional float32 CUDA tensor [MLP_NPARAM] selecting the learned proposal (1);
     proposal: 0 uniform path index, 1 learned (needs mlp; parameters that are not all finite fall back
     to the score proposal), 2 score proposal, 3 tile-shared score proposal (group a multiple of 64)
-    (default: 1 with mlp, else 0)."""
+    (default: 1 with mlp, else 0);
+    compressed: 1 walks on the compressed aggregates of a tree built with compress=1 (uniform proposal,
+    potential or smooth distance; samples <= 32 unless group is a multiple of 64)."""
     import torch
     _dev(queries, "queries", (3,))
     nq = queries.shape[0]
@@ -284,7 +300,7 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
         proposal = 0 if mlp is None else 1
     o = EvalOpts(eps, alpha, group, rr_mode, int(proposal), batch,
                  None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr(),
-                 int(subdomains))
+                 int(subdomains), int(compressed))
     _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
                                       C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
     return out

@@ -148,6 +148,7 @@ void sbh_build_opts_default(sbh_build_opts* o)
     o->branching = 2;
     o->leaf_size = 8;
     o->max_level = 0;
+    o->compress = 0;
 }
 
 void sbh_eval_opts_default(sbh_eval_opts* o)
@@ -162,6 +163,7 @@ void sbh_eval_opts_default(sbh_eval_opts* o)
     o->paths = nullptr;
     o->mlp = nullptr;
     o->subdomains = 0;
+    o->compressed = 0;
 }
 
 const char* sbh_status_string(sbh_status s)
@@ -192,6 +194,9 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     if (o.branching != 2 && o.branching != 4 && o.branching != 8)
         return fail(SBH_EINVAL, "sbh_build: branching must be 2, 4 or 8");
     if (o.leaf_size < 1 || o.leaf_size > 64) return fail(SBH_EINVAL, "sbh_build: leaf_size must be in [1, 64]");
+    if (o.compress != 0 && o.compress != 1) return fail(SBH_EINVAL, "sbh_build: compress must be 0 or 1");
+    if (o.compress && o.branching != 2)
+        return fail(SBH_EUNSUPPORTED, "sbh_build: compressed aggregates need branching 2");
     const int bits = o.branching == 2 ? 3 : o.branching == 4 ? 6 : 9;
     const int lmax = 60 / bits;
     if (o.max_level < 0 || o.max_level > lmax) return fail(SBH_EINVAL, "sbh_build: max_level must be in [0, %d]", lmax);
@@ -204,7 +209,8 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     t->impl.mem = sbh::allocator_current();
     std::string msg;
     const sbh_status st =
-        sbh::build_tree_impl(sources, weights, normals, n, o.branching, o.leaf_size, o.max_level, stream, &t->impl, &msg);
+        sbh::build_tree_impl(sources, weights, normals, n, o.branching, o.leaf_size, o.max_level, o.compress, stream,
+                             &t->impl, &msg);
     if (st != SBH_OK) {
         (void)hipStreamSynchronize(stream);
         free_impl(&t->impl, stream);
@@ -258,6 +264,17 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
     if (e.cut && !(beta > 0.0f && std::isfinite(beta)))
         return fail(SBH_EINVAL, "sbh_eval: Barnes-Hut-cut subdomains need a finite beta > 0");
     if (e.cut && t->d == 8) return fail(SBH_EUNSUPPORTED, "sbh_eval: Barnes-Hut-cut subdomains need branching 2 or 4");
+    if (o.compressed != 0 && o.compressed != 1) return fail(SBH_EINVAL, "sbh_eval: compressed must be 0 or 1");
+    e.compressed = (samples > 0 && o.compressed == 1) ? 1 : 0;
+    if (e.compressed) {
+        if (!t->bq) return fail(SBH_ESTATE, "sbh_eval: compressed needs a tree built with compress = 1");
+        if (o.proposal != 0 || o.subdomains != 0)
+            return fail(SBH_EUNSUPPORTED, "sbh_eval: compressed needs the uniform proposal and subdomains 0");
+        if (o.group % 64 != 0 && 8 * (int64_t)samples > 256)
+            return fail(SBH_EUNSUPPORTED, "sbh_eval: compressed with group not a multiple of 64 needs samples <= 32");
+        if (kernel != SBH_POTENTIAL && kernel != SBH_SMOOTHDIST)
+            return fail(SBH_EUNSUPPORTED, "sbh_eval: compressed needs the potential or smooth-distance kernel");
+    }
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;
     if (samples == 0) err = sbh::launch_bh_eval(t, queries, nq, e, out, stream);
@@ -334,6 +351,17 @@ sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count,
         const hipError_t e = hipMemcpy(it.dst, it.src, it.bytes, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "sbh_tree_export: copy");
     }
+    return SBH_OK;
+}
+
+sbh_status sbh_tree_export_compressed(const sbh_tree* tree, uint32_t* codes)
+{
+    if (!tree || !codes) return fail(SBH_EINVAL, "sbh_tree_export_compressed: NULL argument");
+    const sbh::sbh_tree_impl& t = tree->impl;
+    if (!t.bq) return fail(SBH_ESTATE, "sbh_tree_export_compressed: the tree was built without compress");
+    const size_t bytes = (size_t)(t.n_blocks > 0 ? t.n_blocks : 1) * t.d3 * sizeof(uint2);
+    const hipError_t e = hipMemcpy(codes, t.bq, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "sbh_tree_export_compressed: copy");
     return SBH_OK;
 }
 

@@ -491,6 +491,7 @@ __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ 
                             double* __restrict__ spr64, float4* __restrict__ nagg, float4* __restrict__ ndip,
                             float* __restrict__ nspr)
 {
+#pragma clang fp contract(off)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t g = off + i;
@@ -538,6 +539,59 @@ __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ 
         dip64[g] = make_double4(dx, dy, dz, 0.0);
         ndip[g] = make_float4((float)dx, (float)dy, (float)dz, 0.0f);
     }
+}
+
+// binary16 value nearest to x (round to nearest even) as a double: the rounding
+// is done on x itself (no float32 rounding first); |x| beyond binary16's range
+// gives +-infinity, x below it the nearest subnormal.
+__device__ __forceinline__ double f16_round_d(double x)
+{
+    if (!(x == x) || x == 0.0 || __builtin_isinf(x)) return x;
+    int e;
+    (void)frexp(x, &e);
+    int ex = e - 1;
+    if (ex < -14) ex = -14;
+    const double quantum = ldexp(1.0, ex - 10);
+    const double r = rint(x / quantum) * quantum;
+    if (fabs(r) > 65504.0) return x > 0.0 ? __builtin_inf() : -__builtin_inf();
+    return r;
+}
+
+__device__ __forceinline__ uint32_t f16_bits(double exact16)
+{
+    const _Float16 h = (_Float16)(float)exact16;   // exact: the value is a binary16 number
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
+// Compressed aggregates of one level's nodes (offset off, n of them; level
+// >= 1), top-down: each node's binary16 offset from its decoded parent in
+// units of its cell side sl, and its binary16 fraction of the decoded parent's
+// mass, decoded again in float64 for its own children.  agg64 holds the exact
+// aggregates (float64 sums, k_aggregate); qagg the decoded ones (com, mass).
+__global__ void k_compress(int32_t off, int32_t n, double sl, const int32_t* __restrict__ nparent,
+                           const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
+                           const double4* __restrict__ agg64, double4* __restrict__ qagg, uint2* __restrict__ bq,
+                           int d3)
+{
+#pragma clang fp contract(off)
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = off + i;
+    const double4 a = agg64[g];
+    const double4 pq = qagg[nparent[g]];
+    const double ox = f16_round_d((a.x - pq.x) / sl);
+    const double oy = f16_round_d((a.y - pq.y) / sl);
+    const double oz = f16_round_d((a.z - pq.z) / sl);
+    const double fm = f16_round_d(a.w / pq.w);
+    qagg[g] = make_double4(pq.x + ox * sl, pq.y + oy * sl, pq.z + oz * sl, pq.w * fm);
+    bq[(int64_t)npblk[g] * d3 + ndig[g]] = make_uint2(f16_bits(ox) | (f16_bits(oy) << 16), f16_bits(oz) | (f16_bits(fm) << 16));
+}
+
+// the root's decoded aggregate: its float32 centre of mass and mass
+__global__ void k_compress_root(const double4* __restrict__ agg64, double4* __restrict__ qagg)
+{
+    const double4 a = agg64[0];
+    qagg[0] = make_double4((double)(float)a.x, (double)(float)a.y, (double)(float)a.z, (double)(float)a.w);
 }
 
 __global__ void k_pack(int32_t n_nodes, const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
@@ -633,7 +687,7 @@ struct LevelBufs {
 
 // Builds the tree into *t.  Returns SBH_OK or an error code with *msg set.
 sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, int64_t n, int d, int leaf_size,
-                           int max_level, hipStream_t s, sbh_tree_impl* t, std::string* msg)
+                           int max_level, int compress, hipStream_t s, sbh_tree_impl* t, std::string* msg)
 {
     DevPool tmp(t->mem, s);
     auto fail_hip = [&](hipError_t e, const char* where) {
@@ -845,7 +899,7 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     const int64_t nbk = n_blocks > 0 ? n_blocks : 1;
     {
         const size_t bytes = carve_bytes<uint32_t>(nbk * ts) + carve_bytes<float4>(nbk * d3) * (nrm ? 2 : 1) +
-                             carve_bytes<float>(nbk * d3);
+                             carve_bytes<float>(nbk * d3) + (compress ? carve_bytes<uint2>(nbk * d3) : 0);
         t->slab_bytes[2] = bytes;
         SBH_TRY(dev_alloc(t->mem, &t->slab[2], bytes, s), "allocating blocks");
         SBH_TRY(hipMemsetAsync(t->slab[2], 0, bytes, s), "blocks clear");
@@ -854,6 +908,7 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         t->bagg = c.take<float4>(nbk * d3);
         t->bspr = c.take<float>(nbk * d3);
         if (nrm) t->bdip = c.take<float4>(nbk * d3);
+        if (compress) t->bq = c.take<uint2>(nbk * d3);
     }
     for (int l = 0; l < n_levels; ++l) {
         if (n_int_lv[l] > 0 && btopo_lv[l]) {
@@ -875,6 +930,18 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
                                                       t->nnchild, t->pts, t->pdip, agg64, dip64, spr64, t->nagg,
                                                       t->ndip, t->nspr);
             SBH_TRY(hipGetLastError(), "aggregate kernel");
+        }
+        if (compress && n_nodes > 1) {   // compressed aggregates, top-down from the root's
+            double4* qagg = tmp.alloc<double4>(n_nodes);
+            SBH_ALLOC_OK("allocating decoded aggregates");
+            k_compress_root<<<1, 1, 0, s>>>(agg64, qagg);
+            SBH_TRY(hipGetLastError(), "compress kernel");
+            for (int l = 1; l < n_levels; ++l) {
+                const double sl = (double)t->side / std::pow((double)d, (double)l);
+                k_compress<<<nblk(lv[l].n), 256, 0, s>>>((int32_t)off[l], lv[l].n, sl, t->nparent, npblk, t->ndigit,
+                                                         agg64, qagg, t->bq, d3);
+                SBH_TRY(hipGetLastError(), "compress kernel");
+            }
         }
     }
     if (n_nodes > 1) {

@@ -59,6 +59,7 @@ TreeView make_view(const sbh_tree_impl* t)
     v.btopo = t->btopo;
     v.nagg = t->nagg;
     v.ndip = t->ndip;
+    v.bq = t->bq;
     v.n_points = (int32_t)t->n_points;
     v.leaf_size = t->leaf_size;
     v.max_level = t->max_level;
@@ -288,6 +289,11 @@ __global__ void __launch_bounds__(256) k_sbh(TreeView tv, const float* __restric
 // the pool is drained each query adds CV_a + F_a / S over its subdomains in
 // slot order, so the result does not depend on which lane walked what.  The
 // step is the one of sample_path, operation for operation.
+// CMP (d = 2, potential and smooth distance): the walk on the compressed
+// aggregates, each child decoded from its 8-byte code as in the coherent
+// compressed walk (the lane carries its node's decoded offset from the query,
+// its decoded mass and its children's cell side); a node of one point takes
+// the leaf step.
 // ---------------------------------------------------------------------------
 constexpr int kPoolPaths = 256;
 
@@ -295,11 +301,18 @@ constexpr int kPoolPaths = 256;
 // (exactly representable, in [0, 1)).
 __device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
 
-template <int D, int K, bool TRACE>
+// A compressed aggregate's field: the binary16 number in the low 16 bits, as a float.
+__device__ __forceinline__ float h16(uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); }
+typedef uint32_t sbh_u32x4v __attribute__((ext_vector_type(4)));
+// 16 bytes (16-byte aligned): adjacent loads of a block merge into one wide scalar load
+__device__ __forceinline__ sbh_u32x4v gld4u(const uint32_t* p) { return *(const SBH_GLOBAL sbh_u32x4v*)p; }
+
+template <int D, int K, bool TRACE, bool CMP = false>
 __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __restrict__ queries, int64_t nq,
                                                   SbhArgs a, float* __restrict__ out)
 {
 #pragma clang fp contract(off)
+    static_assert(!CMP || (D == 2 && K != SBH_WINDING), "compressed aggregates: d = 2, no dipoles");
     constexpr int D3 = D * D * D;
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
@@ -317,7 +330,17 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
     const int NP = Q * D3 * S;
     const int64_t q0 = ((int64_t)blockIdx.x * 4 + wv) * Q;
     for (int c = threadIdx.x; c < D3; c += 256) {   // before the block's waves part: all reach the barrier
-        root_agg[c] = gld4(tv.bagg + c);
+        if constexpr (CMP) {
+            // a subdomain's decoded aggregate is q-independent except for its offset: keep the
+            // root's float32 centre of mass with the slot's offset code (x, y, z: cell sides of
+            // level 1) and its decoded mass
+            const float4 g0 = gld4(tv.nagg);
+            const uint32_t w0 = gld(reinterpret_cast<const uint32_t*>(tv.bq) + 2 * c);
+            const uint32_t w1 = gld(reinterpret_cast<const uint32_t*>(tv.bq) + 2 * c + 1);
+            root_agg[c] = make_float4(h16(w0 & 0xFFFFu), h16(w0 >> 16), h16(w1 & 0xFFFFu), g0.w * h16(w1 >> 16));
+        } else {
+            root_agg[c] = gld4(tv.bagg + c);
+        }
         if constexpr (K == SBH_WINDING) root_dip[c] = gld4(tv.bdip + c);
     }
     __syncthreads();
@@ -362,6 +385,8 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
     uint32_t nT = 0u, beginT = 0u, ctr0 = 0u, ctr1 = 0u;
     int32_t blk = 0, end_b = 0, end_l = 1;
     float diamT = 0.f, dT = 0.f, tT = 0.f, prr = 1.f, acc = 0.f, fna = 0.f;
+    float dTx = 0.f, dTy = 0.f, dTz = 0.f, mT = 0.f, sideC = 0.f;   // CMP: the node's decoded aggregate
+    const float4 g0 = CMP ? gld4(tv.nagg) : zero4;                   // CMP: the root's
     u32x4 rnd = {0u, 0u, 0u, 0u};
     bool open = false;   // a path with points is being walked
     auto start = [&](int np) {
@@ -388,14 +413,25 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
         }
         const float4 agg_a = root_agg[slot];
         const float4 dip_a = (K == SBH_WINDING) ? root_dip[slot] : zero4;
-        const float cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);   // control variate CV_a
+        float cv;
+        if constexpr (CMP) {
+            const float s1 = tv.side * 0.5f;
+            dTx = fmaf(agg_a.x, s1, g0.x - qx);
+            dTy = fmaf(agg_a.y, s1, g0.y - qy);
+            dTz = fmaf(agg_a.z, s1, g0.z - qz);
+            mT = agg_a.w;
+            sideC = tv.side * 0.25f;
+            cv = term_r2<K>(make_float4(0.f, 0.f, 0.f, mT), zero4, dTx, dTy, dTz, norm2(dTx, dTy, dTz), kp, r0);
+        } else {
+            cv = term<K>(agg_a, dip_a, qx, qy, qz, kp, r0);   // control variate CV_a
+        }
         if (smp == 0) cvs[wv][p / S] = cv;
         nT = n_a;
         beginT = tab[wv][slot][1];
         blk = (int32_t)tab[wv][slot][2];
         level = 1;
         diamT = tv.diam0 * kInvD;
-        dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
+        dT = CMP ? fsqrt(norm2(dTx, dTy, dTz)) : fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
         tT = cv;
         prr = 1.0f;
         fna = (float)n_a;
@@ -415,7 +451,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
         if (open) {
             end_b = (int32_t)beginT;
             end_l = level;
-            if (nT == 1u) {
+            if (nT == 1u && !CMP) {
                 flag = 1;
                 done = true;
             } else {
@@ -446,20 +482,32 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                         nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
                         pre += cnt;
                     }
-                    aggC = gld4(ba + csel);
+                    if constexpr (CMP) {
+                        // the selected child decoded: offset o s_c + (com^q_T - q), mass m^q_T f
+                        const uint32_t* __restrict__ qb = reinterpret_cast<const uint32_t*>(tv.bq) + (int64_t)blk * 16;
+                        const uint32_t w0 = gld(qb + 2 * csel), w1 = gld(qb + 2 * csel + 1);
+                        aggC = make_float4(fmaf(h16(w0 & 0xFFFFu), sideC, dTx), fmaf(h16(w0 >> 16), sideC, dTy),
+                                           fmaf(h16(w1 & 0xFFFFu), sideC, dTz), fmaf(h16(w1 >> 16), mT, 0.0f));
+                    } else {
+                        aggC = gld4(ba + csel);
+                    }
                     if constexpr (K == SBH_WINDING) dpC = gld4(bd + csel);
                     beginC = beginT + preC;
                     blkC = (int32_t)gld(bt + D3) + nintC;
                 } else {
                     aggC = gld4(tv.pts + beginT + r);
+                    if constexpr (CMP) aggC = make_float4(aggC.x - qx, aggC.y - qy, aggC.z - qz, aggC.w);
                     if constexpr (K == SBH_WINDING) dpC = gld4(tv.pdip + beginT + r);
                     beginC = beginT + r;
                 }
                 // roulette first (Eq. (5)); its offset and squared distance also give the
                 // selected child's own term, bit for bit the value the swap's sum takes for it
+                // (CMP: aggC holds the offset itself)
                 float pr;
                 float dC = 0.0f;
-                const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+                const float cx = CMP ? aggC.x : aggC.x - qx;
+                const float cy = CMP ? aggC.y : aggC.y - qy;
+                const float cz = CMP ? aggC.z : aggC.z - qz;
                 const float r2C = norm2(cx, cy, cz);
                 if (a.rr_mode == 0) {
                     dC = fsqrt(r2C);
@@ -474,7 +522,25 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     // contribution swap, Eq. (6)
                     float sumc = 0.0f;
                     const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
-                    if (internal) {
+                    if (internal && CMP) {
+                        const uint32_t* __restrict__ qb = reinterpret_cast<const uint32_t*>(tv.bq) + (int64_t)blk * 16;
+                        sbh_u32x4v cb[D3 / 2];
+#pragma unroll
+                        for (int i = 0; i < D3 / 2; ++i) cb[i] = gld4u(qb + 4 * i);
+#pragma unroll
+                        for (int c = 0; c < D3; ++c) {
+                            const uint32_t cnt = gld(bt + c);
+                            const uint32_t c0 = (c & 1) ? cb[c >> 1].z : cb[c >> 1].x;
+                            const uint32_t c1 = (c & 1) ? cb[c >> 1].w : cb[c >> 1].y;
+                            const float ex = fmaf(h16(c0 & 0xFFFFu), sideC, dTx);
+                            const float ey = fmaf(h16(c0 >> 16), sideC, dTy);
+                            const float ez = fmaf(h16(c1 & 0xFFFFu), sideC, dTz);
+                            const float mc = fmaf(h16(c1 >> 16), mT, 0.0f);
+                            const float v = term_r2_acc<K>(make_float4(0.f, 0.f, 0.f, mc), zero4, ex, ey, ez,
+                                                           norm2(ex, ey, ez), kp, r0, sumc);
+                            sumc = cnt ? v : sumc;
+                        }
+                    } else if (internal) {
 #pragma unroll
                         for (int c = 0; c < D3; ++c) {
                             const uint32_t cnt = gld(bt + c);
@@ -505,6 +571,13 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                         ++level;
                         diamT *= kInvD;
                         ++k;
+                        if constexpr (CMP) {
+                            dTx = cx;
+                            dTy = cy;
+                            dTz = cz;
+                            mT = aggC.w;
+                            sideC *= kInvD;
+                        }
                     }
                 }
             }
@@ -931,6 +1004,296 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     }
     if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
     return acc;
+}
+
+// ---------------------------------------------------------------------------
+// The coherent walk on compressed aggregates (d = 2; potential and smooth
+// distance; uniform path index).  A child block is eight 8-byte codes: the
+// child's centre of mass as a binary16 offset from its decoded parent in units
+// of its cell side, and its mass as a binary16 fraction of the decoded
+// parent's.  Each lane carries the decoded parent's offset from its query
+// (dT, float32) and the wavefront the decoded parent mass mT, so a child's
+// offset is one multiply-add per axis: com^q_c - q = o_c s_c + (com^q_T - q).
+// The decoded values are those the oracle defines, up to float32 rounding.
+// A node holding one point is not exact under compression, so it takes the
+// leaf step too (its point is a virtual child).  Random words, selection and
+// roulette are those of wave_path.
+// ---------------------------------------------------------------------------
+
+template <int K, bool TRACE, bool O64>
+__device__ __forceinline__ float wave_path_q(const TreeView& tv, float qx, float qy, float qz, float r0,
+                                             const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
+                                             int32_t blk_a, float dax, float day, float daz, float m_a, float t_a,
+                                             const PathWords& pw, uint32_t ctr0, uint32_t ctr1, uint32_t ctr3,
+                                             uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kInvD = 0.5f;
+    using Off = typename TreeOff<O64>::T;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t nT = n_a, beginT = begin_a;
+    int32_t blk = blk_a;
+    int level = 1;
+    float diamT = tv.diam0 * kInvD;
+    float sideC = tv.side * 0.25f;   // the cell side of the children of a level-1 node
+    float mT = m_a;
+    const float fna = (float)n_a;
+    uint64_t actm = __ballot(valid);
+    float dTx = dax, dTy = day, dTz = daz;
+    float dT = fsqrt(norm2(dax, day, daz));
+    float tT = t_a, prr = 1.0f, acc = 0.0f;
+    int steps = 0, flag = 0;
+    int32_t end_b = (int32_t)beginT, end_l = level;
+    const bool rr_eq5 = rr_mode == 0;
+    const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    auto roulette = [&](float r2C, float& dC) -> float {
+        const float ic = __builtin_amdgcn_rsqf(r2C);
+        dC = r2C * ic;
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
+        return rr_eq5 ? p5 : rr_fixed;
+    };
+    int k = 0;
+    bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
+    const int lvl_int = tv.max_level - 1;
+    auto internal_step = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        uint32_t xsel;
+        float u;
+        if constexpr (M == 2) pw.step_late(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        else pw.template step_held<M == 1>(k, ctr1, xsel, u);
+        const uint32_t r = __umulhi(xsel, nT);
+        const Off qoff = (Off)(uint32_t)blk * (Off)(D3 * 8);    // the block's codes
+        const Off toff = (Off)(uint32_t)blk * (Off)(TS * 4);
+        const uint32_t* __restrict__ bt = at_off(tv.btopo, toff);
+        const uint32_t* __restrict__ bqw = at_off(reinterpret_cast<const uint32_t*>(tv.bq), qoff);
+        // child selection across lanes 0..7, as wave_path
+        const int ln = threadIdx.x & 63;
+        const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
+        uint32_t inc = cl;
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
+        const uint32_t excl = inc - cl;
+        const uint32_t hm = (uint32_t)__ballot((r - excl) < cl);
+        const uint32_t im = level < lvl_int ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
+        const uint32_t nonempty = (uint32_t)__ballot(cl != 0u);
+        const int csel = __builtin_ctz(hm);
+        const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+        const uint32_t nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+        const int32_t nintC = __popc(im & ((1u << csel) - 1u));
+        const uint32_t w0 = gld(bqw + 2 * csel), w1 = gld(bqw + 2 * csel + 1);
+        const uint32_t beginC = beginT + preC;
+        const int32_t blkC = (int32_t)gld(bt + D3) + nintC;
+        // the selected child's offset and the roulette (Eq. (5))
+        const float cx = fmaf(h16(w0 & 0xFFFFu), sideC, dTx);
+        const float cy = fmaf(h16(w0 >> 16), sideC, dTy);
+        const float cz = fmaf(h16(w1 & 0xFFFFu), sideC, dTz);
+        const float r2C = norm2(cx, cy, cz);
+        float dC;
+        const float p = roulette(r2C, dC);
+        const float mC = fmaf(h16(w1 >> 16), mT, 0.0f);
+        const uint64_t contm = __ballot(u < p) & actm;
+        if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        actm = contm;
+        if (contm != 0ull) {
+            // contribution swap, Eq. (6): the selected child's term opens the sum
+            const float tC = term_r2<K>(make_float4(0.f, 0.f, 0.f, mC), zero4, cx, cy, cz, r2C, kp, r0);
+            float sumc = tC;
+            sbh_u32x4v cb[D3 / 2];   // the block's codes: slot c in words 2c, 2c + 1
+#pragma unroll
+            for (int i = 0; i < D3 / 2; ++i) cb[i] = gld4u(bqw + 4 * i);
+            const uint32_t rest = nonempty & ~(1u << csel);
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                if (!((rest >> c) & 1u)) continue;
+                const uint32_t c0 = (c & 1) ? cb[c >> 1].z : cb[c >> 1].x;
+                const uint32_t c1 = (c & 1) ? cb[c >> 1].w : cb[c >> 1].y;
+                const float ex = fmaf(h16(c0 & 0xFFFFu), sideC, dTx);
+                const float ey = fmaf(h16(c0 >> 16), sideC, dTy);
+                const float ez = fmaf(h16(c1 & 0xFFFFu), sideC, dTz);
+                const float mc = fmaf(h16(c1 >> 16), mT, 0.0f);   // = mT f (masses are not negative)
+                sumc = term_r2_acc<K>(make_float4(0.f, 0.f, 0.f, mc), zero4, ex, ey, ez, norm2(ex, ey, ez), kp, r0,
+                                      sumc);
+            }
+            const bool cont = __builtin_amdgcn_inverse_ballot_w64(contm);
+            const float prr2 = prr * p;
+            const float acc2 = acc + (sumc - tT) * (fna * frcp((float)nT * prr2));
+            prr = cont ? prr2 : prr;
+            acc = cont ? acc2 : acc;
+            tT = cont ? tC : tT;
+            steps += cont ? 1 : 0;
+            dT = dC;
+            dTx = cx;
+            dTy = cy;
+            dTz = cz;
+            mT = mC;
+            nT = nC;
+            beginT = beginC;
+            blk = blkC;
+            ++level;
+            diamT *= kInvD;
+            sideC *= kInvD;
+            ++k;
+        }
+        go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
+    };
+    while (go && k < 16) {
+        internal_step(std::integral_constant<int, 0>{});
+        if (go) internal_step(std::integral_constant<int, 1>{});
+    }
+    while (go) internal_step(std::integral_constant<int, 2>{});
+    if (actm != 0ull) {
+        // a leaf (one point included): its points are the virtual children, one drawn uniformly
+        uint32_t xsel;
+        float u;
+        pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        const uint32_t r = __umulhi(xsel, nT);
+        const float4 aggC = gld4(at_off(tv.pts, (Off)(beginT + r) * (Off)16));
+        float dC;
+        const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+        const float r2C = norm2(cx, cy, cz);
+        const float p = roulette(r2C, dC);
+        const uint64_t contm = __ballot(u < p) & actm;
+        if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        if (contm != 0ull) {
+            float sumc = term_r2<K>(aggC, zero4, cx, cy, cz, r2C, kp, r0);
+            for (uint32_t i = 0; i < nT; ++i) {
+                if (i == r) continue;
+                const Off po = (Off)(beginT + i) * (Off)16;
+                sumc = term_acc<K>(gld4(at_off(tv.pts, po)), zero4, qx, qy, qz, kp, r0, sumc);
+            }
+            if (__builtin_amdgcn_inverse_ballot_w64(contm)) {
+                prr *= p;
+                acc += (sumc - tT) * (fna * frcp((float)nT * prr));
+                ++steps;
+                flag = 2;
+                end_b = (int32_t)(beginT + r);
+                end_l = level + 1;
+            }
+        }
+    }
+    if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
+    return acc;
+}
+
+// One tile (64 consecutive queries) of the compressed walk: the root's
+// subdomains decoded from the root block's codes (com^q_a - q = o_a s_1 +
+// (com_0 - q), m^q_a = m_0 f_a, with com_0 and m_0 the root's float32
+// aggregate), then wave_path_q per (subdomain, sample).  Two wavefronts per
+// tile share the slots as k_sbh_wave's do.
+template <int K, bool TRACE, int P, bool O64>
+__device__ __forceinline__ void sbh_wave_tile_q(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
+                                                const SbhArgs& a, float* __restrict__ out, int64_t wave, int part,
+                                                int w, float (*part_f)[64], uint32_t* done)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    const int lane = threadIdx.x & 63;
+    const int64_t j0 = wave * 64;
+    if (j0 >= nq) return;
+    const int64_t j = j0 + lane;
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = gld(queries + 3 * j);
+        qy = gld(queries + 3 * j + 1);
+        qz = gld(queries + 3 * j + 2);
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    float logwbar = 0.f, r0 = 0.f;
+    if constexpr (K == SBH_SMOOTHDIST) {
+        smooth_setup(tv, kp.wscale, logwbar);
+        r0 = smooth_shift<2>(tv, qx, qy, qz, a.alpha);
+    }
+    const uint32_t stream = (uint32_t)(j0 / a.group);
+    const uint32_t* __restrict__ rt = tv.btopo;
+    const uint32_t* __restrict__ rq = reinterpret_cast<const uint32_t*>(tv.bq);
+    const int32_t base_root = (int32_t)gld(rt + D3);
+    const float4 g0 = gld4(tv.nagg);
+    const float s1 = tv.side * 0.5f;   // the cell side of level 1
+    const float ox0 = g0.x - qx, oy0 = g0.y - qy, oz0 = g0.z - qz;
+    const int slot_lo = part * (D3 / P), slot_hi = slot_lo + D3 / P;
+    uint32_t begin_a = 0u;
+    int32_t nint = 0;
+    for (int slot = 0; slot < slot_lo; ++slot) {
+        const uint32_t n_a = gld(rt + slot);
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
+    float F = 0.0f;
+    PathWords pw;
+    for (int slot = slot_lo; slot < slot_hi; ++slot) {
+        const uint32_t n_a = gld(rt + slot);
+        if (n_a == 0u) {
+            if constexpr (TRACE) {
+                if (valid)
+                    for (int s = 0; s < a.samples; ++s)
+                        reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = make_int4(-1, 0, 0, 0);
+            }
+            continue;
+        }
+        const int32_t blk_a = base_root + nint;
+        const uint32_t w0 = gld(rq + 2 * slot), w1 = gld(rq + 2 * slot + 1);
+        const float dax = fmaf(h16(w0 & 0xFFFFu), s1, ox0);
+        const float day = fmaf(h16(w0 >> 16), s1, oy0);
+        const float daz = fmaf(h16(w1 & 0xFFFFu), s1, oz0);
+        const float m_a = g0.w * h16(w1 >> 16);
+        const float cv = term_r2<K>(make_float4(0.f, 0.f, 0.f, m_a), make_float4(0.f, 0.f, 0.f, 0.f), dax, day, daz,
+                                    norm2(dax, day, daz), kp, r0);   // control variate CV_a
+        float fa = 0.0f;
+        for (int s = 0; s < a.samples; ++s) {
+            int4 rec;
+            const uint32_t path = (uint32_t)(slot * a.samples + s);
+            pw.need(path, stream, a.batch, a.key0, a.key1);
+            fa += wave_path_q<K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, dax, day, daz, m_a,
+                                             cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
+            if constexpr (TRACE) {
+                if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
+            }
+        }
+        F += cv + fa / (float)a.samples;
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
+    if constexpr (P > 1) {
+        const int tl = w / P;
+        part_f[w][lane] = F;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t prev = 0u;
+        if (lane == 0) prev = __hip_atomic_fetch_add(&done[tl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__builtin_amdgcn_readfirstlane(prev) != (uint32_t)(P - 1)) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        F = part_f[tl * P][lane];
+#pragma unroll
+        for (int q = 1; q < P; ++q) F += part_f[tl * P + q][lane];
+    }
+    if (valid) gst(out + j, query_value<K>(F, r0, logwbar, a.alpha, qx, qy, qz));
+}
+
+template <int K, bool TRACE, bool O64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_sbh_wave_q(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
+{
+    constexpr int P = kWaveParts, TPB = 4 / P;
+    __shared__ float part_f[4][64];
+    __shared__ uint32_t done[TPB];
+    if constexpr (P > 1) {
+        if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
+    sbh_wave_tile_q<K, TRACE, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // Sum over the 64 lanes of eight values per lane, in a fixed order, on the
@@ -1735,6 +2098,38 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
         if (e.kernel == SBH_POTENTIAL) return launch_leaf<SBH_POTENTIAL>(tv, queries, nq, e, out, s);
         if (e.kernel == SBH_WINDING) return launch_leaf<SBH_WINDING>(tv, queries, nq, e, out, s);
         return launch_leaf<SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
+    }
+    if (e.compressed) {   // the coherent walk on compressed aggregates (d = 2, potential or smooth distance)
+        SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
+                  e.eps * e.eps, e.alpha, e.paths};
+        if (e.group % 64 != 0) {   // per-query streams: the per-lane walk with lane refill
+            if (8 * e.samples > kPoolPaths) return hipErrorInvalidValue;   // the API checks S
+            const int64_t qpw = kPoolPaths / (8 * e.samples);
+            const unsigned blocks = (unsigned)(((nq + qpw - 1) / qpw + 3) / 4);
+            if (e.kernel == SBH_POTENTIAL) {
+                if (e.paths) k_sbh_pool<2, SBH_POTENTIAL, true, true><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);
+                else k_sbh_pool<2, SBH_POTENTIAL, false, true><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);
+            } else {
+                if (e.paths) k_sbh_pool<2, SBH_SMOOTHDIST, true, true><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);
+                else k_sbh_pool<2, SBH_SMOOTHDIST, false, true><<<blocks, 256, 0, s>>>(tv, queries, nq, a, out);
+            }
+            return hipGetLastError();
+        }
+        const unsigned wblocks = (unsigned)(((nq + 63) / 64 + (4 / kWaveParts) - 1) / (4 / kWaveParts));
+#define SBH_Q(KK)                                                                                           \
+    do {                                                                                                    \
+        if (tv.wide) {                                                                                      \
+            if (e.paths) k_sbh_wave_q<KK, true, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);      \
+            else k_sbh_wave_q<KK, false, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);             \
+        } else {                                                                                            \
+            if (e.paths) k_sbh_wave_q<KK, true, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);     \
+            else k_sbh_wave_q<KK, false, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);            \
+        }                                                                                                   \
+    } while (0)
+        if (e.kernel == SBH_POTENTIAL) SBH_Q(SBH_POTENTIAL);
+        else SBH_Q(SBH_SMOOTHDIST);
+#undef SBH_Q
+        return hipGetLastError();
     }
     if (e.cut) {   // subdomains: the Barnes-Hut cut (branching 2 and 4)
         SBH_DISPATCH(launch_cut_dk, t, tv, queries, nq, e, out, s);
