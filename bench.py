@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-grid", action="store_true", help="skip the estimator on the plane's original order")
     ap.add_argument("--no-cut", action="store_true", help="skip the Barnes-Hut-cut subdomains")
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-aggregate walk")
+    ap.add_argument("--no-lod2", action="store_true", help="skip the second-order (quadrupole) walk")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -505,6 +506,28 @@ def main():
                           float32_interior_aggregate_bytes=int(ctree.n_blocks) * d3 * 16)
         ctree.free()
 
+    # --- second-order node terms (the potential's quadrupole term where a node is far), same queries;
+    # an S sweep gives its error / time curve beside the point-mass one
+    lod2 = None
+    if (not args.no_lod2 and args.group % 64 == 0 and args.branching == 2 and kernel == P.POTENTIAL):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        qtree = P.sbh_build(src, wts, nrm, branching=2, leaf_size=8, quadrupole=True)
+        torch.cuda.synchronize()
+        qbuild_ms = (time.perf_counter() - tb) * 1e3
+
+        def run_l2(samples=S):
+            P.sbh_eval(qtree, qry, kernel, samples=samples, seed=0, group=args.group, out=out, lod=2)
+
+        ms_l = timed(run_l2, args.steps, args.warmup)
+        lod2 = dict(group=args.group, samples=S, ms_per_step=ms_l, queries_per_s=N / (ms_l * 1e-3),
+                    median_rel_err=err_of(run_l2), vs_headline=ms_per_step / ms_l, build_ms=qbuild_ms,
+                    tensor_bytes=int(qtree.n_blocks) * 8 * 32, sweep=[])
+        for sv in (2, 4):
+            lod2["sweep"].append(dict(samples=sv, ms=timed(lambda: run_l2(sv), 3, 1),
+                                      median_rel_err=err_of(lambda: run_l2(sv))))
+        qtree.free()
+
     # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
     # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
     # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
@@ -514,7 +537,8 @@ def main():
         bh_tree = tree if args.bh_branching == args.branching else build(args.bh_branching)[0]
 
         # sweep until Barnes-Hut is well below every error it is compared at
-        e_floor = min([err_star] + ([c_["median_rel_err"] for c_ in cut["sweep"]] if cut else []))
+        e_floor = min([err_star] + ([c_["median_rel_err"] for c_ in cut["sweep"]] if cut else [])
+                      + ([lod2["median_rel_err"]] if lod2 else []))
 
         def bh_sweep(qset, idx_t):
             pts = []
@@ -558,6 +582,10 @@ def main():
                 tb = at_error(pts_s, c_["median_rel_err"])[0]
                 c_["bh_ms_at_this_error"] = tb
                 c_["speedup_vs_bh_at_this_error"] = None if tb is None else tb / c_["ms"]
+        if lod2 is not None:
+            tb = at_error(pts_s, lod2["median_rel_err"])[0]
+            lod2["bh_ms_at_this_error"] = tb
+            lod2["speedup_vs_bh_at_this_error"] = None if tb is None else tb / lod2["ms_per_step"]
         if grid_order is not None:
             tb = at_error(pts_g, grid_order["median_rel_err"])[0]
             grid_order["bh_ms_at_this_error"] = tb
@@ -764,6 +792,7 @@ def main():
         "tile_score_grid_order": tile_grid,
         "cut_subdomains": cut,
         "compressed_aggregates": compressed,
+        "second_order_lod": lod2,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

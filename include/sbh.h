@@ -74,6 +74,10 @@ typedef struct sbh_build_opts {
                             exact aggregates summed in float64, a leaf over its points in order,
                             an internal node over its children in slot order); 8 bytes per
                             child instead of 16.  Default 0. */
+    int32_t quadrupole;  /* 1: also store each child's second-moment tensor about its centre of
+                            mass, Q = sum w (p - com)(p - com)^T (float64 sums, rounded once),
+                            for second-order node terms (sbh_eval_opts.lod = 2; Section 3.1's
+                            higher-order approximations); 32 bytes per child.  Default 0. */
 } sbh_build_opts;
 
 typedef struct sbh_eval_opts {
@@ -113,6 +117,15 @@ typedef struct sbh_eval_opts {
                             point takes the leaf step.  Needs the uniform proposal, subdomains
                             0, the potential or smooth-distance kernel, and samples <= 32 when
                             group is not a multiple of 64.  Default 0. */
+    int32_t lod;         /* order of the node terms: 1 (or 0, the default) the point mass
+                            m f(com, q) of Section 3.1; 2 adds, for the potential, the next term
+                            of the Taylor expansion about the centre of mass wherever the query
+                            sees the node as far (|q - com| >= |B|):
+                            1/2 u^5 (3 x^T Q x - tr(Q) (|x|^2 + eps^2)), x = com - q,
+                            u = (|x|^2 + eps^2)^(-1/2).  2 needs a tree built with quadrupole =
+                            1, branching 2, the potential, samples >= 1, group a multiple of 64,
+                            the uniform proposal, subdomains 0 and compressed 0.  The estimator
+                            stays unbiased (Theorem 1 holds for any node terms). */
 } sbh_eval_opts;
 
 typedef struct sbh_tree sbh_tree;   /* opaque; immutable after sbh_build */
@@ -432,6 +445,16 @@ sbh_status sbh_tree_export(const sbh_tree* tree, int32_t* begin, int32_t* count,
  * SBH_EHIP.
  */
 sbh_status sbh_tree_export_compressed(const sbh_tree* tree, uint32_t* codes);
+
+/*
+ * sbh_tree_export_quadrupole - copy a tree's scaled second-moment tensors
+ * (built with opts->quadrupole = 1) to the host: quad [n_blocks][d^3][8]
+ * float, laid out as the child blocks of sbh_tree_export_compressed: {1.5
+ * Qxx, 1.5 Qyy, 1.5 Qzz, 3 Qxy, 3 Qxz, 3 Qyz, tr(Q) / 2, 0} of the child in
+ * each slot (zero for empty slots).  Synchronises the null stream.  Errors:
+ * SBH_EINVAL (NULL), SBH_ESTATE (no tensors), SBH_EHIP.
+ */
+sbh_status sbh_tree_export_quadrupole(const sbh_tree* tree, float* quad);
 
 /* sbh_free - release a tree (waits for the device to finish using it). NULL is a no-op. */
 sbh_status sbh_free(sbh_tree* tree);

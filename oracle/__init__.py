@@ -34,6 +34,11 @@ def lib():
         L.orc_tree_build.argtypes = [P, P, P, i64, i32, i32, i32]
         L.orc_tree_build.restype = P
         L.orc_tree_free.argtypes = [P]
+        L.orc_tree_set_lod.argtypes = [P, i32]
+        L.orc_tree_set_lod.restype = i32
+        L.orc_tree_quad.argtypes = [P, P]
+        L.orc_node_term.argtypes = [P, i32, f64, f64, i64, P]
+        L.orc_node_term.restype = f64
         L.orc_tree_set_compressed.argtypes = [P, i32]
         L.orc_tree_set_compressed.restype = i32
         L.orc_tree_compressed.argtypes = [P, P, P]
@@ -144,7 +149,8 @@ class Tree:
         """Use the compressed interior aggregates (binary16 centre-of-mass offsets relative to the
         decoded parent, in units of the node's cell side, and binary16 mass fractions of the decoded
         parent) in every node term and far-field ratio; points stay exact."""
-        lib().orc_tree_set_compressed(self._h, int(bool(on)))
+        if lib().orc_tree_set_compressed(self._h, int(bool(on))) != 0:
+            raise ValueError("the compressed aggregates exclude lod 2")
         self._cmp = bool(on)
 
     def compressed(self):
@@ -155,6 +161,23 @@ class Tree:
         lib().orc_tree_compressed(self._h, _p(qa), _p(code))
         lib().orc_tree_set_compressed(self._h, int(getattr(self, "_cmp", False)))
         return qa, code
+
+    def set_lod(self, lod):
+        """Node terms of order 1 (point masses, the default) or 2 (plus the potential's quadrupole
+        term wherever the node is far: |q - com| >= |B|)."""
+        if lib().orc_tree_set_lod(self._h, int(lod)) != 0:
+            raise ValueError("lod must be 1 or 2, and 2 excludes the compressed aggregates")
+
+    def quad(self):
+        """Second-moment tensors [n, 6] (xx, yy, zz, xy, xz, yz) about each node's centre of mass."""
+        out = np.zeros((self.n_nodes, 6))
+        lib().orc_tree_quad(self._h, _p(out))
+        return out
+
+    def node_term(self, i, q, kernel=0, eps=1e-3, alpha=100.0):
+        """Node i's term at query q under the tree's lod."""
+        qq = np.ascontiguousarray(q, dtype=np.float64)
+        return lib().orc_node_term(self._h, int(kernel), float(eps), float(alpha), int(i), _p(qq))
 
     def set_diam_mode(self, mode):
         """The reading of |B| for a study of the paper's wording (0, the default and the one the

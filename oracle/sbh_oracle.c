@@ -182,6 +182,12 @@ typedef struct orc_tree {
     int cmp;
     double *qcom, *qmass;     /* [n][3], [n] decoded centres of mass and masses */
     float* qcode;             /* [n][4] the stored binary16 values: offset x, y, z, mass fraction */
+    /* Second-order level of detail (Section 3.1 allows higher-order node
+     * approximations): lod 2 adds, for the potential, the quadrupole term of
+     * the node's Taylor expansion about its centre of mass wherever the query
+     * sees the node as far (|q - com| >= |B|). */
+    int lod;
+    double* quad;             /* [n][6] Q = sum w (p - com)(p - com)^T: xx, yy, zz, xy, xz, yz */
 } orc_tree;
 
 static uint64_t spread3(uint32_t v)
@@ -237,7 +243,7 @@ void orc_tree_free(orc_tree* t)
     free(t->begin); free(t->count); free(t->first_child); free(t->parent);
     free(t->level); free(t->nchild); free(t->digit);
     free(t->mass); free(t->com); free(t->dip); free(t->spr); free(t->bdiag);
-    free(t->qcom); free(t->qmass); free(t->qcode);
+    free(t->qcom); free(t->qmass); free(t->qcode); free(t->quad);
     free(t);
 }
 
@@ -449,6 +455,7 @@ static double f16_round_d(double x)
  * aggregate values (Theorem 1). */
 int orc_tree_set_compressed(orc_tree* t, int on)
 {
+    if (on && t->lod == 2) return -1;
     if (on && !t->qcom) {
         int64_t n = t->n_nodes;
         /* the exact aggregates the codes round, in a fixed float64 summation order: a leaf sums its
@@ -516,10 +523,8 @@ void orc_tree_compressed(const orc_tree* t, double* qagg, float* code)
     }
 }
 
-static double node_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
-{
-    return term(kp, node_com(t, i), node_mass(t, i), &t->dip[3 * i], q);
-}
+static double node_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3]);
+static double node_term_m(const orc_tree* t, const kparams* kp, int64_t i, const double q[3], double* margin);
 
 static double point_term(const orc_tree* t, const kparams* kp, int64_t s, const double q[3])
 {
@@ -589,6 +594,81 @@ static double node_diam(const orc_tree* t, int64_t i)
     if (t->diam_mode == 2) return t->bdiag[i];
     double c = t->diam[t->level[i]];
     return t->diam_mode == 1 ? c / sqrt(3.0) : c;
+}
+
+/* The second-order term of node i for the potential f = (r^2 + eps^2)^(-1/2):
+ * expanding f(p) about the centre of mass c, the first-order terms cancel
+ * (c is the weighted mean) and the second-order one is 1/2 sum_ij Q_ij
+ * d_i d_j f with d_i d_j f = 3 u^5 x_i x_j - u^3 delta_ij (x = c - q,
+ * u = (|x|^2 + eps^2)^(-1/2)): 1/2 u^5 (3 x^T Q x - tr(Q) (|x|^2 + eps^2)).
+ * It is added where the node is far (|x| >= |B|, the threshold under which
+ * Eq. (5) never stops a path), since the expansion diverges inside the node.
+ * margin, if given, takes the relative distance of |x| / |B| from 1 (the
+ * decision a float32 evaluation may take the other way). */
+static double quad_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3], double* margin)
+{
+    const double* c = &t->com[3 * i];
+    const double* Q = &t->quad[6 * i];
+    double x = c[0] - q[0], y = c[1] - q[1], z = c[2] - q[2];
+    double r2 = x * x + y * y + z * z, B = node_diam(t, i);
+    if (margin) {
+        double g = fabs(sqrt(r2) / B - 1.0);
+        if (g < *margin) *margin = g;
+    }
+    if (!(r2 >= B * B)) return 0.0;
+    double s2 = r2 + kp->eps * kp->eps, u = 1.0 / sqrt(s2), u2 = u * u;
+    double xQx = Q[0] * x * x + Q[1] * y * y + Q[2] * z * z + 2.0 * (Q[3] * x * y + Q[4] * x * z + Q[5] * y * z);
+    return 0.5 * u * u2 * u2 * (3.0 * xQx - (Q[0] + Q[1] + Q[2]) * s2);
+}
+
+static double node_term_m(const orc_tree* t, const kparams* kp, int64_t i, const double q[3], double* margin)
+{
+    double v = term(kp, node_com(t, i), node_mass(t, i), &t->dip[3 * i], q);
+    if (t->lod == 2 && kp->kernel == ORC_POTENTIAL) v += quad_term(t, kp, i, q, margin);
+    return v;
+}
+
+static double node_term(const orc_tree* t, const kparams* kp, int64_t i, const double q[3])
+{
+    return node_term_m(t, kp, i, q, NULL);
+}
+
+/* lod 1: point-mass node terms (the paper's); lod 2: plus the quadrupole term
+ * (potential only).  The second-moment tensors are computed on first use,
+ * from each node's own points about its centre of mass (float64).  The
+ * compressed aggregates and lod 2 exclude each other (returns -1). */
+int orc_tree_set_lod(orc_tree* t, int lod)
+{
+    if (lod != 1 && lod != 2) return -1;
+    if (lod == 2 && t->cmp) return -1;
+    if (lod == 2 && !t->quad) {
+        t->quad = calloc(6 * (size_t)t->n_nodes, sizeof(double));
+        for (int64_t v = 0; v < t->n_nodes; ++v) {
+            const double* c = &t->com[3 * v];
+            double* Q = &t->quad[6 * v];
+            for (int64_t s = t->begin[v]; s < t->begin[v] + t->count[v]; ++s) {
+                double w = t->pw[s];
+                double x = t->pxyz[3 * s] - c[0], y = t->pxyz[3 * s + 1] - c[1], z = t->pxyz[3 * s + 2] - c[2];
+                Q[0] += w * x * x; Q[1] += w * y * y; Q[2] += w * z * z;
+                Q[3] += w * x * y; Q[4] += w * x * z; Q[5] += w * y * z;
+            }
+        }
+    }
+    t->lod = lod;
+    return 0;
+}
+
+/* The second-moment tensors, for tests: quad [n][6] (lod 2 computes them). */
+void orc_tree_quad(const orc_tree* t, double* quad)
+{
+    for (int64_t i = 0; i < 6 * t->n_nodes; ++i) quad[i] = t->quad ? t->quad[i] : 0.0;
+}
+
+/* A node's term at an arbitrary query under the tree's lod (tests). */
+double orc_node_term(const orc_tree* t, int kernel, double eps, double alpha, int64_t i, const double q[3])
+{
+    kparams kp = {kernel, eps, alpha};
+    return node_term(t, &kp, i, q);
 }
 
 static double point_diam(const orc_tree* t, int64_t leaf)
@@ -940,7 +1020,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
 {
     path_out po = {0.0, 0.0, 0.0, INFINITY, 0, 0, 0, 0};
     int64_t T = a;                  /* current node (a real node) */
-    double tT = node_term(t, kp, a, q);
+    double tT = node_term_m(t, kp, a, q, &po.margin);
     double p_sel = 1.0;             /* probability that the path index lies in T */
     double p_rr = 1.0;              /* running product of roulette probabilities */
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -965,7 +1045,7 @@ static path_out sample_path(const orc_tree* t, const kparams* kp, const double q
         if (is_internal(t, T)) {
             int64_t c = -1;
             for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
-                double v = node_term(t, kp, ch, q);
+                double v = node_term_m(t, kp, ch, q, &po.margin);
                 sum_children += v;
                 abs_children += fabs(v);
                 sens_step += node_sens(t, kp, ch, q);
@@ -1066,7 +1146,7 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
             for (int ci = 0; ci < t->nchild[0]; ++ci) {
                 int64_t a = t->first_child[0] + ci;
                 int slot = t->digit[a];
-                double cv = node_term(t, &kp, a, q);     /* control variate CV_a */
+                double cv = node_term_m(t, &kp, a, q, &mg);     /* control variate CV_a */
                 double Fa = 0.0, Aa = 0.0, Sa = 0.0;
                 for (int s = 0; s < S; ++s) {
                     path_out po = sample_path(t, &kp, q, a, sigma, (uint32_t)(slot * S + s), 0u, batch, seed, rr_mode,

@@ -22,13 +22,14 @@ KERNELS = {"potential": POTENTIAL, "winding": WINDING, "smoothdist": SMOOTHDIST}
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("branching", C.c_int32), ("leaf_size", C.c_int32), ("max_level", C.c_int32), ("compress", C.c_int32)]
+    _fields_ = [("branching", C.c_int32), ("leaf_size", C.c_int32), ("max_level", C.c_int32), ("compress", C.c_int32),
+                ("quadrupole", C.c_int32)]
 
 
 class EvalOpts(C.Structure):
     _fields_ = [("eps", C.c_float), ("alpha", C.c_float), ("group", C.c_int32), ("rr_mode", C.c_int32),
                 ("proposal", C.c_int32), ("batch", C.c_uint32), ("paths", C.c_void_p), ("mlp", C.c_void_p),
-                ("subdomains", C.c_int32), ("compressed", C.c_int32)]
+                ("subdomains", C.c_int32), ("compressed", C.c_int32), ("lod", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -81,6 +82,8 @@ def lib():
         L.sbh_tree_export.restype = i32
         L.sbh_tree_export_compressed.argtypes = [P, P]
         L.sbh_tree_export_compressed.restype = i32
+        L.sbh_tree_export_quadrupole.argtypes = [P, P]
+        L.sbh_tree_export_quadrupole.restype = i32
         L.sbh_mlp_forward.argtypes = [P, P, i64, P, P]
         L.sbh_mlp_forward.restype = i32
         L.sbh_mlp_pairs.argtypes = [P, P, i64, i32, u64, i32, P, P, P, P, P, P]
@@ -186,6 +189,14 @@ class Tree:
         h = np.stack([w[..., 0] & 0xFFFF, w[..., 0] >> 16, w[..., 1] & 0xFFFF, w[..., 1] >> 16], -1).astype(np.uint16)
         return h.view(np.float16).astype(np.float32)
 
+    def export_quadrupole(self):
+        """The scaled second-moment tensors (sbh_tree_export_quadrupole) [n_blocks, d^3, 8] float32:
+        1.5 Qxx, 1.5 Qyy, 1.5 Qzz, 3 Qxy, 3 Qxz, 3 Qyz, tr(Q) / 2, 0."""
+        nb = max(self.n_blocks, 1)
+        q = np.zeros((nb, self.branching ** 3, 8), np.float32)
+        _check("sbh_tree_export_quadrupole", lib().sbh_tree_export_quadrupole(self._h, q.ctypes.data_as(C.c_void_p)))
+        return q
+
     def free(self):
         if self._h:
             lib().sbh_free(self._h)
@@ -254,14 +265,15 @@ def use_torch_allocator():
 
 
 def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_level=0, stream=None,
-              compress=False) -> Tree:
+              compress=False, quadrupole=False) -> Tree:
     """Build the tree on the GPU (sbh_build). sources [n,3], weights [n], normals [n,3] or None;
-    compress: also store the compressed interior aggregates (branching 2)."""
+    compress: also store the compressed interior aggregates (branching 2); quadrupole: also store the
+    children's second-moment tensors (for lod=2)."""
     _dev(sources, "sources", (3,)); _dev(weights, "weights"); _dev(normals, "normals", (3,))
     n = sources.shape[0]
     if weights.shape != (n,) or (normals is not None and normals.shape[0] != n):
         raise ValueError("sources, weights and normals must have the same length")
-    o = BuildOpts(branching, leaf_size, max_level, int(bool(compress)))
+    o = BuildOpts(branching, leaf_size, max_level, int(bool(compress)), int(bool(quadrupole)))
     h = C.c_void_p()
     _check("sbh_build", lib().sbh_build(_ptr(sources), _ptr(weights), _ptr(normals), n, C.byref(o),
                                         _stream(stream), C.byref(h)))
@@ -270,7 +282,7 @@ def sbh_build(sources, weights, normals=None, branching=2, leaf_size=8, max_leve
 
 def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3, alpha=100.0, group=1,
              rr_mode=0, batch=0, paths=None, out=None, stream=None, mlp=None, proposal=None, subdomains=0,
-             compressed=0):
+             compressed=0, lod=1):
     """Evaluate every query (sbh_eval): samples >= 1 stochastic estimator, samples == 0 Barnes-Hut(beta).
     subdomains: 0 the root's children, 1 the Barnes-Hut cut at beta (group a multiple of 64);
     paths: optional int32 CUDA tensor [nq, d^3, samples, 4] receiving the path records ([nq, 4]
@@ -280,7 +292,9 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
     to the score proposal), 2 score proposal, 3 tile-shared score proposal (group a multiple of 64)
     (default: 1 with mlp, else 0);
     compressed: 1 walks on the compressed aggregates of a tree built with compress=1 (uniform proposal,
-    potential or smooth distance; samples <= 32 unless group is a multiple of 64)."""
+    potential or smooth distance; samples <= 32 unless group is a multiple of 64);
+    lod: 1 point-mass node terms, 2 adds the potential's quadrupole term where the node is far (a tree
+    built with quadrupole=True; d = 2, group a multiple of 64, uniform proposal)."""
     import torch
     _dev(queries, "queries", (3,))
     nq = queries.shape[0]
@@ -300,7 +314,7 @@ def sbh_eval(tree: Tree, queries, kernel, beta=2.0, samples=1, seed=0, eps=1e-3,
         proposal = 0 if mlp is None else 1
     o = EvalOpts(eps, alpha, group, rr_mode, int(proposal), batch,
                  None if paths is None else paths.data_ptr(), None if mlp is None else mlp.data_ptr(),
-                 int(subdomains), int(compressed))
+                 int(subdomains), int(compressed), int(lod))
     _check("sbh_eval", lib().sbh_eval(tree.handle, _ptr(queries), nq, int(kernel), float(beta), int(samples),
                                       C.c_uint64(seed), C.byref(o), _stream(stream), _ptr(out)))
     return out

@@ -149,6 +149,7 @@ void sbh_build_opts_default(sbh_build_opts* o)
     o->leaf_size = 8;
     o->max_level = 0;
     o->compress = 0;
+    o->quadrupole = 0;
 }
 
 void sbh_eval_opts_default(sbh_eval_opts* o)
@@ -164,6 +165,7 @@ void sbh_eval_opts_default(sbh_eval_opts* o)
     o->mlp = nullptr;
     o->subdomains = 0;
     o->compressed = 0;
+    o->lod = 0;
 }
 
 const char* sbh_status_string(sbh_status s)
@@ -197,6 +199,7 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     if (o.compress != 0 && o.compress != 1) return fail(SBH_EINVAL, "sbh_build: compress must be 0 or 1");
     if (o.compress && o.branching != 2)
         return fail(SBH_EUNSUPPORTED, "sbh_build: compressed aggregates need branching 2");
+    if (o.quadrupole != 0 && o.quadrupole != 1) return fail(SBH_EINVAL, "sbh_build: quadrupole must be 0 or 1");
     const int bits = o.branching == 2 ? 3 : o.branching == 4 ? 6 : 9;
     const int lmax = 60 / bits;
     if (o.max_level < 0 || o.max_level > lmax) return fail(SBH_EINVAL, "sbh_build: max_level must be in [0, %d]", lmax);
@@ -209,8 +212,8 @@ sbh_status sbh_build(const float* sources, const float* weights, const float* no
     t->impl.mem = sbh::allocator_current();
     std::string msg;
     const sbh_status st =
-        sbh::build_tree_impl(sources, weights, normals, n, o.branching, o.leaf_size, o.max_level, o.compress, stream,
-                             &t->impl, &msg);
+        sbh::build_tree_impl(sources, weights, normals, n, o.branching, o.leaf_size, o.max_level, o.compress,
+                             o.quadrupole, stream, &t->impl, &msg);
     if (st != SBH_OK) {
         (void)hipStreamSynchronize(stream);
         free_impl(&t->impl, stream);
@@ -274,6 +277,16 @@ sbh_status sbh_eval(const sbh_tree* tree, const float* queries, int64_t nq, sbh_
             return fail(SBH_EUNSUPPORTED, "sbh_eval: compressed with group not a multiple of 64 needs samples <= 32");
         if (kernel != SBH_POTENTIAL && kernel != SBH_SMOOTHDIST)
             return fail(SBH_EUNSUPPORTED, "sbh_eval: compressed needs the potential or smooth-distance kernel");
+    }
+    if (o.lod < 0 || o.lod > 2) return fail(SBH_EINVAL, "sbh_eval: lod must be 0, 1 or 2");
+    e.lod = o.lod == 2 ? 2 : 1;
+    if (e.lod == 2) {
+        if (!t->bquad) return fail(SBH_ESTATE, "sbh_eval: lod 2 needs a tree built with quadrupole = 1");
+        if (samples == 0 || kernel != SBH_POTENTIAL || t->d != 2 || o.group % 64 != 0 || o.proposal != 0 ||
+            o.subdomains != 0 || o.compressed != 0)
+            return fail(SBH_EUNSUPPORTED,
+                        "sbh_eval: lod 2 needs the estimator, the potential, branching 2, group a multiple of 64, "
+                        "the uniform proposal, subdomains 0 and compressed 0");
     }
     const bool root_leaf = !(t->n_points > t->leaf_size && t->max_level > 0);
     hipError_t err;
@@ -362,6 +375,17 @@ sbh_status sbh_tree_export_compressed(const sbh_tree* tree, uint32_t* codes)
     const size_t bytes = (size_t)(t.n_blocks > 0 ? t.n_blocks : 1) * t.d3 * sizeof(uint2);
     const hipError_t e = hipMemcpy(codes, t.bq, bytes, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "sbh_tree_export_compressed: copy");
+    return SBH_OK;
+}
+
+sbh_status sbh_tree_export_quadrupole(const sbh_tree* tree, float* quad)
+{
+    if (!tree || !quad) return fail(SBH_EINVAL, "sbh_tree_export_quadrupole: NULL argument");
+    const sbh::sbh_tree_impl& t = tree->impl;
+    if (!t.bquad) return fail(SBH_ESTATE, "sbh_tree_export_quadrupole: the tree was built without quadrupole");
+    const size_t bytes = (size_t)(t.n_blocks > 0 ? t.n_blocks : 1) * t.d3 * 2 * sizeof(float4);
+    const hipError_t e = hipMemcpy(quad, t.bquad, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "sbh_tree_export_quadrupole: copy");
     return SBH_OK;
 }
 
@@ -627,6 +651,8 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     if (opts) o = *opts;
     if (check_eval_opts(o) != SBH_OK) return SBH_EINVAL;
     if (o.subdomains != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: batches take the root's children as subdomains");
+    if (o.compressed != 0 || o.lod == 2)
+        return fail(SBH_EUNSUPPORTED, "sbh_batch_create: batches walk the float32 point-mass aggregates");
     if (o.group % 64 != 0) return fail(SBH_EINVAL, "sbh_batch_create: group must be a multiple of 64");
     if (o.proposal != 0) return fail(SBH_EUNSUPPORTED, "sbh_batch_create: only the uniform proposal is batched");
     if (o.paths) return fail(SBH_EINVAL, "sbh_batch_create: path records are not available in a batch");

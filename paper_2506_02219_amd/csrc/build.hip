@@ -489,7 +489,7 @@ __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ 
                             const int32_t* __restrict__ nnchild, const float4* __restrict__ pts,
                             const float4* __restrict__ pdip, double4* __restrict__ agg64, double4* __restrict__ dip64,
                             double* __restrict__ spr64, float4* __restrict__ nagg, float4* __restrict__ ndip,
-                            float* __restrict__ nspr)
+                            float* __restrict__ nspr, double* __restrict__ quad64)
 {
 #pragma clang fp contract(off)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -531,6 +531,31 @@ __global__ void k_aggregate(int32_t off, int32_t n, const int32_t* __restrict__ 
         }
     }
     s2 /= m;
+    if (quad64) {
+        // second-moment tensor about the centre of mass, Q = sum w (p - c)(p - c)^T: over the
+        // points of a leaf; over the children of a node by the parallel-axis rule,
+        // Q = sum_c (Q_c + m_c (c_c - c)(c_c - c)^T)
+        double Q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (f < 0) {
+            const int32_t b = nbegin[g], e = b + ncount[g];
+            for (int32_t s = b; s < e; ++s) {
+                const float4 p = pts[s];
+                const double ww = p.w, ex = (double)p.x - cx, ey = (double)p.y - cy, ez = (double)p.z - cz;
+                Q[0] += ww * ex * ex; Q[1] += ww * ey * ey; Q[2] += ww * ez * ez;
+                Q[3] += ww * ex * ey; Q[4] += ww * ex * ez; Q[5] += ww * ey * ez;
+            }
+        } else {
+            const int32_t e = f + nnchild[g];
+            for (int32_t c = f; c < e; ++c) {
+                const double4 a = agg64[c];
+                const double* qc = quad64 + 6 * (int64_t)c;
+                const double ex = a.x - cx, ey = a.y - cy, ez = a.z - cz;
+                Q[0] += qc[0] + a.w * ex * ex; Q[1] += qc[1] + a.w * ey * ey; Q[2] += qc[2] + a.w * ez * ez;
+                Q[3] += qc[3] + a.w * ex * ey; Q[4] += qc[4] + a.w * ex * ez; Q[5] += qc[5] + a.w * ey * ez;
+            }
+        }
+        for (int k = 0; k < 6; ++k) quad64[6 * (int64_t)g + k] = Q[k];
+    }
     agg64[g] = make_double4(cx, cy, cz, m);
     spr64[g] = s2;
     nagg[g] = make_float4((float)cx, (float)cy, (float)cz, (float)m);
@@ -592,6 +617,19 @@ __global__ void k_compress_root(const double4* __restrict__ agg64, double4* __re
 {
     const double4 a = agg64[0];
     qagg[0] = make_double4((double)(float)a.x, (double)(float)a.y, (double)(float)a.z, (double)(float)a.w);
+}
+
+// The children's second-moment tensors into their block slots, scaled for the
+// second-order term (rounded once from float64).
+__global__ void k_pack_quad(int32_t n_nodes, const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
+                            const double* __restrict__ quad64, float4* __restrict__ bquad, int d3)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (g >= n_nodes) return;
+    const int64_t slot = (int64_t)npblk[g] * d3 + ndig[g];
+    const double* Q = quad64 + 6 * (int64_t)g;
+    bquad[2 * slot] = make_float4((float)(1.5 * Q[0]), (float)(1.5 * Q[1]), (float)(1.5 * Q[2]), (float)(3.0 * Q[3]));
+    bquad[2 * slot + 1] = make_float4((float)(3.0 * Q[4]), (float)(3.0 * Q[5]), (float)(0.5 * (Q[0] + Q[1] + Q[2])), 0.0f);
 }
 
 __global__ void k_pack(int32_t n_nodes, const int32_t* __restrict__ npblk, const int32_t* __restrict__ ndig,
@@ -687,7 +725,8 @@ struct LevelBufs {
 
 // Builds the tree into *t.  Returns SBH_OK or an error code with *msg set.
 sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, int64_t n, int d, int leaf_size,
-                           int max_level, int compress, hipStream_t s, sbh_tree_impl* t, std::string* msg)
+                           int max_level, int compress, int quadrupole, hipStream_t s, sbh_tree_impl* t,
+                           std::string* msg)
 {
     DevPool tmp(t->mem, s);
     auto fail_hip = [&](hipError_t e, const char* where) {
@@ -899,7 +938,8 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     const int64_t nbk = n_blocks > 0 ? n_blocks : 1;
     {
         const size_t bytes = carve_bytes<uint32_t>(nbk * ts) + carve_bytes<float4>(nbk * d3) * (nrm ? 2 : 1) +
-                             carve_bytes<float>(nbk * d3) + (compress ? carve_bytes<uint2>(nbk * d3) : 0);
+                             carve_bytes<float>(nbk * d3) + (compress ? carve_bytes<uint2>(nbk * d3) : 0) +
+                             (quadrupole ? carve_bytes<float4>(2 * nbk * d3) : 0);
         t->slab_bytes[2] = bytes;
         SBH_TRY(dev_alloc(t->mem, &t->slab[2], bytes, s), "allocating blocks");
         SBH_TRY(hipMemsetAsync(t->slab[2], 0, bytes, s), "blocks clear");
@@ -909,6 +949,7 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         t->bspr = c.take<float>(nbk * d3);
         if (nrm) t->bdip = c.take<float4>(nbk * d3);
         if (compress) t->bq = c.take<uint2>(nbk * d3);
+        if (quadrupole) t->bquad = c.take<float4>(2 * nbk * d3);
     }
     for (int l = 0; l < n_levels; ++l) {
         if (n_int_lv[l] > 0 && btopo_lv[l]) {
@@ -924,12 +965,17 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         double4* agg64 = tmp.alloc<double4>(n_nodes);
         double4* dip64 = nrm ? tmp.alloc<double4>(n_nodes) : nullptr;
         double* spr64 = tmp.alloc<double>(n_nodes);
+        double* quad64 = quadrupole ? tmp.alloc<double>(6 * n_nodes) : nullptr;
         SBH_ALLOC_OK("allocating float64 aggregates");
         for (int l = n_levels - 1; l >= 0; --l) {
             k_aggregate<<<nblk(lv[l].n), 256, 0, s>>>((int32_t)off[l], lv[l].n, t->nbegin, t->ncount, t->nfirst,
                                                       t->nnchild, t->pts, t->pdip, agg64, dip64, spr64, t->nagg,
-                                                      t->ndip, t->nspr);
+                                                      t->ndip, t->nspr, quad64);
             SBH_TRY(hipGetLastError(), "aggregate kernel");
+        }
+        if (quadrupole && n_nodes > 1) {
+            k_pack_quad<<<nblk(n_nodes - 1), 256, 0, s>>>((int32_t)n_nodes, npblk, t->ndigit, quad64, t->bquad, d3);
+            SBH_TRY(hipGetLastError(), "quadrupole pack kernel");
         }
         if (compress && n_nodes > 1) {   // compressed aggregates, top-down from the root's
             double4* qagg = tmp.alloc<double4>(n_nodes);

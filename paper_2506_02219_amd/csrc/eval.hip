@@ -60,13 +60,14 @@ TreeView make_view(const sbh_tree_impl* t)
     v.nagg = t->nagg;
     v.ndip = t->ndip;
     v.bq = t->bq;
+    v.bquad = t->bquad;
     v.n_points = (int32_t)t->n_points;
     v.leaf_size = t->leaf_size;
     v.max_level = t->max_level;
     v.root_internal = (t->n_points > t->leaf_size && t->max_level > 0) ? 1 : 0;
     const uint64_t nbk = (uint64_t)(t->n_blocks > 0 ? t->n_blocks : 1);
-    const uint64_t big = std::max({nbk * (uint64_t)t->d3 * 16u, nbk * (uint64_t)topo_stride(t->d3) * 4u,
-                                   (uint64_t)t->n_points * 16u});
+    const uint64_t big = std::max({nbk * (uint64_t)t->d3 * (t->bquad ? 32u : 16u),
+                                   nbk * (uint64_t)topo_stride(t->d3) * 4u, (uint64_t)t->n_points * 16u});
     // SBH_FORCE_WIDE_OFFSETS=1 takes the 64-bit offsets for any tree (a diagnostic:
     // both forms give the same values bit for bit)
     const char* force = std::getenv("SBH_FORCE_WIDE_OFFSETS");
@@ -1296,6 +1297,282 @@ k_sbh_wave_q(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs
     sbh_wave_tile_q<K, TRACE, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
+// ---------------------------------------------------------------------------
+// The coherent walk with second-order node terms (d = 2, potential, uniform
+// path index).  A node's term is its point-mass term plus, where the query
+// sees it as far (|x| >= |B|, x = com - q), the next term of its Taylor
+// expansion about the centre of mass:
+//   m u + 1/2 u^5 (3 x^T Q x - tr(Q) (|x|^2 + eps^2)),  u = (|x|^2 + eps^2)^(-1/2),
+// with Q the node's second-moment tensor, stored per child slot scaled as
+// A = {1.5 Qxx, 1.5 Qyy, 1.5 Qzz, 3 Qxy}, {3 Qxz, 3 Qyz, tr(Q) / 2}, so that
+// the term is m u + u^5 (x^T A x - h (|x|^2 + eps^2)).  Points stay exact
+// (their tensor is zero), so a one-point node ends the walk as in wave_path.
+// Selection, random words and roulette are those of wave_path.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float term_l2(float m, float4 qa, float4 qb, float dx, float dy, float dz, float r2,
+                                         float diam2, float eps2)
+{
+#pragma clang fp contract(off)
+    const float s2 = r2 + eps2;
+    const float u = __builtin_amdgcn_rsqf(s2);
+    const float xa = fmaf(qa.x, dx, fmaf(qa.w, dy, qb.x * dz));
+    const float ya = fmaf(qa.y, dy, qb.y * dz);
+    const float xax = fmaf(dx, xa, fmaf(dy, ya, qa.z * (dz * dz)));
+    const float u2 = u * u;
+    const float c = (u2 * u2 * u) * fmaf(-qb.z, s2, xax);
+    return fmaf(m, u, r2 >= diam2 ? c : 0.0f);
+}
+
+template <bool TRACE, bool O64>
+__device__ __forceinline__ float wave_path_l2(const TreeView& tv, float qx, float qy, float qz, const KParams& kp,
+                                              bool valid, uint32_t n_a, uint32_t begin_a, int32_t blk_a, float4 agg_a,
+                                              float t_a, const PathWords& pw, uint32_t ctr0, uint32_t ctr1,
+                                              uint32_t ctr3, uint32_t key0, uint32_t key1, int rr_mode, int4* rec)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    constexpr int TS = topo_stride(D3);
+    constexpr float kInvD = 0.5f;
+    using Off = typename TreeOff<O64>::T;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t nT = n_a, beginT = begin_a;
+    int32_t blk = blk_a;
+    int level = 1;
+    float diamT = tv.diam0 * kInvD;
+    const float fna = (float)n_a;
+    uint64_t actm = __ballot(valid);
+    float dT = fsqrt(norm2(agg_a.x - qx, agg_a.y - qy, agg_a.z - qz));
+    float tT = t_a, prr = 1.0f, acc = 0.0f;
+    int steps = 0, flag = 0;
+    int32_t end_b = (int32_t)beginT, end_l = level;
+    const bool rr_eq5 = rr_mode == 0;
+    const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    auto roulette = [&](float r2C, float& dC) -> float {
+        const float ic = __builtin_amdgcn_rsqf(r2C);
+        dC = r2C * ic;
+        const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
+        return rr_eq5 ? p5 : rr_fixed;
+    };
+    int k = 0;
+    bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
+    const int lvl_int = tv.max_level - 1;
+    auto internal_step = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        uint32_t xsel;
+        float u;
+        if constexpr (M == 2) pw.step_late(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+        else pw.template step_held<M == 1>(k, ctr1, xsel, u);
+        const uint32_t r = __umulhi(xsel, nT);
+        const Off boff = (Off)(uint32_t)blk * (Off)(D3 * 16);   // the block's aggregates
+        const Off qoff = (Off)(uint32_t)blk * (Off)(D3 * 32);   // and its tensors
+        const Off toff = (Off)(uint32_t)blk * (Off)(TS * 4);
+        const uint32_t* __restrict__ bt = at_off(tv.btopo, toff);
+        const int ln = threadIdx.x & 63;
+        const uint32_t cl = gld(bt + (ln < D3 ? ln : TS - 1));
+        uint32_t inc = cl;
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);   // row_shr:1
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);   // row_shr:2
+        inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);   // row_shr:4
+        const uint32_t excl = inc - cl;
+        const uint32_t hm = (uint32_t)__ballot((r - excl) < cl);
+        const uint32_t im = level < lvl_int ? (uint32_t)__ballot((int)cl > tv.leaf_size) : 0u;
+        const uint32_t nonempty = (uint32_t)__ballot(cl != 0u);
+        const int csel = __builtin_ctz(hm);
+        const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)excl, csel);
+        const uint32_t nC = (uint32_t)__builtin_amdgcn_readlane((int)cl, csel);
+        const int32_t nintC = __popc(im & ((1u << csel) - 1u));
+        const float4 aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
+        const uint32_t beginC = beginT + preC;
+        const int32_t blkC = (int32_t)gld(bt + D3) + nintC;
+        float dC;
+        const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+        const float r2C = norm2(cx, cy, cz);
+        const float p = roulette(r2C, dC);
+        const uint64_t contm = __ballot(u < p) & actm;
+        if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
+            flag = 0;
+            end_b = (int32_t)beginT;
+            end_l = level;
+        }
+        actm = contm;
+        if (contm != 0ull) {
+            // contribution swap, Eq. (6), with second-order terms
+            const float diamC = diamT * kInvD, d2C = diamC * diamC;
+            const float4* __restrict__ bqd = at_off(tv.bquad, qoff);
+            const float tC = term_l2(aggC.w, gld4(bqd + 2 * csel), gld4(bqd + 2 * csel + 1), cx, cy, cz, r2C, d2C,
+                                     kp.eps2);
+            float sumc = tC;
+            const float4* __restrict__ ba = at_off(tv.bagg, boff);
+            float4 g8[D3];
+#pragma unroll
+            for (int c = 0; c < D3; ++c) g8[c] = gld4(ba + c);
+            const uint32_t rest = nonempty & ~(1u << csel);
+#pragma unroll
+            for (int c = 0; c < D3; ++c) {
+                if (!((rest >> c) & 1u)) continue;
+                const float ex = g8[c].x - qx, ey = g8[c].y - qy, ez = g8[c].z - qz;
+                sumc += term_l2(g8[c].w, gld4(bqd + 2 * c), gld4(bqd + 2 * c + 1), ex, ey, ez, norm2(ex, ey, ez), d2C,
+                                kp.eps2);
+            }
+            const bool cont = __builtin_amdgcn_inverse_ballot_w64(contm);
+            const float prr2 = prr * p;
+            const float acc2 = acc + (sumc - tT) * (fna * frcp((float)nT * prr2));
+            prr = cont ? prr2 : prr;
+            acc = cont ? acc2 : acc;
+            tT = cont ? tC : tT;
+            steps += cont ? 1 : 0;
+            dT = dC;
+            nT = nC;
+            beginT = beginC;
+            blk = blkC;
+            ++level;
+            diamT *= kInvD;
+            ++k;
+        }
+        go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
+    };
+    while (go && k < 16) {
+        internal_step(std::integral_constant<int, 0>{});
+        if (go) internal_step(std::integral_constant<int, 1>{});
+    }
+    while (go) internal_step(std::integral_constant<int, 2>{});
+    if (actm != 0ull) {
+        if (nT == 1u) {   // a single point: its node term is exact (a zero tensor)
+            if (__builtin_amdgcn_inverse_ballot_w64(actm)) { flag = 1; end_b = (int32_t)beginT; end_l = level; }
+        } else {          // a leaf: its points are the virtual children, one drawn uniformly
+            uint32_t xsel;
+            float u;
+            pw.step(k, ctr1, ctr0, ctr3, key0, key1, xsel, u);
+            const uint32_t r = __umulhi(xsel, nT);
+            const float4 aggC = gld4(at_off(tv.pts, (Off)(beginT + r) * (Off)16));
+            float dC;
+            const float cx = aggC.x - qx, cy = aggC.y - qy, cz = aggC.z - qz;
+            const float r2C = norm2(cx, cy, cz);
+            const float p = roulette(r2C, dC);
+            const uint64_t contm = __ballot(u < p) & actm;
+            if (__builtin_amdgcn_inverse_ballot_w64(actm & ~contm)) {
+                flag = 0;
+                end_b = (int32_t)beginT;
+                end_l = level;
+            }
+            if (contm != 0ull) {
+                float sumc = term_r2<SBH_POTENTIAL>(aggC, zero4, cx, cy, cz, r2C, kp, 0.0f);
+                for (uint32_t i = 0; i < nT; ++i) {
+                    if (i == r) continue;
+                    const Off po = (Off)(beginT + i) * (Off)16;
+                    sumc = term_acc<SBH_POTENTIAL>(gld4(at_off(tv.pts, po)), zero4, qx, qy, qz, kp, 0.0f, sumc);
+                }
+                if (__builtin_amdgcn_inverse_ballot_w64(contm)) {
+                    prr *= p;
+                    acc += (sumc - tT) * (fna * frcp((float)nT * prr));
+                    ++steps;
+                    flag = 2;
+                    end_b = (int32_t)(beginT + r);
+                    end_l = level + 1;
+                }
+            }
+        }
+    }
+    if constexpr (TRACE) *rec = make_int4(end_b, end_l, steps, flag);
+    return acc;
+}
+
+// One tile of 64 consecutive queries of the second-order walk (two wavefronts
+// per tile share the slots as k_sbh_wave's do).
+template <bool TRACE, int P, bool O64>
+__device__ __forceinline__ void sbh_wave_tile_l2(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
+                                                 const SbhArgs& a, float* __restrict__ out, int64_t wave, int part,
+                                                 int w, float (*part_f)[64], uint32_t* done)
+{
+#pragma clang fp contract(off)
+    constexpr int D3 = 8;
+    const int lane = threadIdx.x & 63;
+    const int64_t j0 = wave * 64;
+    if (j0 >= nq) return;
+    const int64_t j = j0 + lane;
+    const bool valid = j < nq;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (valid) {
+        qx = gld(queries + 3 * j);
+        qy = gld(queries + 3 * j + 1);
+        qz = gld(queries + 3 * j + 2);
+    }
+    KParams kp{a.eps2, a.alpha, 1.0f};
+    const uint32_t stream = (uint32_t)(j0 / a.group);
+    const uint32_t* __restrict__ rt = tv.btopo;
+    const int32_t base_root = (int32_t)gld(rt + D3);
+    const float diam1 = tv.diam0 * 0.5f, d21 = diam1 * diam1;
+    const int slot_lo = part * (D3 / P), slot_hi = slot_lo + D3 / P;
+    uint32_t begin_a = 0u;
+    int32_t nint = 0;
+    for (int slot = 0; slot < slot_lo; ++slot) {
+        const uint32_t n_a = gld(rt + slot);
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
+    float F = 0.0f;
+    PathWords pw;
+    for (int slot = slot_lo; slot < slot_hi; ++slot) {
+        const uint32_t n_a = gld(rt + slot);
+        if (n_a == 0u) {
+            if constexpr (TRACE) {
+                if (valid)
+                    for (int s = 0; s < a.samples; ++s)
+                        reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = make_int4(-1, 0, 0, 0);
+            }
+            continue;
+        }
+        const int32_t blk_a = base_root + nint;
+        const float4 agg_a = gld4(tv.bagg + slot);
+        const float dx = agg_a.x - qx, dy = agg_a.y - qy, dz = agg_a.z - qz;
+        const float cv = term_l2(agg_a.w, gld4(tv.bquad + 2 * slot), gld4(tv.bquad + 2 * slot + 1), dx, dy, dz,
+                                 norm2(dx, dy, dz), d21, kp.eps2);   // control variate CV_a
+        float fa = 0.0f;
+        for (int s = 0; s < a.samples; ++s) {
+            int4 rec;
+            const uint32_t path = (uint32_t)(slot * a.samples + s);
+            pw.need(path, stream, a.batch, a.key0, a.key1);
+            fa += wave_path_l2<TRACE, O64>(tv, qx, qy, qz, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw, stream, path,
+                                           a.batch, a.key0, a.key1, a.rr_mode, &rec);
+            if constexpr (TRACE) {
+                if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
+            }
+        }
+        F += cv + fa / (float)a.samples;
+        begin_a += n_a;
+        nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
+    }
+    if constexpr (P > 1) {
+        const int tl = w / P;
+        part_f[w][lane] = F;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t prev = 0u;
+        if (lane == 0) prev = __hip_atomic_fetch_add(&done[tl], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__builtin_amdgcn_readfirstlane(prev) != (uint32_t)(P - 1)) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        F = part_f[tl * P][lane];
+#pragma unroll
+        for (int q = 1; q < P; ++q) F += part_f[tl * P + q][lane];
+    }
+    if (valid) gst(out + j, query_value<SBH_POTENTIAL>(F, 0.0f, 0.0f, a.alpha, qx, qy, qz));
+}
+
+template <bool TRACE, bool O64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_sbh_wave_l2(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
+{
+    constexpr int P = kWaveParts, TPB = 4 / P;
+    __shared__ float part_f[4][64];
+    __shared__ uint32_t done[TPB];
+    if constexpr (P > 1) {
+        if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
+    sbh_wave_tile_l2<TRACE, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+}
+
 // Sum over the 64 lanes of eight values per lane, in a fixed order, on the
 // vector unit (no LDS): a swap between the wavefront's halves and one between
 // row pairs (gfx950 lane-swap instructions) each halve the values a lane
@@ -2098,6 +2375,19 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
         if (e.kernel == SBH_POTENTIAL) return launch_leaf<SBH_POTENTIAL>(tv, queries, nq, e, out, s);
         if (e.kernel == SBH_WINDING) return launch_leaf<SBH_WINDING>(tv, queries, nq, e, out, s);
         return launch_leaf<SBH_SMOOTHDIST>(tv, queries, nq, e, out, s);
+    }
+    if (e.lod == 2) {   // second-order node terms (d = 2, potential, G a multiple of 64)
+        SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
+                  e.eps * e.eps, e.alpha, e.paths};
+        const unsigned wblocks = (unsigned)(((nq + 63) / 64 + (4 / kWaveParts) - 1) / (4 / kWaveParts));
+        if (tv.wide) {
+            if (e.paths) k_sbh_wave_l2<true, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
+            else k_sbh_wave_l2<false, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
+        } else {
+            if (e.paths) k_sbh_wave_l2<true, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
+            else k_sbh_wave_l2<false, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
+        }
+        return hipGetLastError();
     }
     if (e.compressed) {   // the coherent walk on compressed aggregates (d = 2, potential or smooth distance)
         SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),

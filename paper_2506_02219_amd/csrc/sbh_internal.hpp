@@ -44,6 +44,7 @@ struct TreeView {
     const float4* nagg;   // nagg[0] = root aggregate
     const float4* ndip;
     const uint2* bq;      // compressed child aggregates, or NULL
+    const float4* bquad;  // scaled second-moment tensors (two float4 per child slot), or NULL
     int32_t n_points;
     int32_t leaf_size;
     int32_t max_level;
@@ -101,6 +102,10 @@ struct sbh_tree_impl {
     // compressed aggregates (built on request): per child slot two words, binary16
     // {offset x | offset y << 16, offset z | mass fraction << 16}; NULL when absent
     uint2* bq;
+    // second-order LOD (built on request): per child slot two float4, the second-moment
+    // tensor Q about the child's centre of mass, scaled for the term's evaluation:
+    // {1.5 Qxx, 1.5 Qyy, 1.5 Qzz, 3 Qxy}, {3 Qxz, 3 Qyz, tr(Q) / 2, 0}; NULL when absent
+    float4* bquad;
     void* slab[3];   // the allocations the arrays above are carved from: points, nodes, blocks
     size_t slab_bytes[3];
 };
@@ -359,6 +364,7 @@ struct EvalLaunch {
     int tile_score;     // coherent walk with the tile-shared score proposal (d = 2, group % 64 == 0)
     int cut;            // subdomains: the Barnes-Hut cut at beta (group % 64 == 0, d = 2 or 4)
     int compressed;     // the coherent walk on the compressed aggregates (d = 2, potential or smooth distance)
+    int lod;            // 2: second-order node terms (potential, d = 2, coherent walk)
 };
 
 hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t nq, const EvalLaunch& e,
@@ -368,7 +374,8 @@ hipError_t launch_bh_eval(const sbh_tree_impl* t, const float* queries, int64_t 
 hipError_t launch_brute(const float* src, const float* w, const float* nrm, int64_t n, const float* queries,
                         int64_t nq, int kernel, float eps, float alpha, int fp64, void* out, hipStream_t s);
 sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, int64_t n, int d, int leaf_size,
-                           int max_level, int compress, hipStream_t s, sbh_tree_impl* t, std::string* msg);
+                           int max_level, int compress, int quadrupole, hipStream_t s, sbh_tree_impl* t,
+                           std::string* msg);
 
 TreeView make_view(const sbh_tree_impl* t);
 

@@ -83,6 +83,20 @@ def compressed_codes_by_node(gt):
     return code
 
 
+def quadrupole_by_node(gt):
+    """The GPU tree's scaled second-moment tensors [n_nodes, 8] (the root's row zero), mapped from the
+    child blocks to node order as compressed_codes_by_node does."""
+    g = gt.export()
+    blocks = gt.export_quadrupole()
+    internal = g["first_child"] >= 0
+    rank = np.cumsum(internal) - 1
+    out = np.zeros((gt.n_nodes, 8), np.float32)
+    par = g["parent"].astype(np.int64)
+    v = np.arange(1, gt.n_nodes)
+    out[v] = blocks[rank[par[v]], g["digit"][v]]
+    return out
+
+
 def compare_trees(gt, ot):
     """Bit-exact topology; aggregates to float32 accuracy."""
     g = gt.export()
@@ -159,27 +173,29 @@ def value_errors(gpu, F, absum, kernel, alpha=100.0, sens=None):
 
 def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, eps=1e-3, alpha=100.0,
               index=None, gpu_out=None, gpu_paths=None, batch=0, mlp=None, near_tie=NEAR_TIE,
-              max_divergent=1e-5, proposal=None, tile_all=None, max_fp32_share=0.01, compressed=False):
+              max_divergent=1e-5, proposal=None, tile_all=None, max_fp32_share=0.01, compressed=False, lod=1):
     """Run (or take) the GPU estimator and compare with the oracle, query by query.
     With `index`, `queries` are a subset of a larger set evaluated on the GPU
     (gpu_out/gpu_paths are the full-set outputs).  mlp: float32 network
     parameters (numpy) for the learned proposal on both sides; proposal=2 runs the
     score proposal on the GPU against the oracle's all-zero network; proposal=3 the tile-shared
     score proposal (tile_all: the full query set when `queries` is a subset); compressed: both sides
-    walk on the compressed aggregates (the GPU tree built with compress=True)."""
+    walk on the compressed aggregates (the GPU tree built with compress=True); lod=2: both sides take
+    second-order node terms (the GPU tree built with quadrupole=True)."""
     d3 = gt.branching ** 3
     if gpu_out is None:
         q = T(queries)
         paths = torch.full((queries.shape[0], d3, samples, 4), -7, dtype=torch.int32, device=DEV)
         out = P.sbh_eval(gt, q, kernel, samples=samples, seed=seed, eps=eps, alpha=alpha, group=group,
                          rr_mode=rr_mode, paths=paths, batch=batch, mlp=None if mlp is None else T(mlp),
-                         proposal=proposal, compressed=int(compressed))
+                         proposal=proposal, compressed=int(compressed), lod=lod)
         g = host(out)
         gp = host(paths)
     else:
         g = gpu_out[index]
         gp = gpu_paths[index]
     ot.set_compressed(compressed)
+    ot.set_lod(lod)
     try:
         r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps, alpha=alpha,
                    paths=True, index=index, batch=batch,
@@ -187,6 +203,7 @@ def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, ep
                    tile_queries=(queries if tile_all is None else tile_all) if proposal == 3 else None)
     finally:
         ot.set_compressed(False)
+        ot.set_lod(1)
     near = r["margin"] < near_tie
     path_bad = np.any(gp != r["paths"], axis=(1, 2, 3))
     ok, err, used_bound = value_errors(g, r["F"], r["absum"], kernel, alpha, r["sens"])

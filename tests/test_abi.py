@@ -24,7 +24,7 @@ def test_header_declares_the_boundary():
               "sbh_status_string", "sbh_last_error", "sbh_build_opts_default", "sbh_eval_opts_default",
               "sbh_mlp_forward", "sbh_mlp_pairs", "sbh_mlp_loss_grad", "sbh_mlp_train",
               "sbh_batch_create", "sbh_batch_launch", "sbh_batch_get_config", "sbh_batch_free",
-              "sbh_tree_export_compressed"):
+              "sbh_tree_export_compressed", "sbh_tree_export_quadrupole"):
         assert n in names
 
 
@@ -46,10 +46,10 @@ def test_status_strings_and_defaults():
     o = P.EvalOpts()
     L.sbh_eval_opts_default(ctypes.byref(o))
     assert (round(o.eps, 6), o.alpha, o.group, o.rr_mode, o.proposal, o.batch, o.paths, o.mlp, o.subdomains,
-            o.compressed) == (0.001, 100.0, 1, 0, 0, 0, None, None, 0, 0)
+            o.compressed, o.lod) == (0.001, 100.0, 1, 0, 0, 0, None, None, 0, 0, 0)
     b = P.BuildOpts()
     L.sbh_build_opts_default(ctypes.byref(b))
-    assert (b.branching, b.leaf_size, b.max_level, b.compress) == (2, 8, 0, 0)
+    assert (b.branching, b.leaf_size, b.max_level, b.compress, b.quadrupole) == (2, 8, 0, 0, 0)
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -58,7 +58,8 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [("sbh_build_opts", None), ("sbh_eval_opts", None), ("sbh_eval_opts", "paths"),
               ("sbh_eval_opts", "mlp"), ("sbh_eval_opts", "batch"), ("sbh_eval_opts", "subdomains"),
-              ("sbh_eval_opts", "compressed"), ("sbh_build_opts", "compress"), ("sbh_tree_desc", None),
+              ("sbh_eval_opts", "compressed"), ("sbh_build_opts", "compress"),
+              ("sbh_eval_opts", "lod"), ("sbh_build_opts", "quadrupole"), ("sbh_tree_desc", None),
               ("sbh_tree_desc", "lo"), ("sbh_tree_desc", "inv_side"), ("sbh_batch_item", None),
               ("sbh_batch_item", "nq"), ("sbh_batch_item", "kernel"), ("sbh_batch_config", None),
               ("sbh_batch_config", "ms")]
@@ -72,7 +73,8 @@ def test_struct_layouts_match_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(P.BuildOpts), ctypes.sizeof(P.EvalOpts), P.EvalOpts.paths.offset, P.EvalOpts.mlp.offset,
             P.EvalOpts.batch.offset, P.EvalOpts.subdomains.offset, P.EvalOpts.compressed.offset,
-            P.BuildOpts.compress.offset, ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset,
+            P.BuildOpts.compress.offset, P.EvalOpts.lod.offset, P.BuildOpts.quadrupole.offset,
+            ctypes.sizeof(P.TreeDesc), P.TreeDesc.lo.offset, P.TreeDesc.inv_side.offset,
             ctypes.sizeof(P.BatchItem), P.BatchItem.nq.offset, P.BatchItem.kernel.offset, ctypes.sizeof(P.BatchConfig),
             P.BatchConfig.ms.offset]
     assert got == want
