@@ -1808,15 +1808,23 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
 // (the launch's floor on its duration) at the price of one more Philox
 // evaluation per part.  LDS: part_f [wavefronts of the block][64] and one
 // counter per tile of the block in `done`, zeroed before the block's first
-// barrier.
+// barrier.  four (P = 2, d = 2: the last tiles of a launch): the tile is
+// split over four wavefronts of two slots each, which store each slot's
+// total in part_f [slot][64]; the last of them adds the totals in the
+// association of two parts (slots 0-3 in order, slots 4-7 in order, then
+// the two sums), so a query's value does not depend on how its tile was
+// split.  (A run-time choice: one inlined walk serves both splits.)
 template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave, int part = 0,
-                                              int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr)
+                                              int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr,
+                                              bool four = false)
 {
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     static_assert(D3 % P == 0, "parts must split the root slots evenly");
+    constexpr bool kFour = D == 2 && P == 2;   // the four-way split is available
+    if constexpr (!kFour) four = false;
     const int lane = threadIdx.x & 63;
     const int64_t j0 = wave * 64;
     if (j0 >= nq) return;
@@ -1839,7 +1847,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     (void)inv_valid;
     const uint32_t* __restrict__ rt = tv.btopo;
     const int32_t base_root = (int32_t)gld(rt + D3);
-    const int slot_lo = part * (D3 / P), slot_hi = slot_lo + D3 / P;
+    const int nslots = four ? 2 : D3 / P;
+    const int slot_lo = part * nslots, slot_hi = slot_lo + nslots;
     uint32_t begin_a = 0u;
     int32_t nint = 0;
     for (int slot = 0; slot < slot_lo; ++slot) {   // points and internal blocks of the slots before the part
@@ -1879,11 +1888,27 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
             }
         }
-        F += cv + fa / (float)a.samples;
+        const float vs = cv + fa / (float)a.samples;
+        if (kFour && four) part_f[slot][lane] = vs;
+        else F += vs;
         begin_a += n_a;
         nint += ((int)n_a > tv.leaf_size && 1 < tv.max_level) ? 1 : 0;
     }
-    if constexpr (P > 1) {
+    if (kFour && four) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        uint32_t prev = 0u;
+        if (lane == 0) prev = __hip_atomic_fetch_add(&done[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__builtin_amdgcn_readfirstlane(prev) != 3u) return;   // another part finishes the tile
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        float fa_lo = 0.0f, fa_hi = 0.0f;
+#pragma unroll
+        for (int slot = 0; slot < 4; ++slot)
+            if (gld(rt + slot) != 0u) fa_lo += part_f[slot][lane];
+#pragma unroll
+        for (int slot = 4; slot < 8; ++slot)
+            if (gld(rt + slot) != 0u) fa_hi += part_f[slot][lane];
+        F = fa_lo + fa_hi;
+    } else if constexpr (P > 1) {
         const int tl = w / P;   // the tile's index within the block
         part_f[w][lane] = F;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1898,20 +1923,39 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
     if (valid) gst(out + j, query_value<K>(F, r0, logwbar, a.alpha, qx, qy, qz));
 }
 
+// Tiles below split_tile: TPB tiles per block, each over kWaveParts wavefronts;
+// from split_tile on (d = 2, the end of the launch, where the last wavefronts
+// run on a partly idle chip): one tile per block over all four wavefronts,
+// which halves the chain of steps each of them walks.
 template <int D, int K, bool TRACE, bool O64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
+k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out,
+           int64_t split_tile)
 {
     constexpr int P = kWaveParts, TPB = 4 / P;   // 4 wavefronts per block, TPB tiles
-    __shared__ float part_f[4][64];
+    static_assert(P == 2, "the tail split assumes two parts per tile");
+    __shared__ float part_f[D == 2 ? 8 : 4][64];
     __shared__ uint32_t done[TPB];
-    if constexpr (P > 1) {
-        if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
-        __syncthreads();
-    }
+    if (threadIdx.x < TPB) done[threadIdx.x] = 0u;
+    __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile<D, K, TRACE, false, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+    const int64_t nb2 = split_tile / TPB;
+    const bool four = D == 2 && (int64_t)blockIdx.x >= nb2;
+    const int64_t tile = four ? split_tile + ((int64_t)blockIdx.x - nb2) : (int64_t)blockIdx.x * TPB + w / P;
+    sbh_wave_tile<D, K, TRACE, false, P, O64>(tv, queries, nq, a, out, tile, four ? w : w % P, w, part_f, done, four);
+}
+
+// Tiles of the launch's four-part tail (d = 2): kTailTiles, or SBH_TAIL_TILES
+// from the environment (a tuning override; values are the same for any split).
+constexpr int64_t kTailTiles = 1024;
+static int64_t tail_tiles()
+{
+    const char* e = std::getenv("SBH_TAIL_TILES");
+    if (e && e[0]) {
+        const long long v = std::atoll(e);
+        return v < 0 ? 0 : (int64_t)v;
+    }
+    return kTailTiles;
 }
 
 // the coherent walk with the tile-shared score proposal (d = 2)
@@ -2299,12 +2343,21 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             }
             return hipErrorInvalidValue;
         }
+        // d = 2: the last tiles over four wavefronts each (split_tile a multiple of the two
+        // tiles a block takes before it)
+        constexpr int64_t TPB = 4 / kWaveParts;
+        int64_t split = (tiles + TPB - 1) / TPB * TPB;
+        unsigned blocks = wblocks;
+        if constexpr (D == 2) {
+            split = std::max<int64_t>(0, tiles - std::min(tail_tiles(), tiles)) / TPB * TPB;
+            blocks = (unsigned)(split / TPB + (tiles - split));
+        }
         if (tv.wide) {
-            if (e.paths) k_sbh_wave<D, K, true, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
-            else k_sbh_wave<D, K, false, true><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+            if (e.paths) k_sbh_wave<D, K, true, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
+            else k_sbh_wave<D, K, false, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
         } else {
-            if (e.paths) k_sbh_wave<D, K, true, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
-            else k_sbh_wave<D, K, false, false><<<wblocks, 256, 0, s>>>(tv, q, nq, a, out);
+            if (e.paths) k_sbh_wave<D, K, true, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
+            else k_sbh_wave<D, K, false, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
         }
         return hipGetLastError();
     }

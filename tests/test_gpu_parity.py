@@ -122,6 +122,32 @@ def test_sbh_deterministic_and_launch_independent(G):
     assert np.array_equal(part, a[:1000])
 
 
+@pytest.mark.parametrize("kernel", [P.POTENTIAL, P.WINDING, P.SMOOTHDIST])
+@pytest.mark.parametrize("S", [1, 3])
+def test_sbh_tail_split_gives_the_same_values(kernel, S, monkeypatch):
+    """The coherent walk (d = 2) walks the last tiles of a launch over four wavefronts instead of
+    two and adds the slot totals in the two-part association: every value and path must be the
+    same bit for bit whatever the number of four-part tiles (none, some, all), on a ragged count."""
+    src, nrm, w = surface(20000, seed=35)
+    nq = 64 * 37 + 21
+    q = T(box_queries(nq, 36))
+    gt = P.sbh_build(T(src), T(w), T(nrm) if kernel == P.WINDING else None)
+
+    def run():
+        paths = torch.full((nq, 8, S, 4), -7, dtype=torch.int32, device=DEV)
+        out = P.sbh_eval(gt, q, kernel, samples=S, seed=5, group=64, paths=paths, alpha=100.0)
+        plain = P.sbh_eval(gt, q, kernel, samples=S, seed=5, group=64, alpha=100.0)
+        return [host(out), host(paths), host(plain)]
+
+    res = []
+    for tail in ("0", "7", "20", "100000"):
+        monkeypatch.setenv("SBH_TAIL_TILES", tail)
+        res.append(run())
+    for r in res[1:]:
+        for x, y in zip(res[0], r):
+            assert np.array_equal(x, y, equal_nan=True)
+
+
 @pytest.mark.parametrize("kernel,branching", [(P.POTENTIAL, 2), (P.WINDING, 2), (P.SMOOTHDIST, 4)])
 def test_sbh_wide_offsets_give_the_same_walk(kernel, branching, monkeypatch):
     """The coherent walks and Barnes-Hut take 32-bit byte offsets into trees below 4 GiB and
