@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--no-cut", action="store_true", help="skip the Barnes-Hut-cut subdomains")
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-aggregate walk")
     ap.add_argument("--no-lod2", action="store_true", help="skip the second-order (quadrupole) walk")
+    ap.add_argument("--no-vote", action="store_true", help="skip the roulette voted over the wavefront")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -159,12 +160,13 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
-ABLATION_RR = {0: "eq5", 1: "p=1", 2: "p=1/2"}
+ABLATION_RR = {0: "eq5", 1: "p=1", 2: "p=1/2", 3: "eq5 voted over the wavefront"}
 
 
 def ablation(args):
     """The paper's roulette study (Appendix C) and the branching factor (Section 3.3): the estimator
-    with Eq. (5), with p = 1 (no roulette) and with p = 1/2, on trees of branching 2 and 4, on the
+    with Eq. (5), with p = 1 (no roulette), with p = 1/2 and with Eq. (5) voted over each wavefront's
+    64 queries, on trees of branching 2 and 4, on the
     potential (c1), winding (c2, shuffled plane) and smooth-distance (c3) workloads; one sample per
     subdomain, G = 64 (the coherent walk).  Time per evaluation of every query (HIP events, median
     of rounds of K launches) and median relative error against float64 brute force on a fixed
@@ -191,7 +193,7 @@ def ablation(args):
         out = torch.empty(N, dtype=torch.float32, device=dev)
         for d in (2, 4):
             tree = P.sbh_build(src, wts, nrm, branching=d, leaf_size=8)
-            for rr in (0, 1, 2):
+            for rr in (0, 1, 2, 3):
                 def run(rr=rr):
                     P.sbh_eval(tree, qry, kernel, samples=1, seed=0, group=64, rr_mode=rr, out=out)
                 for _ in range(2):
@@ -528,6 +530,20 @@ def main():
                                       median_rel_err=err_of(lambda: run_l2(sv))))
         qtree.free()
 
+    # --- the roulette voted over each wavefront (rr_mode 3: every query of a tile continues with the
+    # largest Eq. (5) p of the tile's queries), same tree and queries, with an S sweep
+    voted = None
+    if not args.no_vote and args.group % 64 == 0:
+        def run_vote(samples=S):
+            P.sbh_eval(tree, qry, kernel, samples=samples, seed=0, group=args.group, out=out, rr_mode=3)
+
+        ms_v = timed(run_vote, args.steps, args.warmup)
+        voted = dict(group=args.group, samples=S, ms_per_step=ms_v, queries_per_s=N / (ms_v * 1e-3),
+                     median_rel_err=err_of(run_vote), vs_headline=ms_per_step / ms_v, sweep=[])
+        for sv in (2, 4):
+            voted["sweep"].append(dict(samples=sv, ms=timed(lambda: run_vote(sv), 3, 1),
+                                       median_rel_err=err_of(lambda: run_vote(sv))))
+
     # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
     # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
     # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
@@ -538,7 +554,7 @@ def main():
 
         # sweep until Barnes-Hut is well below every error it is compared at
         e_floor = min([err_star] + ([c_["median_rel_err"] for c_ in cut["sweep"]] if cut else [])
-                      + ([lod2["median_rel_err"]] if lod2 else []))
+                      + ([lod2["median_rel_err"]] if lod2 else []) + ([voted["median_rel_err"]] if voted else []))
 
         def bh_sweep(qset, idx_t):
             pts = []
@@ -582,6 +598,15 @@ def main():
                 tb = at_error(pts_s, c_["median_rel_err"])[0]
                 c_["bh_ms_at_this_error"] = tb
                 c_["speedup_vs_bh_at_this_error"] = None if tb is None else tb / c_["ms"]
+        if voted is not None:
+            tb = at_error(pts_s, voted["median_rel_err"])[0]
+            voted["bh_ms_at_this_error"] = tb
+            voted["speedup_vs_bh_at_this_error"] = None if tb is None else tb / voted["ms_per_step"]
+            # the headline estimator (Eq. (5)) at the voted roulette's error, from its S sweep
+            if sweep:
+                te = log_interp([r["median_rel_err"] for r in sweep], [r["ms"] for r in sweep], voted["median_rel_err"])
+                voted["eq5_ms_at_this_error"] = te
+                voted["speedup_vs_eq5_at_this_error"] = None if te is None else te / voted["ms_per_step"]
         if lod2 is not None:
             tb = at_error(pts_s, lod2["median_rel_err"])[0]
             lod2["bh_ms_at_this_error"] = tb
@@ -793,6 +818,7 @@ def main():
         "cut_subdomains": cut,
         "compressed_aggregates": compressed,
         "second_order_lod": lod2,
+        "voted_roulette": voted,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,

@@ -86,7 +86,11 @@ typedef struct sbh_eval_opts {
     int32_t group;       /* G >= 1: queries j with equal floor(j/G) share one random
                             stream (G = 1: every query has its own); default 1 */
     int32_t rr_mode;     /* Russian roulette: 0 = Eq. (5) (default), 1 = p = 1 (none),
-                            2 = p = 1/2 (the two comparisons of the supplement) */
+                            2 = p = 1/2 (the two comparisons of the supplement), 3 = Eq. (5)
+                            voted over each tile of 64 consecutive queries: every query of
+                            the tile continues with the largest Eq. (5) p among the tile's
+                            queries with finite coordinates (still unbiased, Theorem 1); needs
+                            group a multiple of 64, the uniform proposal and subdomains 0 */
     int32_t proposal;    /* child-selection distribution: 0 = uniform path index
                             (the paper's, default); 1 = the learned proposal with
                             network parameters opts->mlp; 2 = the score proposal

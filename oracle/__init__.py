@@ -34,6 +34,8 @@ def lib():
         L.orc_tree_build.argtypes = [P, P, P, i64, i32, i32, i32]
         L.orc_tree_build.restype = P
         L.orc_tree_free.argtypes = [P]
+        L.orc_sbh_vote.argtypes = [P, P, i64, i32, f64, f64, i32, u64, i32, u32, P, P, P, P, P, P, i32]
+        L.orc_sbh_vote_expect.argtypes = [P, P, i64, i32, f64, f64, P, i32]
         L.orc_tree_set_lod.argtypes = [P, i32]
         L.orc_tree_set_lod.restype = i32
         L.orc_tree_quad.argtypes = [P, P]
@@ -216,6 +218,31 @@ class Tree:
         if paths:
             r["paths"] = pth
         return r
+
+    def sbh_vote(self, queries, kernel, samples=1, seed=0, group=64, batch=0, eps=1e-3, alpha=100.0,
+                 paths=False, index=None, threads=0):
+        """Algorithm 2 with the roulette voted over each tile (rr_mode 3): every query of a tile of 64
+        consecutive indices (sharing one stream: group a multiple of 64) continues with the largest
+        Eq. (5) probability among the tile's queries.  index: original indices of the queries (whole
+        tiles, in order); returns dict(F, margin, absum, sens[, paths])."""
+        q = _f32(queries, (-1, 3)); n = q.shape[0]
+        idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
+        out = np.zeros(n); mg = np.zeros(n); ab = np.zeros(n); sn = np.zeros(n)
+        d3 = self.d ** 3
+        pth = np.zeros((n, d3, samples, 4), np.int32) if paths else None
+        lib().orc_sbh_vote(self._h, _p(q), n, kernel, eps, alpha, samples, seed, group, batch, _p(idx), _p(out),
+                           _p(mg), _p(ab), _p(sn), _p(pth), threads)
+        r = dict(F=out, margin=mg, absum=ab, sens=sn)
+        if paths:
+            r["paths"] = pth
+        return r
+
+    def vote_expect(self, queries, kernel, eps=1e-3, alpha=100.0, threads=0):
+        """Exact expectation (Theorem 1) of the one-sample estimator with the roulette voted over tiles
+        of 64 consecutive queries."""
+        q = _f32(queries, (-1, 3)); out = np.zeros(q.shape[0])
+        lib().orc_sbh_vote_expect(self._h, _p(q), q.shape[0], kernel, eps, alpha, _p(out), threads)
+        return out
 
     def sbh_cut(self, queries, kernel, beta_low, samples=1, seed=0, group=64, vote=64, batch=0, rr_mode=0,
                 eps=1e-3, alpha=100.0, index=None, expect=False, threads=0):

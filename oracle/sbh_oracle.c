@@ -1173,6 +1173,203 @@ void orc_sbh(const orc_tree* t, const float* qry, int64_t n, int kernel, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* The roulette voted over a tile (rr_mode 3).  The queries of a tile of 64  */
+/* consecutive indices share one random stream (G a multiple of 64), so     */
+/* under the uniform path index they walk the same node sequence and test   */
+/* the same variate u.  Here the tile also shares the roulette probability: */
+/* at each step every query of the tile continues with p = the largest      */
+/* Eq. (5) probability among the tile's queries with finite coordinates (a  */
+/* probability fixed before u is drawn, so each query's estimate stays      */
+/* unbiased, as for any roulette in (0, 1]; Theorem 1).  The tile stops or  */
+/* continues together.  Counters, selection and the estimate are those of   */
+/* sample_path.  Per query: value, margin (|u - p| of its tile's            */
+/* decisions), absum, sens and path records as orc_sbh's.                   */
+/* ------------------------------------------------------------------------ */
+static int finite3(const double* q) { return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]); }
+
+/* the voted probability of the step from T onto child c (c < 0: onto point `target` of leaf T) */
+static double vote_prob(const orc_tree* t, const double* qs, int gn, int64_t T, int64_t c, int64_t target)
+{
+    double pw = 0.0;
+    for (int g = 0; g < gn; ++g) {
+        const double* q = &qs[3 * g];
+        if (!finite3(q)) continue;
+        double bT = dist3(node_com(t, T), q) / node_diam(t, T);
+        double bc = c >= 0 ? dist3(node_com(t, c), q) / node_diam(t, c)
+                           : dist3(&t->pxyz[3 * target], q) / point_diam(t, T);
+        double p = rr_prob(0, bT, bc);
+        if (p > pw) pw = p;
+    }
+    return pw;
+}
+static void vote_group(const orc_tree* t, const kparams* kp, const double* qs, int gn, uint32_t sigma, int S,
+                       uint64_t seed, uint32_t batch, int d3, double* F, double* A, double* SN, double* mg,
+                       int32_t* paths)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    double* tT = malloc(sizeof(double) * gn);
+    double* acc = malloc(sizeof(double) * gn);
+    double* ab = malloc(sizeof(double) * gn);
+    double* sn = malloc(sizeof(double) * gn);
+    double* sum = malloc(sizeof(double) * gn);
+    double* abc = malloc(sizeof(double) * gn);
+    double* snc = malloc(sizeof(double) * gn);
+    double* tc = malloc(sizeof(double) * gn);
+    double* Fa = malloc(sizeof(double) * gn);
+    double* Aa = malloc(sizeof(double) * gn);
+    double* Sa = malloc(sizeof(double) * gn);
+    for (int ci = 0; ci < t->nchild[0]; ++ci) {
+        int64_t a = t->first_child[0] + ci;
+        int slot = t->digit[a];
+        for (int g = 0; g < gn; ++g) { Fa[g] = 0.0; Aa[g] = 0.0; Sa[g] = 0.0; }
+        for (int s = 0; s < S; ++s) {
+            int64_t T = a;
+            double p_sel = 1.0, p_rr = 1.0;
+            int32_t end_b = (int32_t)t->begin[a], end_l = t->level[a], steps = 0, flags = 0;
+            for (int g = 0; g < gn; ++g) {
+                tT[g] = node_term_m(t, kp, a, &qs[3 * g], &mg[g]);
+                acc[g] = 0.0; ab[g] = 0.0; sn[g] = 0.0;
+            }
+            for (int k = 0;; ++k) {
+                int64_t nT = t->count[T];
+                end_b = (int32_t)t->begin[T];
+                end_l = t->level[T];
+                if (nT == 1 && !t->cmp) { flags = 1; break; }
+                uint32_t ctr[4] = {sigma, (uint32_t)(slot * S + s), (uint32_t)(k >> 1), batch}, rnd[4];
+                orc_philox4x32_10(ctr, key, rnd);
+                uint32_t x_sel = rnd[2 * (k & 1)], x_rr = rnd[2 * (k & 1) + 1];
+                double u = (double)(x_rr >> 8) * (1.0 / 16777216.0);
+                int64_t r = (int64_t)(((uint64_t)x_sel * (uint64_t)nT) >> 32);
+                int64_t target = t->begin[T] + r, c = -1;
+                double q_c;
+                int internal = is_internal(t, T);
+                if (internal) {
+                    for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
+                        if (target >= t->begin[ch] && target < t->begin[ch] + t->count[ch]) c = ch;
+                    q_c = (double)t->count[c] / (double)nT;
+                } else {
+                    q_c = 1.0 / (double)nT;
+                }
+                /* every query's Eq. (5) probability at this step; the tile takes the largest */
+                double pw = vote_prob(t, qs, gn, T, internal ? c : -1, target);
+                for (int g = 0; g < gn; ++g) {
+                    double m = fabs(u - pw);
+                    if (m < mg[g]) mg[g] = m;
+                }
+                if (u >= pw) { flags = 0; break; }
+                p_rr *= pw;
+                double wgt = 1.0 / (p_sel * p_rr);
+                for (int g = 0; g < gn; ++g) {
+                    const double* q = &qs[3 * g];
+                    sum[g] = 0.0; abc[g] = 0.0; snc[g] = node_sens(t, kp, T, q);
+                    if (internal) {
+                        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+                            double v = node_term_m(t, kp, ch, q, &mg[g]);
+                            sum[g] += v;
+                            abc[g] += fabs(v);
+                            snc[g] += node_sens(t, kp, ch, q);
+                        }
+                        tc[g] = node_term(t, kp, c, q);
+                    } else {
+                        for (int64_t p = t->begin[T]; p < t->begin[T] + nT; ++p) {
+                            double v = point_term(t, kp, p, q);
+                            sum[g] += v;
+                            abc[g] += fabs(v);
+                        }
+                    }
+                    acc[g] += (sum[g] - tT[g]) * wgt;
+                    ab[g] += (abc[g] + fabs(tT[g])) * wgt;
+                    sn[g] += snc[g] * wgt;
+                }
+                steps += 1;
+                p_sel *= q_c;
+                if (!internal) {
+                    end_b = (int32_t)target;
+                    end_l = t->level[T] + 1;
+                    flags = 2;
+                    break;
+                }
+                T = c;
+                for (int g = 0; g < gn; ++g) tT[g] = tc[g];
+            }
+            for (int g = 0; g < gn; ++g) { Fa[g] += acc[g]; Aa[g] += ab[g]; Sa[g] += sn[g]; }
+            if (paths)
+                for (int g = 0; g < gn; ++g) {
+                    int32_t* rec = &paths[((int64_t)g * d3 * S + (int64_t)slot * S + s) * 4];
+                    rec[0] = end_b; rec[1] = end_l; rec[2] = steps; rec[3] = flags;
+                }
+        }
+        for (int g = 0; g < gn; ++g) {
+            const double* q = &qs[3 * g];
+            double cv = node_term_m(t, kp, a, q, &mg[g]);
+            F[g] += cv + Fa[g] / S;
+            A[g] += fabs(cv) + Aa[g] / S;
+            SN[g] += node_sens(t, kp, a, q) + Sa[g] / S;
+        }
+    }
+    free(tT); free(acc); free(ab); free(sn); free(sum); free(abc); free(snc); free(tc);
+    free(Fa); free(Aa); free(Sa);
+}
+
+/* The voted roulette for n queries; stream id floor(qindex[j] / G) (qindex
+ * NULL: j), G a multiple of 64; the queries vote in tiles of 64 consecutive
+ * indices: a tile is a run of consecutive entries with equal floor(index /
+ * 64) (a subset must hold whole tiles). */
+void orc_sbh_vote(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha, int S,
+                  uint64_t seed, int G, uint32_t batch, const int64_t* qindex, double* out, double* min_margin,
+                  double* absum, double* sens, int32_t* paths, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+    int d3 = t->d * t->d * t->d;
+    if (G < 1) G = 1;
+    /* group starts: a new group wherever the stream id changes */
+    int64_t* start = malloc(sizeof(int64_t) * (n + 1));
+    int64_t ng = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t jj = qindex ? qindex[j] : j;
+        if (j == 0 || jj / 64 != (qindex ? qindex[j - 1] : j - 1) / 64) start[ng++] = j;
+    }
+    start[ng] = n;
+    if (paths)
+        for (int64_t k = 0; k < n * d3 * S; ++k) {
+            int32_t* rec = &paths[k * 4];
+            rec[0] = -1; rec[1] = 0; rec[2] = 0; rec[3] = 0;
+        }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t gi = 0; gi < ng; ++gi) {
+        int64_t j0 = start[gi], j1 = start[gi + 1];
+        int gn = (int)(j1 - j0);
+        double* qs = malloc(sizeof(double) * 3 * gn);
+        double* F = calloc(gn, sizeof(double));
+        double* A = calloc(gn, sizeof(double));
+        double* SN = calloc(gn, sizeof(double));
+        double* mg = malloc(sizeof(double) * gn);
+        for (int g = 0; g < gn; ++g) {
+            for (int c = 0; c < 3; ++c) qs[3 * g + c] = qry[3 * (j0 + g) + c];
+            mg[g] = INFINITY;
+        }
+        int64_t jj = qindex ? qindex[j0] : j0;
+        if (!is_internal(t, 0)) {
+            for (int g = 0; g < gn; ++g) { F[g] = leaf_exact(t, &kp, 0, &qs[3 * g]); A[g] = fabs(F[g]); }
+        } else {
+            vote_group(t, &kp, qs, gn, (uint32_t)(jj / G), S, seed, batch, d3, F, A, SN, mg,
+                       paths ? &paths[j0 * d3 * S * 4] : NULL);
+        }
+        for (int g = 0; g < gn; ++g) {
+            out[j0 + g] = F[g];
+            if (min_margin) min_margin[j0 + g] = mg[g];
+            if (absum) absum[j0 + g] = A[g];
+            if (sens) sens[j0 + g] = SN[g];
+        }
+        free(qs); free(F); free(A); free(SN); free(mg);
+    }
+    free(start);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Stratification by a Barnes-Hut cut (Section 3.3.1 names the contribution */
 /* nodes D(q, beta) of a low beta as an alternative to the root's children   */
 /* as path roots).  The cut is voted over groups of `vote` consecutive       */
@@ -1337,6 +1534,65 @@ static double expect_rec(const orc_tree* t, const kparams* kp, const double q[3]
         }
     }
     return total;
+}
+
+/* The exact expectation (Theorem 1) of query g's one-sample estimate under
+ * the roulette voted over its tile (queries qs, gn of them). */
+static double expect_vote_rec(const orc_tree* t, const kparams* kp, const double* qs, int gn, int g, int64_t T,
+                              double tT, double ps, double pr)
+{
+    const double* q = &qs[3 * g];
+    int64_t nT = t->count[T];
+    if (nT == 1 && !t->cmp) return 0.0;
+    double total = 0.0;
+    if (is_internal(t, T)) {
+        double sum = 0.0;
+        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch)
+            sum += node_term(t, kp, ch, q);
+        double delta = sum - tT;
+        for (int64_t ch = t->first_child[T]; ch < t->first_child[T] + t->nchild[T]; ++ch) {
+            double qc = (double)t->count[ch] / (double)nT;
+            double pc = vote_prob(t, qs, gn, T, ch, -1);
+            if (pc == 0.0) continue;
+            double tc = node_term(t, kp, ch, q);
+            total += qc * pc * (delta / (ps * pr * pc) + expect_vote_rec(t, kp, qs, gn, g, ch, tc, ps * qc, pr * pc));
+        }
+    } else {
+        double sum = 0.0;
+        for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) sum += point_term(t, kp, s, q);
+        double delta = sum - tT;
+        for (int64_t s = t->begin[T]; s < t->begin[T] + nT; ++s) {
+            double pc = vote_prob(t, qs, gn, T, -1, s);
+            if (pc == 0.0) continue;
+            total += (1.0 / (double)nT) * pc * (delta / (ps * pr * pc));
+        }
+    }
+    return total;
+}
+
+void orc_sbh_vote_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,
+                         double* out, int nthreads)
+{
+    kparams kp = {kernel, eps, alpha};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t t0 = (j / 64) * 64, t1 = t0 + 64 < n ? t0 + 64 : n;
+        int gn = (int)(t1 - t0);
+        double qs[64 * 3];
+        for (int k = 0; k < 3 * gn; ++k) qs[k] = qry[3 * t0 + k];
+        const double* q = &qs[3 * (j - t0)];
+        if (!is_internal(t, 0)) { out[j] = leaf_exact(t, &kp, 0, q); continue; }
+        double F = 0.0;
+        for (int ci = 0; ci < t->nchild[0]; ++ci) {
+            int64_t a = t->first_child[0] + ci;
+            double cv = node_term(t, &kp, a, q);
+            F += cv + expect_vote_rec(t, &kp, qs, gn, (int)(j - t0), a, cv, 1.0, 1.0);
+        }
+        out[j] = F;
+    }
 }
 
 void orc_sbh_expect(const orc_tree* t, const float* qry, int64_t n, int kernel, double eps, double alpha,

@@ -91,7 +91,7 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (!(o.eps >= 0.0f) || !std::isfinite(o.eps)) return fail(SBH_EINVAL, "eps must be finite and >= 0");
     if (!(o.alpha > 0.0f) || !std::isfinite(o.alpha)) return fail(SBH_EINVAL, "alpha must be finite and > 0");
     if (o.group < 1) return fail(SBH_EINVAL, "group must be >= 1");
-    if (o.rr_mode < 0 || o.rr_mode > 2) return fail(SBH_EINVAL, "rr_mode must be 0, 1 or 2");
+    if (o.rr_mode < 0 || o.rr_mode > 3) return fail(SBH_EINVAL, "rr_mode must be 0, 1, 2 or 3");
     if (o.proposal < 0 || o.proposal > 3) return fail(SBH_EINVAL, "proposal must be 0, 1, 2 or 3");
     if (o.proposal == 3 && o.group % 64 != 0)
         return fail(SBH_EINVAL, "the tile-shared score proposal needs group a multiple of 64");
@@ -99,6 +99,8 @@ sbh_status check_eval_opts(const sbh_eval_opts& o)
     if (o.subdomains < 0 || o.subdomains > 1) return fail(SBH_EINVAL, "subdomains must be 0 or 1");
     if (o.subdomains == 1 && (o.group % 64 != 0 || o.proposal != 0))
         return fail(SBH_EINVAL, "Barnes-Hut-cut subdomains need group a multiple of 64 and the uniform proposal");
+    if (o.rr_mode == 3 && (o.group % 64 != 0 || o.proposal != 0 || o.subdomains != 0))
+        return fail(SBH_EINVAL, "the voted roulette needs group a multiple of 64, the uniform proposal and subdomains 0");
     return SBH_OK;
 }
 

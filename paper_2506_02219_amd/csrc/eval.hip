@@ -626,6 +626,21 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
 // slots that one wavefront walks (kWaveParts parts), then the parts' sums in
 // part order.
 // ---------------------------------------------------------------------------
+// The largest of the 64 lanes' values (non-negative floats order as their bit
+// patterns): an inclusive max-scan by DPP row shifts and row broadcasts, read
+// from lane 63.  Needs every lane active.
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    uint32_t x = __float_as_uint(v);
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));   // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));   // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));   // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));   // row_shr:8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)x, 63));
+}
+
 // max(a, b) of two non-negative finite floats as one instruction (fmaxf quiets
 // NaN inputs first, two more instructions that the walk does not need)
 // Byte offsets into the tree's arrays: 32-bit while every array of the tree is
@@ -776,8 +791,12 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // variate (the two agree bit for bit and the child is not evaluated twice)
     // (Eq. (5) is evaluated in every mode and replaced by the mode's constant, a select
     // rather than a branch)
-    const bool rr_eq5 = rr_mode == 0;
+    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
+    // coordinates, the same for every lane, so the wavefront stops or continues as one)
+    const bool rr_vote = rr_mode == 3;
+    const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     // One reciprocal square root gives both |c - q| and 1 / (D |c - q|).  At |c - q| = 0
     // the distance is NaN, which the next step's max ignores (v_max returns the other
     // operand), and p = min(1, inf) = 1 as Eq. (5)'s limit.
@@ -785,7 +804,9 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         const float ic = __builtin_amdgcn_rsqf(r2C);
         dC = r2C * ic;
         const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
-        return rr_eq5 ? p5 : rr_fixed;
+        float p = rr_eq5 ? p5 : rr_fixed;
+        if (rr_vote) p = wave_max_nonneg(voter ? p : 0.0f);
+        return p;
     };
     int k = 0;
     // internal nodes: the walk leaves the loops below at a leaf, or when the roulette
@@ -1047,13 +1068,19 @@ __device__ __forceinline__ float wave_path_q(const TreeView& tv, float qx, float
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    const bool rr_eq5 = rr_mode == 0;
+    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
+    // coordinates, the same for every lane, so the wavefront stops or continues as one)
+    const bool rr_vote = rr_mode == 3;
+    const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     auto roulette = [&](float r2C, float& dC) -> float {
         const float ic = __builtin_amdgcn_rsqf(r2C);
         dC = r2C * ic;
         const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
-        return rr_eq5 ? p5 : rr_fixed;
+        float p = rr_eq5 ? p5 : rr_fixed;
+        if (rr_vote) p = wave_max_nonneg(voter ? p : 0.0f);
+        return p;
     };
     int k = 0;
     bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;
@@ -1345,13 +1372,19 @@ __device__ __forceinline__ float wave_path_l2(const TreeView& tv, float qx, floa
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    const bool rr_eq5 = rr_mode == 0;
+    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
+    // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
+    // coordinates, the same for every lane, so the wavefront stops or continues as one)
+    const bool rr_vote = rr_mode == 3;
+    const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     auto roulette = [&](float r2C, float& dC) -> float {
         const float ic = __builtin_amdgcn_rsqf(r2C);
         dC = r2C * ic;
         const float p5 = fminf(1.0f, vmax(diamT, dT) * (kInvD * ic));
-        return rr_eq5 ? p5 : rr_fixed;
+        float p = rr_eq5 ? p5 : rr_fixed;
+        if (rr_vote) p = wave_max_nonneg(voter ? p : 0.0f);
+        return p;
     };
     int k = 0;
     bool go = actm != 0ull && (int)nT > tv.leaf_size && level < tv.max_level;

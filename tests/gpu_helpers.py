@@ -197,10 +197,14 @@ def check_sbh(gt, ot, queries, kernel, samples=1, seed=0, group=1, rr_mode=0, ep
     ot.set_compressed(compressed)
     ot.set_lod(lod)
     try:
-        r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps, alpha=alpha,
-                   paths=True, index=index, batch=batch,
-                   params=np.zeros(oracle.MLP_NPARAM, np.float32) if proposal == 2 else mlp,
-                   tile_queries=(queries if tile_all is None else tile_all) if proposal == 3 else None)
+        if rr_mode == 3:   # the roulette voted over tiles of 64 (`queries` holds whole tiles)
+            r = ot.sbh_vote(queries, kernel, samples=samples, seed=seed, group=group, batch=batch, eps=eps,
+                            alpha=alpha, paths=True, index=index)
+        else:
+            r = ot.sbh(queries, kernel, samples=samples, seed=seed, group=group, rr_mode=rr_mode, eps=eps,
+                       alpha=alpha, paths=True, index=index, batch=batch,
+                       params=np.zeros(oracle.MLP_NPARAM, np.float32) if proposal == 2 else mlp,
+                       tile_queries=(queries if tile_all is None else tile_all) if proposal == 3 else None)
     finally:
         ot.set_compressed(False)
         ot.set_lod(1)
