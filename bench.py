@@ -142,12 +142,20 @@ def rel_errors(v, ref, kernel, alpha=100.0):
 
 
 def git_sha():
-    """HEAD of the repository when it is a git checkout (the benchmark box gets a copy without .git)."""
+    """HEAD of the repository when it is a git checkout; on a copy without .git (the benchmark box),
+    the revision the library was built from (written by the build, +dirty when its sources differed)."""
     import subprocess
     try:
-        return subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True,
-                              timeout=10).stdout.strip() or None
+        sha = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True,
+                             timeout=10).stdout.strip()
+        if sha:
+            return sha
     except Exception:
+        pass
+    try:
+        with open(os.path.join(ROOT, "paper_2506_02219_amd", "_build", "source_revision.txt")) as f:
+            return "built-from:" + f.read().strip()
+    except OSError:
         return None
 
 

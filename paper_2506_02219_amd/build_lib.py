@@ -39,7 +39,24 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
+    _record_revision()
     return LIB
+
+
+def _record_revision():
+    """Write the git revision the library was built from (with +dirty when its sources differ from
+    it) beside the objects, for runs on a copy of the tree without .git."""
+    root = os.path.dirname(HERE)
+    try:
+        sha = subprocess.run(["git", "rev-parse", "HEAD"], cwd=root, capture_output=True, text=True,
+                             timeout=10).stdout.strip()
+        dirty = subprocess.run(["git", "diff", "--quiet", "HEAD", "--", "paper_2506_02219_amd/csrc", "include"],
+                               cwd=root, timeout=10).returncode != 0
+    except Exception:
+        return
+    if sha:
+        with open(os.path.join(OBJ, "source_revision.txt"), "w") as f:
+            f.write(sha + ("+dirty" if dirty else "") + "\n")
 
 
 if __name__ == "__main__":
