@@ -349,7 +349,7 @@ def main():
     d = args.branching
     exp = tree.export()
 
-    def work_of(group):
+    def work_of(group, rr_mode=0):
         """Algorithmic bytes and flops of one launch, from the kernel's own path records.
 
         A path's attempted steps are its accepted ones, plus the step its roulette stopped (flag 0).
@@ -361,7 +361,7 @@ def main():
         does no swap.  Per query: the subdomain control variates and the final sums."""
         d3 = d ** 3
         paths = torch.empty((N, d3, S, 4), dtype=torch.int32, device=dev)
-        P.sbh_eval(tree, qry, kernel, samples=S, seed=0, group=group, out=out, paths=paths)
+        P.sbh_eval(tree, qry, kernel, samples=S, seed=0, group=group, out=out, paths=paths, rr_mode=rr_mode)
         torch.cuda.synchronize()
         rec = paths.cpu().numpy().reshape(-1, 4)
         del paths
@@ -546,8 +546,12 @@ def main():
             P.sbh_eval(tree, qry, kernel, samples=samples, seed=0, group=args.group, out=out, rr_mode=3)
 
         ms_v = timed(run_vote, args.steps, args.warmup)
+        wk_v = work_of(args.group, 3)
+        tf_v = wk_v["alg_flops"] / (ms_v * 1e-3) / 1e12
         voted = dict(group=args.group, samples=S, ms_per_step=ms_v, queries_per_s=N / (ms_v * 1e-3),
-                     median_rel_err=err_of(run_vote), vs_headline=ms_per_step / ms_v, sweep=[])
+                     median_rel_err=err_of(run_vote), vs_headline=ms_per_step / ms_v,
+                     accepted_steps_per_path=wk_v["mean_steps"], alg_flops_per_launch=wk_v["alg_flops"],
+                     achieved_TFLOPs=tf_v, frac_of_fp32_peak=tf_v / FP32_PEAK_TFLOPS, sweep=[])
         for sv in (2, 4):
             voted["sweep"].append(dict(samples=sv, ms=timed(lambda: run_vote(sv), 3, 1),
                                        median_rel_err=err_of(lambda: run_vote(sv))))

@@ -4,7 +4,7 @@ they also share p, the largest Eq. (5) probability among the tile's queries
 with finite coordinates, and stop or continue together) with the FP64
 oracle's voted estimator, to the tolerances stated in gpu_helpers.
 
-Covered: both branching factors used by the coherent walk (2 and 4), every
+Covered: the branching factors of the coherent walk (2, 4 and 8), every
 kernel at alpha = 100, S = 1 and 3, G = 64 and 128, ragged tails, the
 four-part tail tiles, a deep tree whose paths pass step 16, the compressed
 and second-order walks, a query with non-finite coordinates (which does not
@@ -31,7 +31,7 @@ def box_queries(n, seed, lo=-1.5, hi=1.5):
     return np.random.Generator(np.random.PCG64(seed)).uniform(lo, hi, (n, 3)).astype(np.float32)
 
 
-@pytest.mark.parametrize("d", [2, 4])
+@pytest.mark.parametrize("d", [2, 4, 8])
 @pytest.mark.parametrize("S", [1, 3])
 @pytest.mark.parametrize("G", [64, 128])
 def test_vote_parity_c1(d, S, G):
