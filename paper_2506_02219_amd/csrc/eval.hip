@@ -759,7 +759,9 @@ struct PathWordsOne {
 
 // One path of the coherent walk from subdomain node a (n_a points from begin_a, at
 // level level_a; blk_a its child block when internal), for the wavefront's 64 queries.
-template <int D, int K, bool TRACE, bool O64, class PW = PathWords>
+// VM: the voted roulette (rr_mode 3) compiled out (0), always taken (1), or
+// chosen by rr_mode at run time (2).
+template <int D, int K, bool TRACE, bool O64, class PW = PathWords, int VM = 2>
 __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
                                            const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
                                            int32_t blk_a, float4 agg_a, float t_a, const PW& pw,
@@ -795,7 +797,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
     // coordinates, the same for every lane, so the wavefront stops or continues as one)
-    const bool rr_vote = rr_mode == 3;
+    const bool rr_vote = VM == 1 || (VM == 2 && rr_mode == 3);
     const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     // One reciprocal square root gives both |c - q| and 1 / (D |c - q|).  At |c - q| = 0
     // the distance is NaN, which the next step's max ignores (v_max returns the other
@@ -1847,7 +1849,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
 // association of two parts (slots 0-3 in order, slots 4-7 in order, then
 // the two sums), so a query's value does not depend on how its tile was
 // split.  (A run-time choice: one inlined walk serves both splits.)
-template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false>
+template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false, int VM = 2>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave, int part = 0,
                                               int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr,
@@ -1915,7 +1917,8 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
                                                     agg_a, cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode,
                                                     &rec);
             else
-                fa += wave_path<D, K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw,
+                fa += wave_path<D, K, TRACE, O64, PathWords, VM>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a,
+                                                                 agg_a, cv, pw,
                                                   stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
@@ -1960,7 +1963,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
 // from split_tile on (d = 2, the end of the launch, where the last wavefronts
 // run on a partly idle chip): one tile per block over all four wavefronts,
 // which halves the chain of steps each of them walks.
-template <int D, int K, bool TRACE, bool O64>
+template <int D, int K, bool TRACE, bool O64, int VM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out,
            int64_t split_tile)
@@ -1975,7 +1978,8 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
     const int64_t nb2 = split_tile / TPB;
     const bool four = D == 2 && (int64_t)blockIdx.x >= nb2;
     const int64_t tile = four ? split_tile + ((int64_t)blockIdx.x - nb2) : (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile<D, K, TRACE, false, P, O64>(tv, queries, nq, a, out, tile, four ? w : w % P, w, part_f, done, four);
+    sbh_wave_tile<D, K, TRACE, false, P, O64, VM>(tv, queries, nq, a, out, tile, four ? w : w % P, w, part_f, done,
+                                                  four);
 }
 
 // Tiles of the launch's four-part tail (d = 2): kTailTiles, or SBH_TAIL_TILES
@@ -2211,7 +2215,7 @@ __global__ void __launch_bounds__(256) k_sbh_cut(TreeView tv, const float* __res
                     pw.compute(stream, pre, ((uint32_t)(level + 1) << 24) | ((uint32_t)s2 << 16), a.batch, a.key0,
                                a.key1);
                     int4 rec;
-                    fa += wave_path<D, K, TRACE, O64, PathWordsOne>(tv, qx, qy, qz, r0, kp, valid, cnt, pre, blk_c, g,
+                    fa += wave_path<D, K, TRACE, O64, PathWordsOne, 0>(tv, qx, qy, qz, r0, kp, valid, cnt, pre, blk_c, g,
                                                                     cv, pw, stream, 0u, a.batch, a.key0, a.key1,
                                                                     a.rr_mode, &rec, level + 1);
                     if constexpr (TRACE) {
@@ -2385,13 +2389,20 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             split = std::max<int64_t>(0, tiles - std::min(tail_tiles(), tiles)) / TPB * TPB;
             blocks = (unsigned)(split / TPB + (tiles - split));
         }
-        if (tv.wide) {
-            if (e.paths) k_sbh_wave<D, K, true, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
-            else k_sbh_wave<D, K, false, true><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
-        } else {
-            if (e.paths) k_sbh_wave<D, K, true, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
-            else k_sbh_wave<D, K, false, false><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);
-        }
+        // the voted roulette is a kernel of its own, so that the default walk carries none of it
+#define SBH_WAVE(VV)                                                                                        \
+    do {                                                                                                    \
+        if (tv.wide) {                                                                                      \
+            if (e.paths) k_sbh_wave<D, K, true, true, VV><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);  \
+            else k_sbh_wave<D, K, false, true, VV><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);         \
+        } else {                                                                                            \
+            if (e.paths) k_sbh_wave<D, K, true, false, VV><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split); \
+            else k_sbh_wave<D, K, false, false, VV><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);        \
+        }                                                                                                   \
+    } while (0)
+        if (e.rr_mode == 3) SBH_WAVE(1);
+        else SBH_WAVE(0);
+#undef SBH_WAVE
         return hipGetLastError();
     }
     if constexpr (D == 8) {
