@@ -60,8 +60,10 @@ L2_PEAK_GBS = 8 * 16 * 128 * 2.4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # a few hundred steps: the GPU's clocks take some milliseconds of load to ramp up, and a step of
+    # the headline is about 0.1 ms
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--branching", type=int, default=2, help="tree of the stochastic estimator")
     ap.add_argument("--bh-branching", type=int, default=2, help="tree of the Barnes-Hut comparator")

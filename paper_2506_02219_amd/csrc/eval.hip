@@ -1849,7 +1849,7 @@ __device__ __forceinline__ float wave_path_tile(const TreeView& tv, float qx, fl
 // association of two parts (slots 0-3 in order, slots 4-7 in order, then
 // the two sums), so a query's value does not depend on how its tile was
 // split.  (A run-time choice: one inlined walk serves both splits.)
-template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false, int VM = 2>
+template <int D, int K, bool TRACE, bool TILE = false, int P = 1, bool O64 = false, int VM = 2, bool SPLIT = false>
 __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                               const SbhArgs& a, float* __restrict__ out, int64_t wave, int part = 0,
                                               int w = 0, float (*part_f)[64] = nullptr, uint32_t* done = nullptr,
@@ -1858,7 +1858,7 @@ __device__ __forceinline__ void sbh_wave_tile(const TreeView& tv, const float* _
 #pragma clang fp contract(off)
     constexpr int D3 = D * D * D;
     static_assert(D3 % P == 0, "parts must split the root slots evenly");
-    constexpr bool kFour = D == 2 && P == 2;   // the four-way split is available
+    constexpr bool kFour = SPLIT && D == 2 && P == 2;   // the four-way split is compiled in
     if constexpr (!kFour) four = false;
     const int lane = threadIdx.x & 63;
     const int64_t j0 = wave * 64;
@@ -1978,8 +1978,8 @@ k_sbh_wave(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a
     const int64_t nb2 = split_tile / TPB;
     const bool four = D == 2 && (int64_t)blockIdx.x >= nb2;
     const int64_t tile = four ? split_tile + ((int64_t)blockIdx.x - nb2) : (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile<D, K, TRACE, false, P, O64, VM>(tv, queries, nq, a, out, tile, four ? w : w % P, w, part_f, done,
-                                                  four);
+    sbh_wave_tile<D, K, TRACE, false, P, O64, VM, true>(tv, queries, nq, a, out, tile, four ? w : w % P, w, part_f,
+                                                        done, four);
 }
 
 // Tiles of the launch's four-part tail (d = 2): kTailTiles, or SBH_TAIL_TILES
@@ -2303,7 +2303,7 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
 // wavefront, looked up in the workgroup table; the hardware dispatcher
 // starts workgroups as earlier ones finish, which balances clouds of uneven
 // cost without a shared work counter.
-template <int D, int K>
+template <int D, int K, int VM = 0>
 __global__ void __launch_bounds__(64 * kBatchMaxTileWaves * kWaveParts) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, const BatchState* __restrict__ st,
             SbhArgs base)
@@ -2328,9 +2328,11 @@ k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, co
     // the descriptor stays in memory and its fields are read where they are used
     // (scalar loads), as kernel arguments are
     if (it->tv.wide)
-        sbh_wave_tile<D, K, false, false, P, true>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
+        sbh_wave_tile<D, K, false, false, P, true, VM>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f,
+                                                       done);
     else
-        sbh_wave_tile<D, K, false, false, P, false>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f, done);
+        sbh_wave_tile<D, K, false, false, P, false, VM>(it->tv, it->queries, nq, a, it->out, wave, w % P, w, part_f,
+                                                        done);
 }
 
 // Clouds whose root is a leaf are summed exactly, as sbh_eval does, in launches
@@ -2548,7 +2550,12 @@ hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int
 {
     SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
     const dim3 block(64 * tile_waves * kWaveParts);
-#define SBH_LAUNCH_B(DD, KK) k_sbh_batch<DD, KK><<<blocks, block, lds_bytes, s>>>(items, wg, st, a)
+    // the voted roulette (rr_mode 3) is a kernel of its own, as in the single-tree launch
+#define SBH_LAUNCH_B(DD, KK)                                                                      \
+    do {                                                                                          \
+        if (rr_mode == 3) k_sbh_batch<DD, KK, 1><<<blocks, block, lds_bytes, s>>>(items, wg, st, a); \
+        else k_sbh_batch<DD, KK, 0><<<blocks, block, lds_bytes, s>>>(items, wg, st, a);            \
+    } while (0)
     if (d == 2) {
         if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(2, SBH_POTENTIAL);
         else if (kernel == SBH_WINDING) SBH_LAUNCH_B(2, SBH_WINDING);
