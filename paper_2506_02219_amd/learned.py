@@ -43,25 +43,52 @@ def training_rows(tree, queries: torch.Tensor, kernel: int, seed: int, max_depth
     return X[keep], Tg[keep], Cn[keep]
 
 
+def _shuffle(n: int, seed: int, index: int, device) -> torch.Tensor:
+    """The row permutation of shuffle `index` of a training run: a function of (seed, index) only."""
+    g = torch.Generator().manual_seed(int(seed) * 1000003 + int(index))
+    return torch.randperm(n, generator=g).to(device)
+
+
 def train(params: torch.Tensor, X: torch.Tensor, Tg: torch.Tensor, Cn: torch.Tensor, steps: int,
-          batch_rows: int = 8192, lr: float = 2e-3, seed: int = 0, epochs_per_shuffle: int = 1):
-    """Adam on `params` in place over the rows (shuffled with `seed`).  Returns the per-step losses
-    (device tensor) and the final Adam state."""
+          batch_rows: int = 8192, lr: float = 2e-3, seed: int = 0, epochs_per_shuffle: int = 1, state=None,
+          step0: int = 0):
+    """`steps` Adam steps on `params` in place, the run's steps step0 .. step0 + steps - 1.  The rows
+    are shuffled at the start of every `epochs_per_shuffle` epochs by a permutation that depends on
+    (seed, shuffle index) only, and each step's batch on the step's index (sbh_mlp_train), so that a
+    run continued from a checkpoint (params, Adam state and step0 saved by save_checkpoint) takes the
+    same batches, and ends with the same parameters bit for bit, as one that was not interrupted.
+    state: the Adam moments [2 * MLP_NPARAM] (None: zero, a fresh run).  Returns the per-step losses
+    (device tensor) and the Adam state."""
     n = X.shape[0]
-    state = torch.zeros(2 * MLP_NPARAM, dtype=torch.float32, device=params.device)
+    if state is None:
+        state = torch.zeros(2 * MLP_NPARAM, dtype=torch.float32, device=params.device)
     losses = torch.zeros(max(steps, 1), dtype=torch.float32, device=params.device)
-    gen = torch.Generator().manual_seed(seed)
-    per_epoch = max(1, (n + batch_rows - 1) // batch_rows)
-    done = 0
-    while done < steps:
-        perm = torch.randperm(n, generator=gen).to(params.device)
+    per = max(1, (n + batch_rows - 1) // batch_rows) * max(1, epochs_per_shuffle)   # steps per shuffle
+    done, end = int(step0), int(step0) + int(steps)
+    while done < end:
+        e = done // per
+        perm = _shuffle(n, seed, e, params.device)
         Xs, Ts, Cs = X[perm].contiguous(), Tg[perm].contiguous(), Cn[perm].contiguous()
-        k = min(steps - done, per_epoch * epochs_per_shuffle)
-        # steps are counted from `done` so that Adam's bias correction continues across shuffles
+        k = min(end, (e + 1) * per) - done
         sbh_mlp_train(params, state, Xs, Ts, Cs, steps=k, batch_rows=batch_rows, lr=lr, step0=done,
-                      losses=losses[done:done + k])
+                      losses=losses[done - step0:done - step0 + k])
         done += k
     return losses[:steps], state
+
+
+def save_checkpoint(path, params: torch.Tensor, state: torch.Tensor, step: int):
+    """Parameters, Adam state and the number of steps taken, as a .npz of plain arrays (no pickles)."""
+    np.savez(path, params=params.detach().cpu().numpy().astype(np.float32),
+             adam_state=state.detach().cpu().numpy().astype(np.float32), step=np.int64(step))
+
+
+def load_checkpoint(path, device="cuda"):
+    """(params, Adam state, step) saved by save_checkpoint."""
+    with np.load(path, allow_pickle=False) as z:
+        p, st, k = z["params"], z["adam_state"], int(z["step"])
+    if p.shape != (MLP_NPARAM,) or st.shape != (2 * MLP_NPARAM,):
+        raise ValueError("not a checkpoint of the proposal network")
+    return torch.from_numpy(p).to(device), torch.from_numpy(st).to(device), k
 
 
 def train_selected(params: torch.Tensor, X, Tg, Cn, steps: int, validate, chunks: int = 8, batch_rows: int = 8192,
