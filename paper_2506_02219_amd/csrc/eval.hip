@@ -759,8 +759,8 @@ struct PathWordsOne {
 
 // One path of the coherent walk from subdomain node a (n_a points from begin_a, at
 // level level_a; blk_a its child block when internal), for the wavefront's 64 queries.
-// VM: the voted roulette (rr_mode 3) compiled out (0), always taken (1), or
-// chosen by rr_mode at run time (2).
+// VM: the roulette compiled in: 0 Eq. (5) (rr_mode 0), 1 Eq. (5) voted over
+// the wavefront (rr_mode 3), 2 chosen at run time among rr_mode 0, 1 and 2.
 template <int D, int K, bool TRACE, bool O64, class PW = PathWords, int VM = 2>
 __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float qy, float qz, float r0,
                                            const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
@@ -793,11 +793,11 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     // variate (the two agree bit for bit and the child is not evaluated twice)
     // (Eq. (5) is evaluated in every mode and replaced by the mode's constant, a select
     // rather than a branch)
-    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
+    const bool rr_eq5 = VM != 2 || rr_mode == 0;
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
     // coordinates, the same for every lane, so the wavefront stops or continues as one)
-    const bool rr_vote = VM == 1 || (VM == 2 && rr_mode == 3);
+    constexpr bool rr_vote = VM == 1;
     const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     // One reciprocal square root gives both |c - q| and 1 / (D |c - q|).  At |c - q| = 0
     // the distance is NaN, which the next step's max ignores (v_max returns the other
@@ -2215,7 +2215,7 @@ __global__ void __launch_bounds__(256) k_sbh_cut(TreeView tv, const float* __res
                     pw.compute(stream, pre, ((uint32_t)(level + 1) << 24) | ((uint32_t)s2 << 16), a.batch, a.key0,
                                a.key1);
                     int4 rec;
-                    fa += wave_path<D, K, TRACE, O64, PathWordsOne, 0>(tv, qx, qy, qz, r0, kp, valid, cnt, pre, blk_c, g,
+                    fa += wave_path<D, K, TRACE, O64, PathWordsOne, 2>(tv, qx, qy, qz, r0, kp, valid, cnt, pre, blk_c, g,
                                                                     cv, pw, stream, 0u, a.batch, a.key0, a.key1,
                                                                     a.rr_mode, &rec, level + 1);
                     if constexpr (TRACE) {
@@ -2303,7 +2303,7 @@ __global__ void k_batch_begin(BatchState* st, uint32_t key0, uint32_t key1, uint
 // wavefront, looked up in the workgroup table; the hardware dispatcher
 // starts workgroups as earlier ones finish, which balances clouds of uneven
 // cost without a shared work counter.
-template <int D, int K, int VM = 0>
+template <int D, int K, int VM = 2>
 __global__ void __launch_bounds__(64 * kBatchMaxTileWaves * kWaveParts) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, const BatchState* __restrict__ st,
             SbhArgs base)
@@ -2391,7 +2391,8 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             split = std::max<int64_t>(0, tiles - std::min(tail_tiles(), tiles)) / TPB * TPB;
             blocks = (unsigned)(split / TPB + (tiles - split));
         }
-        // the voted roulette is a kernel of its own, so that the default walk carries none of it
+        // each roulette is a kernel of its own (Eq. (5), voted, and the run-time ablation modes),
+        // so that the default walk carries no test of rr_mode
 #define SBH_WAVE(VV)                                                                                        \
     do {                                                                                                    \
         if (tv.wide) {                                                                                      \
@@ -2402,8 +2403,9 @@ static hipError_t launch_sbh_dk(const TreeView& tv, const float* q, int64_t nq, 
             else k_sbh_wave<D, K, false, false, VV><<<blocks, 256, 0, s>>>(tv, q, nq, a, out, split);        \
         }                                                                                                   \
     } while (0)
-        if (e.rr_mode == 3) SBH_WAVE(1);
-        else SBH_WAVE(0);
+        if (e.rr_mode == 0) SBH_WAVE(0);
+        else if (e.rr_mode == 3) SBH_WAVE(1);
+        else SBH_WAVE(2);
 #undef SBH_WAVE
         return hipGetLastError();
     }
@@ -2550,11 +2552,12 @@ hipError_t launch_sbh_batch(int d, int kernel, const BatchItem* items, const int
 {
     SbhArgs a{samples, group, rr_mode, 0u, 0u, 0u, eps * eps, alpha, nullptr};
     const dim3 block(64 * tile_waves * kWaveParts);
-    // the voted roulette (rr_mode 3) is a kernel of its own, as in the single-tree launch
+    // a kernel per roulette (Eq. (5), voted, the ablation modes), as in the single-tree launch
 #define SBH_LAUNCH_B(DD, KK)                                                                      \
     do {                                                                                          \
-        if (rr_mode == 3) k_sbh_batch<DD, KK, 1><<<blocks, block, lds_bytes, s>>>(items, wg, st, a); \
-        else k_sbh_batch<DD, KK, 0><<<blocks, block, lds_bytes, s>>>(items, wg, st, a);            \
+        if (rr_mode == 0) k_sbh_batch<DD, KK, 0><<<blocks, block, lds_bytes, s>>>(items, wg, st, a); \
+        else if (rr_mode == 3) k_sbh_batch<DD, KK, 1><<<blocks, block, lds_bytes, s>>>(items, wg, st, a); \
+        else k_sbh_batch<DD, KK, 2><<<blocks, block, lds_bytes, s>>>(items, wg, st, a);            \
     } while (0)
     if (d == 2) {
         if (kernel == SBH_POTENTIAL) SBH_LAUNCH_B(2, SBH_POTENTIAL);
