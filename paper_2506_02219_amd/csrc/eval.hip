@@ -1044,7 +1044,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
 // roulette are those of wave_path.
 // ---------------------------------------------------------------------------
 
-template <int K, bool TRACE, bool O64>
+template <int K, bool TRACE, bool O64, int VM>
 __device__ __forceinline__ float wave_path_q(const TreeView& tv, float qx, float qy, float qz, float r0,
                                              const KParams& kp, bool valid, uint32_t n_a, uint32_t begin_a,
                                              int32_t blk_a, float dax, float day, float daz, float m_a, float t_a,
@@ -1070,11 +1070,11 @@ __device__ __forceinline__ float wave_path_q(const TreeView& tv, float qx, float
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
+    const bool rr_eq5 = VM != 2 || rr_mode == 0;   // VM: the roulette, as in wave_path
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
     // coordinates, the same for every lane, so the wavefront stops or continues as one)
-    const bool rr_vote = rr_mode == 3;
+    constexpr bool rr_vote = VM == 1;
     const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     auto roulette = [&](float r2C, float& dC) -> float {
         const float ic = __builtin_amdgcn_rsqf(r2C);
@@ -1221,7 +1221,7 @@ __device__ __forceinline__ float wave_path_q(const TreeView& tv, float qx, float
 // (com_0 - q), m^q_a = m_0 f_a, with com_0 and m_0 the root's float32
 // aggregate), then wave_path_q per (subdomain, sample).  Two wavefronts per
 // tile share the slots as k_sbh_wave's do.
-template <int K, bool TRACE, int P, bool O64>
+template <int K, bool TRACE, int P, bool O64, int VM>
 __device__ __forceinline__ void sbh_wave_tile_q(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                                 const SbhArgs& a, float* __restrict__ out, int64_t wave, int part,
                                                 int w, float (*part_f)[64], uint32_t* done)
@@ -1285,7 +1285,7 @@ __device__ __forceinline__ void sbh_wave_tile_q(const TreeView& tv, const float*
             int4 rec;
             const uint32_t path = (uint32_t)(slot * a.samples + s);
             pw.need(path, stream, a.batch, a.key0, a.key1);
-            fa += wave_path_q<K, TRACE, O64>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, dax, day, daz, m_a,
+            fa += wave_path_q<K, TRACE, O64, VM>(tv, qx, qy, qz, r0, kp, valid, n_a, begin_a, blk_a, dax, day, daz, m_a,
                                              cv, pw, stream, path, a.batch, a.key0, a.key1, a.rr_mode, &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
@@ -1310,7 +1310,7 @@ __device__ __forceinline__ void sbh_wave_tile_q(const TreeView& tv, const float*
     if (valid) gst(out + j, query_value<K>(F, r0, logwbar, a.alpha, qx, qy, qz));
 }
 
-template <int K, bool TRACE, bool O64>
+template <int K, bool TRACE, bool O64, int VM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave_q(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
@@ -1323,7 +1323,7 @@ k_sbh_wave_q(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs
     }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile_q<K, TRACE, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+    sbh_wave_tile_q<K, TRACE, P, O64, VM>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // ---------------------------------------------------------------------------
@@ -1352,7 +1352,7 @@ __device__ __forceinline__ float term_l2(float m, float4 qa, float4 qb, float dx
     return fmaf(m, u, r2 >= diam2 ? c : 0.0f);
 }
 
-template <bool TRACE, bool O64>
+template <bool TRACE, bool O64, int VM>
 __device__ __forceinline__ float wave_path_l2(const TreeView& tv, float qx, float qy, float qz, const KParams& kp,
                                               bool valid, uint32_t n_a, uint32_t begin_a, int32_t blk_a, float4 agg_a,
                                               float t_a, const PathWords& pw, uint32_t ctr0, uint32_t ctr1,
@@ -1374,11 +1374,11 @@ __device__ __forceinline__ float wave_path_l2(const TreeView& tv, float qx, floa
     float tT = t_a, prr = 1.0f, acc = 0.0f;
     int steps = 0, flag = 0;
     int32_t end_b = (int32_t)beginT, end_l = level;
-    const bool rr_eq5 = rr_mode == 0 || rr_mode == 3;
+    const bool rr_eq5 = VM != 2 || rr_mode == 0;   // VM: the roulette, as in wave_path
     const float rr_fixed = rr_mode == 1 ? 1.0f : 0.5f;
     // rr_mode 3: Eq. (5) voted over the wavefront (the largest p of its queries with finite
     // coordinates, the same for every lane, so the wavefront stops or continues as one)
-    const bool rr_vote = rr_mode == 3;
+    constexpr bool rr_vote = VM == 1;
     const bool voter = valid && __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz);
     auto roulette = [&](float r2C, float& dC) -> float {
         const float ic = __builtin_amdgcn_rsqf(r2C);
@@ -1514,7 +1514,7 @@ __device__ __forceinline__ float wave_path_l2(const TreeView& tv, float qx, floa
 
 // One tile of 64 consecutive queries of the second-order walk (two wavefronts
 // per tile share the slots as k_sbh_wave's do).
-template <bool TRACE, int P, bool O64>
+template <bool TRACE, int P, bool O64, int VM>
 __device__ __forceinline__ void sbh_wave_tile_l2(const TreeView& tv, const float* __restrict__ queries, int64_t nq,
                                                  const SbhArgs& a, float* __restrict__ out, int64_t wave, int part,
                                                  int w, float (*part_f)[64], uint32_t* done)
@@ -1567,7 +1567,7 @@ __device__ __forceinline__ void sbh_wave_tile_l2(const TreeView& tv, const float
             int4 rec;
             const uint32_t path = (uint32_t)(slot * a.samples + s);
             pw.need(path, stream, a.batch, a.key0, a.key1);
-            fa += wave_path_l2<TRACE, O64>(tv, qx, qy, qz, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw, stream, path,
+            fa += wave_path_l2<TRACE, O64, VM>(tv, qx, qy, qz, kp, valid, n_a, begin_a, blk_a, agg_a, cv, pw, stream, path,
                                            a.batch, a.key0, a.key1, a.rr_mode, &rec);
             if constexpr (TRACE) {
                 if (valid) reinterpret_cast<int4*>(a.paths)[(j * D3 + slot) * (int64_t)a.samples + s] = rec;
@@ -1592,7 +1592,7 @@ __device__ __forceinline__ void sbh_wave_tile_l2(const TreeView& tv, const float
     if (valid) gst(out + j, query_value<SBH_POTENTIAL>(F, 0.0f, 0.0f, a.alpha, qx, qy, qz));
 }
 
-template <bool TRACE, bool O64>
+template <bool TRACE, bool O64, int VM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sbh_wave_l2(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArgs a, float* __restrict__ out)
 {
@@ -1605,7 +1605,7 @@ k_sbh_wave_l2(TreeView tv, const float* __restrict__ queries, int64_t nq, SbhArg
     }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tile = (int64_t)blockIdx.x * TPB + w / P;
-    sbh_wave_tile_l2<TRACE, P, O64>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
+    sbh_wave_tile_l2<TRACE, P, O64, VM>(tv, queries, nq, a, out, tile, w % P, w, part_f, done);
 }
 
 // Sum over the 64 lanes of eight values per lane, in a fixed order, on the
@@ -2481,13 +2481,20 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
         SbhArgs a{e.samples, e.group, e.rr_mode, e.batch, (uint32_t)e.seed, (uint32_t)(e.seed >> 32),
                   e.eps * e.eps, e.alpha, e.paths};
         const unsigned wblocks = (unsigned)(((nq + 63) / 64 + (4 / kWaveParts) - 1) / (4 / kWaveParts));
-        if (tv.wide) {
-            if (e.paths) k_sbh_wave_l2<true, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
-            else k_sbh_wave_l2<false, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
-        } else {
-            if (e.paths) k_sbh_wave_l2<true, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
-            else k_sbh_wave_l2<false, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);
-        }
+#define SBH_L2(VV)                                                                                          \
+    do {                                                                                                    \
+        if (tv.wide) {                                                                                      \
+            if (e.paths) k_sbh_wave_l2<true, true, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);     \
+            else k_sbh_wave_l2<false, true, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);            \
+        } else {                                                                                            \
+            if (e.paths) k_sbh_wave_l2<true, false, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);    \
+            else k_sbh_wave_l2<false, false, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);           \
+        }                                                                                                   \
+    } while (0)
+        if (e.rr_mode == 0) SBH_L2(0);
+        else if (e.rr_mode == 3) SBH_L2(1);
+        else SBH_L2(2);
+#undef SBH_L2
         return hipGetLastError();
     }
     if (e.compressed) {   // the coherent walk on compressed aggregates (d = 2, potential or smooth distance)
@@ -2507,19 +2514,26 @@ hipError_t launch_sbh_eval(const sbh_tree_impl* t, const float* queries, int64_t
             return hipGetLastError();
         }
         const unsigned wblocks = (unsigned)(((nq + 63) / 64 + (4 / kWaveParts) - 1) / (4 / kWaveParts));
-#define SBH_Q(KK)                                                                                           \
+#define SBH_QV(KK, VV)                                                                                      \
     do {                                                                                                    \
         if (tv.wide) {                                                                                      \
-            if (e.paths) k_sbh_wave_q<KK, true, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);      \
-            else k_sbh_wave_q<KK, false, true><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);             \
+            if (e.paths) k_sbh_wave_q<KK, true, true, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);  \
+            else k_sbh_wave_q<KK, false, true, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);         \
         } else {                                                                                            \
-            if (e.paths) k_sbh_wave_q<KK, true, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);     \
-            else k_sbh_wave_q<KK, false, false><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);            \
+            if (e.paths) k_sbh_wave_q<KK, true, false, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out); \
+            else k_sbh_wave_q<KK, false, false, VV><<<wblocks, 256, 0, s>>>(tv, queries, nq, a, out);        \
         }                                                                                                   \
+    } while (0)
+#define SBH_Q(KK)                                                                                           \
+    do {                                                                                                    \
+        if (e.rr_mode == 0) SBH_QV(KK, 0);                                                                  \
+        else if (e.rr_mode == 3) SBH_QV(KK, 1);                                                             \
+        else SBH_QV(KK, 2);                                                                                 \
     } while (0)
         if (e.kernel == SBH_POTENTIAL) SBH_Q(SBH_POTENTIAL);
         else SBH_Q(SBH_SMOOTHDIST);
 #undef SBH_Q
+#undef SBH_QV
         return hipGetLastError();
     }
     if (e.cut) {   // subdomains: the Barnes-Hut cut (branching 2 and 4)
