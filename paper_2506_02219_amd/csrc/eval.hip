@@ -315,6 +315,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
 #pragma clang fp contract(off)
     static_assert(!CMP || (D == 2 && K != SBH_WINDING), "compressed aggregates: d = 2, no dipoles");
     constexpr int D3 = D * D * D;
+    constexpr bool EARLY = D == 2 && K != SBH_WINDING;
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
     __shared__ float res[4][kPoolPaths];   // per path: its sum F (before the division by S)
@@ -467,26 +468,43 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                 float4 aggC, dpC = zero4;
                 uint32_t nC = 1u, beginC;
                 int32_t blkC = 0;
+                // d = 2 without dipoles: the block's eight counts stay in registers from the selection
+                // to the swap (a reload is another gather per lane), and a compressed block's codes
+                // arrive with them, so decoding the selected child waits on no further load
+                uint32_t cn[EARLY ? D3 : 1];
+                sbh_u32x4v cb[CMP ? D3 / 2 : 1];
                 if (internal) {
+                    if constexpr (EARLY) {
+#pragma unroll
+                        for (int c = 0; c < D3; ++c) cn[c] = gld(bt + c);
+                    }
+                    if constexpr (CMP) {
+                        const uint32_t* __restrict__ qb = reinterpret_cast<const uint32_t*>(tv.bq) + (int64_t)blk * 16;
+#pragma unroll
+                        for (int i = 0; i < D3 / 2; ++i) cb[i] = gld4u(qb + 4 * i);
+                    }
                     // child selection from the point counts alone
                     uint32_t pre = 0u, preC = 0u;
                     int32_t nint = 0, nintC = 0;
                     int csel = 0;
+                    uint32_t w0 = 0u, w1 = 0u;
 #pragma unroll
                     for (int c = 0; c < D3; ++c) {
-                        const uint32_t cnt = gld(bt + c);
+                        const uint32_t cnt = EARLY ? cn[c] : gld(bt + c);
                         const bool hit = (r - pre) < cnt;
                         csel = hit ? c : csel;
                         preC = hit ? pre : preC;
                         nintC = hit ? nint : nintC;
                         nC = hit ? cnt : nC;
+                        if constexpr (CMP) {
+                            w0 = hit ? ((c & 1) ? cb[c >> 1].z : cb[c >> 1].x) : w0;
+                            w1 = hit ? ((c & 1) ? cb[c >> 1].w : cb[c >> 1].y) : w1;
+                        }
                         nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
                         pre += cnt;
                     }
                     if constexpr (CMP) {
                         // the selected child decoded: offset o s_c + (com^q_T - q), mass m^q_T f
-                        const uint32_t* __restrict__ qb = reinterpret_cast<const uint32_t*>(tv.bq) + (int64_t)blk * 16;
-                        const uint32_t w0 = gld(qb + 2 * csel), w1 = gld(qb + 2 * csel + 1);
                         aggC = make_float4(fmaf(h16(w0 & 0xFFFFu), sideC, dTx), fmaf(h16(w0 >> 16), sideC, dTy),
                                            fmaf(h16(w1 & 0xFFFFu), sideC, dTz), fmaf(h16(w1 >> 16), mT, 0.0f));
                     } else {
@@ -524,13 +542,9 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     float sumc = 0.0f;
                     const float tC = term_r2<K>(aggC, dpC, cx, cy, cz, r2C, kp, r0);
                     if (internal && CMP) {
-                        const uint32_t* __restrict__ qb = reinterpret_cast<const uint32_t*>(tv.bq) + (int64_t)blk * 16;
-                        sbh_u32x4v cb[D3 / 2];
-#pragma unroll
-                        for (int i = 0; i < D3 / 2; ++i) cb[i] = gld4u(qb + 4 * i);
 #pragma unroll
                         for (int c = 0; c < D3; ++c) {
-                            const uint32_t cnt = gld(bt + c);
+                            const uint32_t cnt = cn[c];
                             const uint32_t c0 = (c & 1) ? cb[c >> 1].z : cb[c >> 1].x;
                             const uint32_t c1 = (c & 1) ? cb[c >> 1].w : cb[c >> 1].y;
                             const float ex = fmaf(h16(c0 & 0xFFFFu), sideC, dTx);
@@ -544,7 +558,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     } else if (internal) {
 #pragma unroll
                         for (int c = 0; c < D3; ++c) {
-                            const uint32_t cnt = gld(bt + c);
+                            const uint32_t cnt = EARLY ? cn[c] : gld(bt + c);
                             const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                             const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
                             sumc = cnt ? v : sumc;
