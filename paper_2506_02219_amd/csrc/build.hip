@@ -14,8 +14,9 @@
 //      in (parent, digit) order, which is breadth-first order;
 //   5. aggregates bottom-up (leaves from points, internal nodes from
 //      children) and packing into the per-node child blocks.
-// Levels need their node counts on the host, so the build synchronises once
-// per level; it is not part of the timed evaluation.
+// Levels need their node counts on the host, so the build synchronises twice
+// per level (its internal nodes, then their children); it is not part of the
+// timed evaluation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -77,18 +78,45 @@ __global__ void __launch_bounds__(kBboxThreads) k_bbox_partial(const float* __re
     }
 }
 
-// params: lo[3], side, inv_side, bad
-__global__ void k_bbox_final(const float* __restrict__ partial, int nb, float* __restrict__ params)
+// params: lo[3], side, inv_side, bad.  One workgroup: each thread folds a
+// stride of the partials, then the wavefronts and the workgroup combine
+// (min and max are exact, so the order does not change the result).
+__global__ void __launch_bounds__(kBboxThreads) k_bbox_final(const float* __restrict__ partial, int nb,
+                                                             float* __restrict__ params)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     float bad = 0.0f;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = threadIdx.x; b < nb; b += kBboxThreads) {
         for (int a = 0; a < 3; ++a) {
             mn[a] = fminf(mn[a], partial[b * 8 + a]);
             mx[a] = fmaxf(mx[a], partial[b * 8 + 3 + a]);
         }
         bad = fmaxf(bad, partial[b * 8 + 6]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o));
+        }
+        bad = fmaxf(bad, __shfl_xor(bad, o));
+    }
+    __shared__ float sh[kBboxThreads / 64][7];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        for (int a = 0; a < 3; ++a) {
+            sh[wv][a] = mn[a];
+            sh[wv][3 + a] = mx[a];
+        }
+        sh[wv][6] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < kBboxThreads / 64; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], sh[k][a]);
+            mx[a] = fmaxf(mx[a], sh[k][3 + a]);
+        }
+        bad = fmaxf(bad, sh[k][6]);
     }
     float side = 0.0f;
     for (int a = 0; a < 3; ++a) {
@@ -106,7 +134,7 @@ hipError_t launch_bbox(const float* src, const float* w, const float* nrm, int64
                        float* partial_dev, int nblocks, hipStream_t s)
 {
     k_bbox_partial<<<nblocks, kBboxThreads, 0, s>>>(src, w, nrm, n, partial_dev);
-    k_bbox_final<<<1, 64, 0, s>>>(partial_dev, nblocks, params_dev);
+    k_bbox_final<<<1, kBboxThreads, 0, s>>>(partial_dev, nblocks, params_dev);
     return hipGetLastError();
 }
 
@@ -367,6 +395,10 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, 
 // ---------------------------------------------------------------------------
 // 4. Levels
 // ---------------------------------------------------------------------------
+struct float3v {
+    float x, y, z;
+};
+
 __global__ void k_gather_points(const float* __restrict__ src, const float* __restrict__ w,
                                 const float* __restrict__ nrm, const uint32_t* __restrict__ perm, int64_t n,
                                 float4* __restrict__ pts, float4* __restrict__ pdip)
@@ -375,10 +407,15 @@ __global__ void k_gather_points(const float* __restrict__ src, const float* __re
     if (s >= n) return;
     const uint32_t i = perm[s];
     const float wi = w[i];
-    pts[s] = make_float4(src[3 * (int64_t)i], src[3 * (int64_t)i + 1], src[3 * (int64_t)i + 2], wi);
+    // a point's three floats in one 12-byte load: the reads are random, so each
+    // separate load would be another cache-line request
+    float3v x;
+    __builtin_memcpy(&x, src + 3 * (int64_t)i, sizeof(x));
+    pts[s] = make_float4(x.x, x.y, x.z, wi);
     if (pdip) {
-        pdip[s] = make_float4(wi * nrm[3 * (int64_t)i], wi * nrm[3 * (int64_t)i + 1], wi * nrm[3 * (int64_t)i + 2],
-                              0.0f);
+        float3v m;
+        __builtin_memcpy(&m, nrm + 3 * (int64_t)i, sizeof(m));
+        pdip[s] = make_float4(wi * m.x, wi * m.y, wi * m.z, 0.0f);
     }
 }
 
@@ -645,10 +682,51 @@ __global__ void k_pack(int32_t n_nodes, const int32_t* __restrict__ npblk, const
     if (bdip) bdip[slot] = ndip[g];
 }
 
-__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
+// the root's level arrays: first point 0, all n points, no parent, digit 0, no parent block
+__global__ void k_root_init(int32_t n, int32_t* b, int32_t* c, int32_t* par, int32_t* dig, int32_t* pblk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (threadIdx.x != 0) return;
+    b[0] = 0;
+    c[0] = n;
+    par[0] = -1;
+    dig[0] = 0;
+    pblk[0] = -1;
+}
+
+// The per-level arrays concatenated into the node and block arrays, each
+// family in one launch (the tables travel as kernel arguments).
+constexpr int kLevelTab = 24;   // levels of a tree: at most 60 / 3 + 1 = 21
+struct LevelTab {
+    int64_t off[kLevelTab + 1];          // first node of each level
+    const int32_t* src[7][kLevelTab];    // begin, count, digit, parent, first child, child count, parent block
+};
+struct NodeDst {
+    int32_t* p[8];                       // the same seven node arrays, then the level
+};
+struct TopoTab {
+    int64_t off[kLevelTab + 1];          // first topology word of each level's blocks
+    const uint32_t* src[kLevelTab];
+};
+
+__global__ void k_concat_levels(LevelTab tab, int n_levels, NodeDst dst)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= tab.off[n_levels]) return;
+    int l = 0;
+    while (g >= tab.off[l + 1]) ++l;
+    const int64_t i = g - tab.off[l];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) dst.p[a][g] = tab.src[a][l][i];
+    dst.p[7][g] = l;
+}
+
+__global__ void k_concat_topo(TopoTab tab, int n_levels, uint32_t* __restrict__ btopo)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= tab.off[n_levels]) return;
+    int l = 0;
+    while (g >= tab.off[l + 1]) ++l;
+    btopo[g] = tab.src[l][g - tab.off[l]];
 }
 
 // ---------------------------------------------------------------------------
@@ -805,15 +883,8 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     root.dig = tmp.alloc<int32_t>(1); root.pblk = tmp.alloc<int32_t>(1);
     root.first = tmp.alloc<int32_t>(1); root.nch = tmp.alloc<int32_t>(1);
     SBH_ALLOC_OK("allocating root");
-    {
-        const int32_t init[5] = {0, (int32_t)n, -1, 0, -1};
-        SBH_TRY(hipMemcpyAsync(root.b, &init[0], 4, hipMemcpyHostToDevice, s), "root init");
-        SBH_TRY(hipMemcpyAsync(root.c, &init[1], 4, hipMemcpyHostToDevice, s), "root init");
-        SBH_TRY(hipMemcpyAsync(root.par, &init[2], 4, hipMemcpyHostToDevice, s), "root init");
-        SBH_TRY(hipMemcpyAsync(root.dig, &init[3], 4, hipMemcpyHostToDevice, s), "root init");
-        SBH_TRY(hipMemcpyAsync(root.pblk, &init[4], 4, hipMemcpyHostToDevice, s), "root init");
-        SBH_TRY(hipStreamSynchronize(s), "root init sync");
-    }
+    k_root_init<<<1, 64, 0, s>>>((int32_t)n, root.b, root.c, root.par, root.dig, root.pblk);
+    SBH_TRY(hipGetLastError(), "root init kernel");
     lv.push_back(root);
     uint32_t* total = stmp;  // scan totals land here; scans use stmp+1.. as scratch
     uint32_t* scan_scratch = stmp + 1;
@@ -917,22 +988,21 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
     }
     int32_t* npblk = tmp.alloc<int32_t>(n_nodes);
     SBH_ALLOC_OK("allocating parent blocks");
+    if (n_levels > kLevelTab) {
+        *msg = "sbh_build: too many levels";
+        return SBH_EINVAL;
+    }
     {
-        int64_t off = 0;
+        LevelTab tab{};
         for (int l = 0; l < n_levels; ++l) {
             const LevelBufs& L = lv[l];
-            const size_t bytes = (size_t)L.n * 4;
-            SBH_TRY(hipMemcpyAsync(t->nbegin + off, L.b, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(t->ncount + off, L.c, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(t->ndigit + off, L.dig, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(t->nparent + off, L.par, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(t->nfirst + off, L.first, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(t->nnchild + off, L.nch, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            SBH_TRY(hipMemcpyAsync(npblk + off, L.pblk, bytes, hipMemcpyDeviceToDevice, s), "node copy");
-            k_fill_i32<<<nblk(L.n), 256, 0, s>>>(t->nlevel + off, L.n, l);
-            SBH_TRY(hipGetLastError(), "level fill");
-            off += L.n;
+            tab.off[l + 1] = tab.off[l] + L.n;
+            const int32_t* src[7] = {L.b, L.c, L.dig, L.par, L.first, L.nch, L.pblk};
+            for (int a = 0; a < 7; ++a) tab.src[a][l] = src[a];
         }
+        const NodeDst dst{{t->nbegin, t->ncount, t->ndigit, t->nparent, t->nfirst, t->nnchild, npblk, t->nlevel}};
+        k_concat_levels<<<nblk(n_nodes), 256, 0, s>>>(tab, n_levels, dst);
+        SBH_TRY(hipGetLastError(), "node concatenation kernel");
     }
     // block arrays
     const int64_t nbk = n_blocks > 0 ? n_blocks : 1;
@@ -951,12 +1021,15 @@ sbh_status build_tree_impl(const float* src, const float* w, const float* nrm, i
         if (compress) t->bq = c.take<uint2>(nbk * d3);
         if (quadrupole) t->bquad = c.take<float4>(2 * nbk * d3);
     }
-    for (int l = 0; l < n_levels; ++l) {
-        if (n_int_lv[l] > 0 && btopo_lv[l]) {
-            SBH_TRY(hipMemcpyAsync(t->btopo + (int64_t)blk_off[l] * ts, btopo_lv[l],
-                                   (size_t)n_int_lv[l] * ts * sizeof(uint32_t), hipMemcpyDeviceToDevice, s),
-                    "topo copy");
+    if (n_blocks > 0) {   // a level's blocks follow the previous level's (blk_off)
+        TopoTab tt{};
+        for (int l = 0; l < n_levels; ++l) {
+            const bool has = n_int_lv[l] > 0 && btopo_lv[l];
+            tt.off[l + 1] = tt.off[l] + (has ? (int64_t)n_int_lv[l] * ts : 0);
+            tt.src[l] = btopo_lv[l];
         }
+        k_concat_topo<<<nblk(tt.off[n_levels]), 256, 0, s>>>(tt, n_levels, t->btopo);
+        SBH_TRY(hipGetLastError(), "topology concatenation kernel");
     }
     // 5. aggregates bottom-up, then pack into the child blocks
     {

@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
 #pragma clang fp contract(off)
     static_assert(!CMP || (D == 2 && K != SBH_WINDING), "compressed aggregates: d = 2, no dipoles");
     constexpr int D3 = D * D * D;
-    constexpr bool EARLY = D == 2 && K != SBH_WINDING;
+    constexpr bool EARLY = D == 2;   // a block's counts fit in registers
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
     __shared__ float res[4][kPoolPaths];   // per path: its sum F (before the division by S)
@@ -468,11 +468,15 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                 float4 aggC, dpC = zero4;
                 uint32_t nC = 1u, beginC;
                 int32_t blkC = 0;
-                // d = 2 without dipoles: the block's eight counts stay in registers from the selection
-                // to the swap (a reload is another gather per lane), and a compressed block's codes
-                // arrive with them, so decoding the selected child waits on no further load
+                // d = 2: the block's eight counts stay in registers from the selection to the swap
+                // (a reload is another gather per lane), and a compressed block's codes arrive with
+                // them, so decoding the selected child waits on no further load
                 uint32_t cn[EARLY ? D3 : 1];
                 sbh_u32x4v cb[CMP ? D3 / 2 : 1];
+                auto count = [&](int c) -> uint32_t {
+                    if constexpr (EARLY) return cn[c];
+                    else return gld(bt + c);
+                };
                 if (internal) {
                     if constexpr (EARLY) {
 #pragma unroll
@@ -490,7 +494,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     uint32_t w0 = 0u, w1 = 0u;
 #pragma unroll
                     for (int c = 0; c < D3; ++c) {
-                        const uint32_t cnt = EARLY ? cn[c] : gld(bt + c);
+                        const uint32_t cnt = count(c);
                         const bool hit = (r - pre) < cnt;
                         csel = hit ? c : csel;
                         preC = hit ? pre : preC;
@@ -544,7 +548,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     if (internal && CMP) {
 #pragma unroll
                         for (int c = 0; c < D3; ++c) {
-                            const uint32_t cnt = cn[c];
+                            const uint32_t cnt = count(c);
                             const uint32_t c0 = (c & 1) ? cb[c >> 1].z : cb[c >> 1].x;
                             const uint32_t c1 = (c & 1) ? cb[c >> 1].w : cb[c >> 1].y;
                             const float ex = fmaf(h16(c0 & 0xFFFFu), sideC, dTx);
@@ -558,7 +562,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                     } else if (internal) {
 #pragma unroll
                         for (int c = 0; c < D3; ++c) {
-                            const uint32_t cnt = EARLY ? cn[c] : gld(bt + c);
+                            const uint32_t cnt = count(c);
                             const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
                             const float v = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
                             sumc = cnt ? v : sumc;
