@@ -176,7 +176,7 @@ ABLATION_RR = {0: "eq5", 1: "p=1", 2: "p=1/2", 3: "eq5 voted over the wavefront"
 def ablation(args):
     """The paper's roulette study (Appendix C) and the branching factor (Section 3.3): the estimator
     with Eq. (5), with p = 1 (no roulette), with p = 1/2 and with Eq. (5) voted over each wavefront's
-    64 queries, on trees of branching 2 and 4, on the
+    64 queries, on trees of branching 2, 4 and 8, on the
     potential (c1), winding (c2, shuffled plane) and smooth-distance (c3) workloads; one sample per
     subdomain, G = 64 (the coherent walk).  Time per evaluation of every query (HIP events, median
     of rounds of K launches) and median relative error against float64 brute force on a fixed
@@ -201,7 +201,7 @@ def ablation(args):
         sidx_t = torch.from_numpy(sidx).to(dev)
         ref = P.sbh_brute(src, wts, nrm, qry[sidx_t].contiguous(), kernel, fp64=True).cpu().numpy()
         out = torch.empty(N, dtype=torch.float32, device=dev)
-        for d in (2, 4):
+        for d in (2, 4, 8):
             tree = P.sbh_build(src, wts, nrm, branching=d, leaf_size=8)
             for rr in (0, 1, 2, 3):
                 def run(rr=rr):
@@ -223,14 +223,16 @@ def ablation(args):
                 err = float(np.median(rel_errors(out[sidx_t].cpu().numpy(), ref, kernel)))
                 paths = torch.empty((N, d ** 3, 1, 4), dtype=torch.int32, device=dev)
                 P.sbh_eval(tree, qry, kernel, samples=1, seed=0, group=64, rr_mode=rr, out=out, paths=paths)
-                rec = paths.cpu().numpy().reshape(-1, 4)
-                del paths
-                rec = rec[rec[:, 0] >= 0]
+                rec = paths.view(-1, 4)
+                acc_steps = float(rec[rec[:, 0] >= 0][:, 2].double().mean())   # on the GPU: d = 8 records are GBs
+                del paths, rec
                 rows.append(dict(workload=cl.name, kernel=["potential", "winding", "smoothdist"][kernel], queries=N,
                                  branching=d, roulette=ABLATION_RR[rr], ms=float(np.median(times)),
-                                 median_rel_err=err, accepted_steps_per_path=float(rec[:, 2].mean()),
+                                 median_rel_err=err, accepted_steps_per_path=acc_steps,
                                  # time x error^2: the cost of reaching a fixed error (variance ~ 1/S)
                                  work_at_unit_variance=float(np.median(times)) * err * err))
+                print(f"[ablation] {cl.name} d={d} {ABLATION_RR[rr]}: {rows[-1]['ms']:.4f} ms, "
+                      f"err {err:.3e}", file=sys.stderr, flush=True)
             tree.free()
     print(json.dumps({"ablation": rows, "samples_per_subdomain": 1, "group": 64, "steps": args.steps,
                       "git_sha": git_sha(), "csrc_sha256_16": csrc_hash()}))

@@ -853,6 +853,7 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
         int csel = 0;
         uint32_t nonempty = 0u;   // d = 2: slots with points (wavefront-uniform)
         uint64_t nonempty64 = 0ull;   // d = 4
+        uint32_t nonempty8 = 0u;      // d = 8: this lane's eight slots with points
         if constexpr (D == 2) {
             // child selection across lanes 0..7 (one slot each): an exclusive scan of the
             // counts by DPP row shifts, then ballots give the slot whose range holds r, the
@@ -906,19 +907,55 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
             beginC = beginT + preC;
             blkC = (int32_t)gld(bt + D3) + nintC;
         } else {
-            // uniform child selection from the point counts alone
-            uint32_t pre = 0u, preC = 0u;
-            int32_t nint = 0, nintC = 0;
-            for (int c = 0; c < D3; ++c) {
-                const uint32_t cnt = gld(bt + c);
-                const bool hit = (r - pre) < cnt;
-                csel = hit ? c : csel;
-                preC = hit ? pre : preC;
-                nintC = hit ? nint : nintC;
-                nC = hit ? cnt : nC;
-                nint += ((int)cnt > tv.leaf_size && level + 1 < tv.max_level) ? 1 : 0;
-                pre += cnt;
+            // d = 8: 512 slots, eight per lane (lane l holds slots 8l .. 8l + 7, two 16-byte
+            // loads); each lane's point total and internal-slot count are scanned across the
+            // wavefront as the d = 4 counts are, a ballot finds the lane whose range holds r,
+            // and that lane's eight slots give the child; each lane keeps its non-empty slots
+            // as eight bits for the swap
+            static_assert(D3 == 512, "eight slots per lane");
+            const int ln = threadIdx.x & 63;
+            const sbh_u32x4v c0 = gld4u(bt + 8 * ln), c1 = gld4u(bt + 8 * ln + 4);
+            const uint32_t cl[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const bool deeper = level < lvl_int;
+            uint32_t tot = 0u, nin = 0u;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                tot += cl[i];
+                nin += (deeper && (int)cl[i] > tv.leaf_size) ? 1u : 0u;
+                nonempty8 |= cl[i] != 0u ? 1u << i : 0u;
             }
+            uint32_t inc = tot, inci = nin;
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xF, 0xF, false);    // row_shr:1
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x111, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xF, 0xF, false);    // row_shr:2
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x112, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xF, 0xF, false);    // row_shr:4
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x114, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x118, 0xF, 0xF, false);    // row_shr:8
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x118, 0xF, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x142, 0xA, 0xF, false);    // row_bcast:15
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x142, 0xA, 0xF, false);
+            inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x143, 0xC, 0xF, false);    // row_bcast:31
+            inci += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inci, 0x143, 0xC, 0xF, false);
+            const uint32_t excl = inc - tot;
+            // (r < n_T, so exactly one lane's range holds it; in the other lanes no slot hits)
+            const int L = (int)__builtin_ctzll(__ballot((r - excl) < tot));
+            uint32_t pre = excl, preS = 0u, nS = 0u, niS = 0u, ni = inci - nin;
+            int sl = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bool hit = (r - pre) < cl[i];
+                sl = hit ? i : sl;
+                preS = hit ? pre : preS;
+                nS = hit ? cl[i] : nS;
+                niS = hit ? ni : niS;
+                ni += (deeper && (int)cl[i] > tv.leaf_size) ? 1u : 0u;
+                pre += cl[i];
+            }
+            csel = 8 * L + __builtin_amdgcn_readlane(sl, L);
+            const uint32_t preC = (uint32_t)__builtin_amdgcn_readlane((int)preS, L);
+            nC = (uint32_t)__builtin_amdgcn_readlane((int)nS, L);
+            const int32_t nintC = __builtin_amdgcn_readlane((int)niS, L);
             aggC = gld4(at_off(tv.bagg, boff + (Off)(csel * 16)));
             if constexpr (K == SBH_WINDING) dpC = gld4(at_off(tv.bdip, boff + (Off)(csel * 16)));
             beginC = beginT + preC;
@@ -974,12 +1011,21 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
                 }
             } else {
-                // only the other non-empty slots, behind wavefront-uniform branches (a surface
-                // fills a few of a node's 512 slots)
-                for (int c = 0; c < D3; ++c) {
-                    if (gld(bt + c) == 0u || c == csel) continue;
-                    const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
-                    sumc = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                // only the other non-empty slots (a surface fills a few of a node's 512), in slot
+                // order: the lanes in order, each lane's eight bits in order
+                const int ln = threadIdx.x & 63;
+                const uint32_t mine = ln == (csel >> 3) ? nonempty8 & ~(1u << (csel & 7)) : nonempty8;
+                uint64_t lanes = __ballot(mine != 0u);
+                while (lanes) {
+                    const int l = (int)__builtin_ctzll(lanes);
+                    lanes &= lanes - 1ull;
+                    uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
+                    while (ml) {
+                        const int c = 8 * l + (int)__builtin_ctz(ml);
+                        ml &= ml - 1u;
+                        const float4 gd = (K == SBH_WINDING) ? gld4(bd + c) : zero4;
+                        sumc = term_acc<K>(gld4(ba + c), gd, qx, qy, qz, kp, r0, sumc);
+                    }
                 }
             }
             // the lanes the roulette keeps take the step (selects, not a branch)
