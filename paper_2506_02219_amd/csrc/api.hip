@@ -554,6 +554,13 @@ struct sbh_batch {
     size_t lds_static = 0;                // the batch kernels' own LDS per workgroup
     int lds_per_cu = 0, lds_per_wg_max = 0;
     hipStream_t cap = nullptr;
+    // the groups' launches run on side streams forked from the launch stream and joined
+    // back, so that in the captured graph they are parallel branches after the begin node
+    // and one group's last workgroups overlap the next group's first
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t begin_node = nullptr;
@@ -567,6 +574,11 @@ void batch_release(sbh_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int i = 0; i < sbh_batch::kSide; ++i) {
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     for (int g = 0; g < sbh::kBatchLaunchGroups; ++g) {
         sbh::dev_free(b->mem, b->d_items[g], b->clouds.size() * sizeof(sbh::BatchItem), 0);
         sbh::dev_free(b->mem, b->d_wg[g], (size_t)b->tiles[g] * sizeof(int2), 0);
@@ -621,18 +633,30 @@ hipError_t batch_upload(sbh_batch* b, const sbh_batch_config& c)
     return hipSuccess;
 }
 
+// the launch state, then every group's launch on the side streams (group i of those with
+// work on side stream i mod kSide), which s waits for
 hipError_t batch_enqueue(sbh_batch* b, uint64_t seed, uint32_t batch, hipStream_t s)
 {
     hipError_t e = sbh::launch_batch_begin(b->d_state, seed, batch, s);
+    if (e == hipSuccess) e = hipEventRecord(b->fork, s);
+    int used = 0;
     for (int g = 0; g < sbh::kBatchLaunchGroups && e == hipSuccess; ++g) {
         if (b->n_wg[g] == 0) continue;
+        hipStream_t sg = b->side[used % sbh_batch::kSide];
+        if (used < sbh_batch::kSide) e = hipStreamWaitEvent(sg, b->fork, 0);
+        ++used;
+        if (e != hipSuccess) break;
         if (g < sbh::kBatchGroups)
             e = sbh::launch_sbh_batch(g < 3 ? 2 : 4, g % 3, b->d_items[g], b->d_wg[g], b->n_wg[g], b->cfg.tile_waves,
                                       b->lds_bytes, b->d_state + g, b->samples, b->opts.group, b->opts.rr_mode,
-                                      b->opts.eps, b->opts.alpha, s);
+                                      b->opts.eps, b->opts.alpha, sg);
         else
             e = sbh::launch_leaf_batch(g - sbh::kBatchGroups, b->d_items[g], b->d_wg[g], b->n_wg[g], b->cfg.tile_waves,
-                                       b->opts.eps, b->opts.alpha, s);
+                                       b->opts.eps, b->opts.alpha, sg);
+    }
+    for (int i = 0; i < std::min(used, sbh_batch::kSide) && e == hipSuccess; ++i) {
+        e = hipEventRecord(b->join[i], b->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[i], 0);
     }
     return e;
 }
@@ -714,6 +738,11 @@ sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t 
     // the tables are written by synchronous copies and read on other streams (graph replays)
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int i = 0; i < sbh_batch::kSide && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipDeviceSynchronize();
         batch_release(b);
