@@ -396,7 +396,11 @@ typedef struct sbh_batch_config {
  * The plan keeps pointers to the trees, queries and outputs, which must
  * stay valid (and the trees alive) until sbh_batch_free.  It allocates
  * 6 x 16 bytes of launch state, the descriptors and the workgroup tables
- * (8 bytes per tile) on the current device.
+ * (8 bytes per tile) on the current device, and owns four streams (default
+ * priority) and four events: the graph's launch groups (one per branching
+ * factor and kernel, and the exact sums of root-leaf clouds) are forked
+ * from its first node onto three of them and joined back, so that they
+ * run as parallel branches.
  * Errors: SBH_EINVAL, SBH_EUNSUPPORTED (proposal != 0), SBH_ENOMEM, SBH_EHIP.
  */
 sbh_status sbh_batch_create(const sbh_batch_item* items, int32_t count, int32_t samples, const sbh_eval_opts* opts,
