@@ -246,7 +246,7 @@ def main():
         ablation(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "queries are independent, so several GPUs would each evaluate a share of them", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -35,7 +35,7 @@ typedef enum sbh_status {
     SBH_EINVAL = -1,        /* invalid argument (null pointer, bad size, NaN input, bad enum) */
     SBH_ENOMEM = -2,        /* device allocation failed */
     SBH_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
-    SBH_EUNSUPPORTED = -4,  /* valid request that this build does not implement */
+    SBH_EUNSUPPORTED = -4,  /* valid request that the library does not implement */
     SBH_ESTATE = -5         /* object in an unusable state */
 } sbh_status;
 
