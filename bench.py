@@ -42,6 +42,11 @@ CONFIGS = {
 BETAS = [0.2, 0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.75, 1, 1.5, 2, 3, 4, 6, 8, 12, 16, 24, 32, 40]
 S_SWEEP = [1, 2, 4, 8, 16, 32]
 FP32_PEAK_TFLOPS = 157.3
+# flops of one brute-force interaction: three differences, the squared distance (three products,
+# two sums) and eps^2, the reciprocal square root, the weight and the sum (potential); the
+# winding number adds r^-3 (two products) and the dot product with the dipole (five); the smooth
+# distance has the distance, the exponent (two) and the rescaled sum (two) instead
+BRUTE_FLOPS = {0: 12, 1: 17, 2: 14}
 # float32 operations per kernel term: differences, squared distance, the
 # kernel itself, the weight; transcendental calls counted as one operation
 TERM_FLOPS = {0: 11, 1: 17, 2: 14}
@@ -81,6 +86,7 @@ def parse():
     ap.add_argument("--no-compressed", action="store_true", help="skip the compressed-aggregate walk")
     ap.add_argument("--no-lod2", action="store_true", help="skip the second-order (quadrupole) walk")
     ap.add_argument("--no-vote", action="store_true", help="skip the roulette voted over the wavefront")
+    ap.add_argument("--no-brute", action="store_true", help="skip the float32 brute-force timing of every query")
     ap.add_argument("--train-seeds", type=int, default=16, help="training surfaces (seeds 5001...)")
     ap.add_argument("--train-queries", type=int, default=2048, help="training queries per surface")
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -560,6 +566,25 @@ def main():
             voted["sweep"].append(dict(samples=sv, ms=timed(lambda: run_vote(sv), 3, 1),
                                        median_rel_err=err_of(lambda: run_vote(sv))))
 
+    # --- float32 brute force over every query (Eq. (1) summed exactly: the paper's third comparator)
+    brute = None
+    if not args.no_brute:
+        bout = torch.empty(N, dtype=torch.float32, device=dev)
+
+        def run_brute():
+            P.sbh_brute(src, wts, nrm, qry, kernel, out=bout)
+
+        ms_b = timed(run_brute, 2, 1)
+        inter = float(cl.m) * N
+        tf_b = BRUTE_FLOPS[kernel] * inter / (ms_b * 1e-3) / 1e12
+        brute = dict(kernel="k_brute32" if kernel != P.SMOOTHDIST else "k_brute<2, float>", queries=N,
+                     sources=int(cl.m), ms=ms_b, interactions_per_s=inter / (ms_b * 1e-3),
+                     flops_per_interaction=BRUTE_FLOPS[kernel], achieved_TFLOPs=tf_b,
+                     frac_of_fp32_peak=tf_b / FP32_PEAK_TFLOPS, frac_of_non_packed_fp32=tf_b / (FP32_PEAK_TFLOPS / 2),
+                     median_rel_err=float(np.median(rel_errors(bout[sidx_t].cpu().numpy(), ref, kernel))),
+                     estimator_speedup=ms_b / ms_per_step)
+        del bout
+
     # --- Barnes-Hut sweeps and equal-error interpolation.  The paper compares the two methods on
     # one query set at a time (a grid, random points), so Barnes-Hut is swept on both orders the
     # estimator is timed on: the shuffled plane (the headline's own queries, in the same order)
@@ -835,6 +860,7 @@ def main():
         "compressed_aggregates": compressed,
         "second_order_lod": lod2,
         "voted_roulette": voted,
+        "brute_force": brute,
         "sbh_sweep": sweep,
         "bh": bh,
         "learned": learned,
