@@ -792,6 +792,10 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     constexpr float kInvD = 1.0f / (float)D;
     using Off = typename TreeOff<O64>::T;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // d = 4: each wavefront's row for the child block of the step (at most four wavefronts per
+    // workgroup walk paths)
+    __shared__ float4 sblk[D == 4 ? 4 : 1][64];
+    __shared__ float4 sblkd[D == 4 && K == SBH_WINDING ? 4 : 1][64];
     // wavefront-uniform walk state
     uint32_t nT = n_a, beginT = begin_a;
     int32_t blk = blk_a;
@@ -993,23 +997,28 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
                     sumc = term_acc<K>(g8[c], gd, qx, qy, qz, kp, r0, sumc);
                 }
             } else if constexpr (D == 4) {
-                // the block in one coalesced load (lane c holds slot c), then the other non-empty
-                // slots (a surface fills a few of the 64) in turn, each broadcast from its lane
+                // the block in one coalesced load (lane c holds slot c), staged in the wavefront's
+                // LDS row, then the other non-empty slots (a surface fills a few of the 64) in
+                // turn, each read back by every lane as one broadcast LDS load
                 const int ln = threadIdx.x & 63;
-                const float4 gl = gld4(ba + ln);
-                const float4 gdl = (K == SBH_WINDING) ? gld4(bd + ln) : zero4;
+                const int wv = (threadIdx.x >> 6) & 3;
+                sblk[wv][ln] = gld4(ba + ln);
+                if constexpr (K == SBH_WINDING) sblkd[wv][ln] = gld4(bd + ln);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 uint64_t rest = nonempty64 & ~(1ull << csel);
                 while (rest) {
                     const int c = (int)__builtin_ctzll(rest);
                     rest &= rest - 1ull;
-                    const float4 g = make_float4(rdlane(gl.x, c), rdlane(gl.y, c),
-                                                 rdlane(gl.z, c), rdlane(gl.w, c));
+                    const float4 g = sblk[wv][c];
                     float4 gd = zero4;
-                    if constexpr (K == SBH_WINDING)
-                        gd = make_float4(rdlane(gdl.x, c), rdlane(gdl.y, c),
-                                         rdlane(gdl.z, c), 0.0f);
+                    if constexpr (K == SBH_WINDING) gd = make_float4(sblkd[wv][c].x, sblkd[wv][c].y, sblkd[wv][c].z, 0.0f);
                     sumc = term_acc<K>(g, gd, qx, qy, qz, kp, r0, sumc);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the row is reused next step
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             } else {
                 // only the other non-empty slots (a surface fills a few of a node's 512), in slot
                 // order: the lanes in order, each lane's eight bits in order
