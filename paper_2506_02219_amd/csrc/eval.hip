@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
 #pragma clang fp contract(off)
     static_assert(!CMP || (D == 2 && K != SBH_WINDING), "compressed aggregates: d = 2, no dipoles");
     constexpr int D3 = D * D * D;
-    constexpr bool EARLY = D == 2;   // a block's counts fit in registers
+    constexpr bool KEEPN = D == 2;   // the block's counts are kept in registers (eight of them)
     constexpr int TS = topo_stride(D3);
     constexpr float kInvD = 1.0f / (float)D;
     __shared__ float res[4][kPoolPaths];   // per path: its sum F (before the division by S)
@@ -471,14 +471,14 @@ __global__ void __launch_bounds__(256) k_sbh_pool(TreeView tv, const float* __re
                 // d = 2: the block's eight counts stay in registers from the selection to the swap
                 // (a reload is another gather per lane), and a compressed block's codes arrive with
                 // them, so decoding the selected child waits on no further load
-                uint32_t cn[EARLY ? D3 : 1];
+                uint32_t cn[KEEPN ? D3 : 1];
                 sbh_u32x4v cb[CMP ? D3 / 2 : 1];
                 auto count = [&](int c) -> uint32_t {
-                    if constexpr (EARLY) return cn[c];
+                    if constexpr (KEEPN) return cn[c];
                     else return gld(bt + c);
                 };
                 if (internal) {
-                    if constexpr (EARLY) {
+                    if constexpr (KEEPN) {
 #pragma unroll
                         for (int c = 0; c < D3; ++c) cn[c] = gld(bt + c);
                     }
