@@ -792,8 +792,8 @@ __device__ __forceinline__ float wave_path(const TreeView& tv, float qx, float q
     constexpr float kInvD = 1.0f / (float)D;
     using Off = typename TreeOff<O64>::T;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    // d = 4: each wavefront's row for the child block of the step (at most four wavefronts per
-    // workgroup walk paths)
+    // d = 4: each wavefront's row for the child block of the step; every kernel that walks
+    // paths runs at most four wavefronts per workgroup (256 threads), one row each
     __shared__ float4 sblk[D == 4 ? 4 : 1][64];
     __shared__ float4 sblkd[D == 4 && K == SBH_WINDING ? 4 : 1][64];
     // wavefront-uniform walk state
@@ -2382,6 +2382,7 @@ k_sbh_batch(const BatchItem* __restrict__ items, const int2* __restrict__ wg, co
             SbhArgs base)
 {
     constexpr int P = kWaveParts;
+    static_assert(kBatchMaxTileWaves * P <= 4, "the walk keeps one LDS row per wavefront, four per workgroup");
     __shared__ float part_f[kBatchMaxTileWaves * P][64];
     __shared__ uint32_t done[kBatchMaxTileWaves];
     if constexpr (P > 1) {
